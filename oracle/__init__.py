@@ -1,0 +1,26 @@
+"""FP64 CPU oracle for Nys-IP-PMM on the separable QP (P)/(D).
+
+TEST INFRASTRUCTURE ONLY.  Nothing in the product path imports, links or
+calls this package; it is used by ``tests/``, by the smoke check in
+``__graft_entry__`` and by the CPU-baseline leg of ``bench.py``.  It shares
+no code with the HIP library: it is plain numpy/scipy in float64, written
+from the paper's definitions and algorithms, slow and direct on purpose.
+
+Modules
+-------
+problem    definitions of (P)/(D): objectives, KKT residuals, stopping measure
+normal_eq  the regularised normal-equation operator and the Newton step
+nystrom    randomized Nystrom approximation and the Nystrom preconditioner
+pcg        textbook preconditioned conjugate gradients
+ippmm      the IP-PMM outer loop with an exact (dense Cholesky) inner solve
+bruteforce active-set enumeration of the KKT conditions of tiny problems
+adjoint    gradient of a loss of the solution through the KKT conditions
+lowprec    round-to-nearest-even emulation of BF16 / FP32 storage
+philox     the Philox4x32-10 counter-based generator and Box-Muller normals
+
+Parity status: every function is pinned by a CPU test against something
+other than itself (closed forms, invariants, brute force, textbook routines
+or published known-answer vectors), except the parts listed as
+"parity unpinned" in the module docstrings of ``ippmm`` (initial point,
+parameter update and stopping rule shape the trajectory, not the optimum).
+"""

@@ -1,0 +1,89 @@
+"""Gradient of a loss of the QP solution with respect to the data (c, b, diag Q, A).
+
+The paper has no adjoint; this is derived from the KKT conditions of (P)/(D).
+At a strictly complementary optimum with support S (x_S > 0, z_{S^c} > 0) the
+solution is locally the solution of the equality-constrained system
+    F(x_S, y) = [q_S * x_S + c_S - A_S^T y ;  A_S x_S - b] = 0,
+with x_{S^c} = 0.  For L(x) with g = dL/dx, solve the adjoint system
+    [[diag(q_S), A_S^T], [A_S, 0]] [u1_S; u2] = [g_S; 0],   u1_{S^c} = 0,
+then dL/dc = -u1, dL/db = u2, dL/dq = -u1 * x, dL/dA = y u1^T - u2 x^T.
+
+The finite-difference reference re-solves the equality system on the same
+support for perturbed data and checks that the support is unchanged.
+
+Test infrastructure (see the package docstring).
+"""
+
+import numpy as np
+import scipy.linalg as sla
+
+
+def active_set(x, z):
+    return x > z
+
+
+def kkt_gradient(A, b, c, q, x, y, z, g, S=None):
+    """Dense reduced-KKT gradient.  Returns dict(c, b, q, A)."""
+    m, n = A.shape
+    if S is None:
+        S = active_set(x, z)
+    k = int(S.sum())
+    AS = A[:, S]
+    K = np.zeros((k + m, k + m))
+    K[:k, :k] = np.diag(q[S])
+    K[:k, k:] = AS.T
+    K[k:, :k] = AS
+    sol = sla.lu_solve(sla.lu_factor(K), np.concatenate([g[S], np.zeros(m)]))
+    u1 = np.zeros(n)
+    u1[S] = sol[:k]
+    u2 = sol[k:]
+    return dict(c=-u1, b=u2.copy(), q=-u1 * x, A=np.outer(y, u1) - np.outer(u2, x),
+                u1=u1, u2=u2)
+
+
+def resolve_on_support(A, b, c, q, S):
+    """x*(data) on a fixed support S (equality-constrained KKT, dense LU).
+    Returns (x, y, z, support_ok)."""
+    m, n = A.shape
+    k = int(S.sum())
+    AS = A[:, S]
+    K = np.zeros((k + m, k + m))
+    K[:k, :k] = np.diag(q[S])
+    K[:k, k:] = -AS.T
+    K[k:, :k] = AS
+    sol = sla.lu_solve(sla.lu_factor(K), np.concatenate([-c[S], b]))
+    x = np.zeros(n)
+    x[S] = sol[:k]
+    y = sol[k:]
+    z = q * x + c - A.T @ y
+    z[S] = 0.0
+    ok = bool(np.all(x[S] > 0) and np.all(z[~S] > 0))
+    return x, y, z, ok
+
+
+def loss(x, x_tgt):
+    """L = 1/2 ||x - x_tgt||^2; dL/dx = x - x_tgt."""
+    d = x - x_tgt
+    return 0.5 * float(d @ d), d
+
+
+def fd_gradient(A, b, c, q, S, x_tgt, block, coords, h_rel=1e-6):
+    """Central differences of L(x*(data)) in the given coordinates of one data
+    block ('c', 'b', 'q' or 'A'; coords are flat indices).  Step
+    h = h_rel * max(1, |theta|)."""
+    data = dict(A=A.copy(), b=b.copy(), c=c.copy(), q=q.copy())
+    out = np.zeros(len(coords))
+    for t, idx in enumerate(coords):
+        arr = data[block].reshape(-1)
+        theta = float(arr[idx])
+        h = h_rel * max(1.0, abs(theta))
+        vals = []
+        for s in (+1.0, -1.0):
+            arr[idx] = theta + s * h
+            x, _, _, ok = resolve_on_support(data["A"], data["b"], data["c"], data["q"], S)
+            if not ok:
+                raise ValueError("support changed under the finite-difference step")
+            vals.append(loss(x, x_tgt)[0])
+        arr[idx] = theta
+        out[t] = (vals[0] - vals[1]) / (2 * h)
+    return out

@@ -1,0 +1,326 @@
+"""CPU pins of the FP64 oracle against facts that do not come from the oracle
+itself: the unreduced Newton system solved by dense LU, closed forms of the
+Nystrom preconditioner, Krylov finite termination, the planted optimum,
+brute-force KKT enumeration, finite differences, torch's BF16 rounding and
+published Philox known-answer vectors."""
+
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg as sla
+import torch
+
+from instances import make_instance, random_feasible_instance
+from oracle import adjoint, bruteforce, ippmm, lowprec, normal_eq, nystrom, pcg, philox, problem
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _np(inst):
+    return (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+
+
+@pytest.fixture(scope="module")
+def small():
+    return make_instance("gauss_200x500", seed=1)
+
+
+# ---------------------------------------------------------------- problem
+
+def test_planted_point_is_kkt(small):
+    A, b, c, q = _np(small)
+    x, y, z = small.x_star.numpy(), small.y_star.numpy(), small.z_star.numpy()
+    meas = problem.kkt_measure(A, b, c, q, x, y, z)
+    assert meas["kkt"] < 1e-14
+    # strong duality at the planted optimum: primal = dual objective
+    assert abs(problem.primal_objective(x, c, q) - problem.dual_objective(x, y, b, q)) < 1e-10
+    assert np.all(x * z == 0) and np.all(x + z > 0)
+
+
+# ---------------------------------------------------------------- normal equations
+
+def test_normal_apply_equals_sum_of_rank_one_terms():
+    rng = np.random.default_rng(0)
+    A = rng.standard_normal((7, 11))
+    d = rng.uniform(0.1, 2, 11)
+    v = rng.standard_normal(7)
+    expect = 0.3 * v
+    for j in range(11):                       # sum_j d_j a_j (a_j^T v), column by column
+        expect = expect + d[j] * A[:, j] * float(A[:, j] @ v)
+    np.testing.assert_allclose(normal_eq.normal_apply(A, d, 0.3, v), expect, rtol=1e-13, atol=1e-13)
+    np.testing.assert_allclose(normal_eq.normal_matrix(A, d, 0.3) @ v, expect, rtol=1e-13, atol=1e-13)
+
+
+def _random_state(m, n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n))
+    q = rng.uniform(0, 1, n)
+    q[: n // 4] = 0.0
+    x = rng.uniform(0.01, 2, n)
+    z = rng.uniform(0.01, 2, n)
+    rd, rp, rxz = rng.standard_normal(n), rng.standard_normal(m), rng.standard_normal(n)
+    return A, q, x, z, rd, rp, rxz
+
+
+@pytest.mark.parametrize("rho,delta", [(1.0, 1.0), (1e-3, 1e-6), (8.0, 8.0)])
+def test_newton_elimination_matches_dense_lu(rho, delta):
+    A, q, x, z, rd, rp, rxz = _random_state(9, 23, 3)
+    D = normal_eq.scaling(x, z, q, rho)
+    M = normal_eq.normal_matrix(A, D, delta)
+    dx, dy, dz, _ = normal_eq.newton_step(A, x, z, D, delta, rd, rp, rxz, lambda xi: np.linalg.solve(M, xi))
+    ex, ey, ez = normal_eq.newton_dense_lu(A, q, x, z, rho, delta, rd, rp, rxz)
+    for a, e in ((dx, ex), (dy, ey), (dz, ez)):
+        assert np.linalg.norm(a - e) <= 1e-10 * (1 + np.linalg.norm(e))
+
+
+def test_inexact_newton_only_second_block_is_inexact():
+    """Proposition 3.1: with an inexact normal-equation solve, blocks 1 and 3
+    of the unreduced Newton residual vanish and block 2 equals the residual
+    of the normal equations."""
+    A, q, x, z, rd, rp, rxz = _random_state(12, 30, 4)
+    rho, delta = 0.5, 0.25
+    D = normal_eq.scaling(x, z, q, rho)
+    Mop = lambda v: normal_eq.normal_apply(A, D, delta, v)
+
+    def truncated(xi):
+        return pcg.pcg(Mop, xi, None, tol=0.0, maxit=3)[0]
+
+    dx, dy, dz, xi = normal_eq.newton_step(A, x, z, D, delta, rd, rp, rxz, truncated)
+    K = normal_eq.newton_matrix(A, q, x, z, rho, delta)
+    res = K @ np.concatenate([dx, dy, dz]) - np.concatenate([rd, rp, rxz])
+    m, n = A.shape
+    theta = Mop(dy) - xi
+    assert np.linalg.norm(theta) > 1e-3                        # really inexact
+    assert np.linalg.norm(res[:n]) < 1e-12 * (1 + np.linalg.norm(rd))
+    assert np.linalg.norm(res[n + m:]) < 1e-12 * (1 + np.linalg.norm(rxz))
+    np.testing.assert_allclose(res[n:n + m], theta, rtol=1e-10, atol=1e-12)
+
+
+# ---------------------------------------------------------------- Nystrom
+
+def _lowrank_psd(m, r, seed, decay=1.0):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    lam = np.arange(1, r + 1) ** -decay
+    return (U * lam) @ U.T
+
+
+def test_nystrom_exact_when_sketch_exceeds_rank():
+    m, r, ell = 120, 15, 25
+    N = _lowrank_psd(m, r, 0)
+    Om = nystrom.orthonormalize(np.random.default_rng(1).standard_normal((m, ell)))
+    U, lam, nu = nystrom.nystrom(lambda V: N @ V, Om)
+    Nh = (U * lam) @ U.T
+    assert np.linalg.norm(N - Nh, 2) <= 1e-12 * np.linalg.norm(N, 2)
+    assert np.all(lam >= 0) and np.all(np.diff(lam) <= 0)
+    np.testing.assert_allclose(U.T @ U, np.eye(ell), atol=1e-12)
+    assert np.count_nonzero(lam > 1e-10) == r
+
+
+def test_nystrom_matches_formula_and_is_dominated():
+    m, ell = 80, 12
+    rng = np.random.default_rng(2)
+    N = _lowrank_psd(m, m, 3, decay=2.0)
+    Om = nystrom.orthonormalize(rng.standard_normal((m, ell)))
+    Y = N @ Om
+    U, lam, nu = nystrom.nystrom_from_sketch(Y, Om)
+    Nh = (U * lam) @ U.T
+    F = nystrom.nystrom_formula(Y, Om)
+    assert np.linalg.norm(Nh - F, 2) <= 1e-8 * np.linalg.norm(N, 2)
+    ev = np.linalg.eigvalsh(N - Nh)                  # 0 <= N_hat <= N up to O(nu)
+    assert ev.min() >= -10 * nu * m
+    assert np.linalg.eigvalsh(Nh).min() >= -10 * nu * m
+
+
+def test_nystrom_invariant_under_rotation_of_test_matrix():
+    m, ell = 60, 10
+    rng = np.random.default_rng(4)
+    N = _lowrank_psd(m, m, 5, decay=1.5)
+    Om = rng.standard_normal((m, ell))
+    R = rng.standard_normal((ell, ell))
+    U1, l1, _ = nystrom.nystrom(lambda V: N @ V, nystrom.orthonormalize(Om))
+    U2, l2, _ = nystrom.nystrom(lambda V: N @ V, nystrom.orthonormalize(Om @ R))
+    np.testing.assert_allclose((U1 * l1) @ U1.T, (U2 * l2) @ U2.T, atol=1e-10)
+
+
+def test_eps_at_matches_library_spacing():
+    for v in (1.0, 3.7, 1e-5, 12345.678):
+        assert nystrom.eps_at(v, "f64") == np.spacing(v)
+        assert nystrom.eps_at(v, "f32") == float(np.spacing(np.float32(v)))
+    assert nystrom.eps_at(1.0, "bf16") == torch.finfo(torch.bfloat16).eps
+
+
+def test_preconditioner_closed_forms():
+    m, ell, delta = 50, 8, 0.05
+    rng = np.random.default_rng(6)
+    U, _ = np.linalg.qr(rng.standard_normal((m, ell)))
+    lam = np.sort(rng.uniform(0, 10, ell))[::-1]
+    P = nystrom.precond_dense(U, lam, delta)
+    Pinv = nystrom.precond_inv_dense(U, lam, delta)
+    np.testing.assert_allclose(P @ Pinv, np.eye(m), atol=1e-12)
+    np.testing.assert_allclose(Pinv, np.linalg.inv(P), atol=1e-10)
+    R = rng.standard_normal((m, 3))
+    np.testing.assert_allclose(nystrom.precond_inv_apply(U, lam, delta, R), np.linalg.solve(P, R), atol=1e-10)
+    # Table 2: one apply costs 2 ell m + m + 5 ell flops; eigenvalues of P^{-1}
+    # are 1 (on the complement) and (lam_l+delta)/(lam_i+delta) on range(U)
+    ev = np.sort(np.linalg.eigvalsh(0.5 * (Pinv + Pinv.T)))
+    expect = np.sort(np.concatenate([(lam.min() + delta) / (lam + delta), np.ones(m - ell)]))
+    np.testing.assert_allclose(ev, expect, atol=1e-12)
+
+
+@pytest.mark.parametrize("extra", [5, 0])
+def test_pcg_finite_termination_with_exact_rank_preconditioner(extra):
+    """N of exact rank r: with ell > r the preconditioned operator is delta*I
+    (one iteration); with ell = r it has two eigenvalues (two iterations)."""
+    m, r, delta = 100, 10, 1e-3
+    N = _lowrank_psd(m, r, 7)
+    Om = nystrom.orthonormalize(np.random.default_rng(8).standard_normal((m, r + extra)))
+    U, lam, _ = nystrom.nystrom(lambda V: N @ V, Om)
+    M = N + delta * np.eye(m)
+    xi = np.random.default_rng(9).standard_normal(m)
+    y, it, tr, _ = pcg.pcg(lambda v: M @ v, xi, lambda v: nystrom.precond_inv_apply(U, lam, delta, v),
+                           tol=1e-9 * np.linalg.norm(xi), maxit=50)
+    assert it == (1 if extra else 2)
+    np.testing.assert_allclose(y, np.linalg.solve(M, xi), rtol=1e-7)
+
+
+def test_pcg_matches_dense_solve():
+    rng = np.random.default_rng(10)
+    B = rng.standard_normal((40, 60))
+    M = B @ B.T + 0.1 * np.eye(40)
+    xi = rng.standard_normal(40)
+    y, it, tr, _ = pcg.pcg(lambda v: M @ v, xi, None, tol=1e-12, maxit=400)
+    np.testing.assert_allclose(y, sla.solve(M, xi, assume_a="pos"), rtol=1e-9)
+    assert tr <= 1e-11
+
+
+# ---------------------------------------------------------------- IP-PMM
+
+def test_step_length_fraction_to_boundary():
+    rng = np.random.default_rng(11)
+    v = rng.uniform(0.1, 1, 200)
+    dv = rng.standard_normal(200)
+    a = ippmm.step_length(v, dv)
+    assert np.all(v + a * dv > 0)
+    j = np.argmin(np.where(dv < 0, -v / np.where(dv < 0, dv, -1), np.inf))
+    np.testing.assert_allclose(v[j] + a / 0.995 * dv[j], 0.0, atol=1e-12)
+    assert ippmm.step_length(v, np.abs(dv)) == 0.995
+
+
+def test_ippmm_reaches_planted_optimum(small):
+    A, b, c, q = _np(small)
+    r = ippmm.solve(A, b, c, q, tol=1e-10)
+    assert r["status"] == 0 and r["kkt"] <= 1e-10
+    xs = small.x_star.numpy()
+    assert np.linalg.norm(r["x"] - xs) <= 1e-8 * np.linalg.norm(xs)
+    np.testing.assert_allclose(r["y"], small.y_star.numpy(), atol=1e-7)
+    xp, yp, zp, ok = ippmm.polish(A, b, c, q, r["x"], r["y"], r["z"])
+    assert ok and np.linalg.norm(xp - xs) <= 1e-12 * np.linalg.norm(xs)
+    assert np.all(r["x"] > 0) and np.all(r["z"] > 0)
+
+
+def test_ippmm_lowrank_zero_curvature_instance():
+    inst = make_instance("lowrank_5000x20000", seed=2, m=300, n=1200, rank=30)
+    A, b, c, q = _np(inst)
+    assert np.count_nonzero(q == 0) == 360
+    r = ippmm.solve(A, b, c, q, tol=1e-9)
+    xs = inst.x_star.numpy()
+    assert r["status"] == 0
+    assert np.linalg.norm(r["x"] - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_ippmm_matches_bruteforce(seed):
+    d = {k: v.numpy() for k, v in random_feasible_instance(4, 10, seed).items()}
+    best = bruteforce.optimum(d["A"], d["b"], d["c"], d["q"])
+    r = ippmm.solve(d["A"], d["b"], d["c"], d["q"], tol=1e-11)
+    assert r["status"] == 0
+    obj = problem.primal_objective(r["x"], d["c"], d["q"])
+    assert abs(obj - best["obj"]) <= 1e-8 * (1 + abs(best["obj"]))
+    np.testing.assert_allclose(r["x"], best["x"], atol=1e-6)     # Q > 0: unique optimum
+
+
+def test_initial_point_is_interior(small):
+    A, b, c, q = _np(small)
+    x0, y0, z0 = ippmm.initial_point(A, b, c, q)
+    assert np.all(x0 > 0) and np.all(z0 > 0)
+    m, n = A.shape
+    # candidates as Tikhonov least-squares problems solved by a library lstsq:
+    # x~ = argmin ||A x - b||^2 + 10 ||x||^2 (push-through identity), and
+    # y~ = argmin ||A^T y - (c + Q x~)||^2 + 10 ||y||^2
+    xt = np.linalg.lstsq(np.vstack([A, np.sqrt(10) * np.eye(n)]), np.concatenate([b, np.zeros(n)]),
+                         rcond=None)[0]
+    yt = np.linalg.lstsq(np.vstack([A.T, np.sqrt(10) * np.eye(m)]),
+                         np.concatenate([c + q * xt, np.zeros(m)]), rcond=None)[0]
+    np.testing.assert_allclose(y0, yt, atol=1e-10)
+    zt = c - A.T @ yt + q * xt
+    sx, sz = x0 - xt, z0 - zt            # the shifts are constant vectors
+    assert np.ptp(sx) < 1e-10 and np.ptp(sz) < 1e-10
+    dp = max(-1.5 * xt.min(), 0.0)
+    dd = max(-1.5 * zt.min(), 0.0)
+    gamma = (xt + dp) @ (zt + dd)
+    np.testing.assert_allclose(sx[0], dp + 0.5 * gamma / np.sum(zt + dd), rtol=1e-9)
+    np.testing.assert_allclose(sz[0], dd + 0.5 * gamma / np.sum(xt + dp), rtol=1e-9)
+
+
+# ---------------------------------------------------------------- adjoint
+
+def test_adjoint_matches_finite_differences():
+    inst = make_instance("gauss_2000x8000", seed=3, m=30, n=80)
+    A, b, c, q = _np(inst)
+    x, y, z = inst.x_star.numpy(), inst.y_star.numpy(), inst.z_star.numpy()
+    S = x > 0
+    x_tgt = x + 0.01 * np.random.default_rng(12).standard_normal(x.shape)
+    g = x - x_tgt
+    grad = adjoint.kkt_gradient(A, b, c, q, x, y, z, g)
+    rng = np.random.default_rng(13)
+    for block, size in (("c", 80), ("b", 30), ("q", 80), ("A", 30 * 80)):
+        coords = rng.choice(size, 16, replace=False)
+        fd = adjoint.fd_gradient(A, b, c, q, S, x_tgt, block, coords)
+        an = grad[block].reshape(-1)[coords]
+        assert np.linalg.norm(an - fd) <= 1e-7 * max(np.linalg.norm(fd), 1e-12), block
+
+
+# ---------------------------------------------------------------- low precision, RNG
+
+def test_bf16_rounding_matches_torch_and_ties_to_even():
+    rng = np.random.default_rng(14)
+    v = rng.standard_normal(20000) * np.exp(rng.uniform(-20, 20, 20000))
+    v32 = v.astype(np.float32)
+    ref = torch.from_numpy(v32).to(torch.bfloat16).to(torch.float64).numpy()
+    np.testing.assert_array_equal(lowprec.round_bf16(v32.astype(np.float64)), ref)
+    assert lowprec.round_bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0           # tie -> even
+    assert lowprec.round_bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
+    assert lowprec.round_f32(np.array([1.0 + 2.0 ** -24]))[0] == 1.0
+
+
+def test_bf16_sketch_exact_on_representable_data():
+    rng = np.random.default_rng(15)
+    A = rng.integers(-8, 8, (20, 30)).astype(np.float64)
+    Om = rng.integers(-4, 4, (20, 3)).astype(np.float64)
+    d = np.full(30, 0.5)
+    W = d[:, None] * (A.T @ Om)                  # small integers / 2: exact in BF16
+    assert np.all(lowprec.round_bf16(W) == W)
+    np.testing.assert_array_equal(lowprec.sketch_bf16(A, d, Om), A @ W)
+
+
+def test_philox_known_answers():
+    with open(os.path.join(GOLDEN, "philox4x32_10_kat.txt")) as f:
+        rows = [ln.split() for ln in f if ln.strip() and not ln.startswith("#")]
+    assert len(rows) == 3
+    for row in rows:
+        v = [int(t, 16) for t in row]
+        out = philox.philox4x32_10(*v[:6])
+        assert [int(o) for o in out] == v[6:]
+
+
+def test_philox_gaussian_distribution():
+    from scipy import stats
+    G = philox.gaussian_matrix(400, 50, seed=123, counter=7)
+    assert G.shape == (400, 50)
+    assert abs(G.mean()) < 0.02 and abs(G.std() - 1) < 0.02
+    assert stats.kstest(G.ravel(), "norm").pvalue > 1e-3
+    G2 = philox.gaussian_matrix(400, 50, seed=123, counter=8)
+    assert abs(np.corrcoef(G.ravel(), G2.ravel())[0, 1]) < 0.02
+    np.testing.assert_array_equal(G, philox.gaussian_matrix(400, 50, seed=123, counter=7))

@@ -1,0 +1,226 @@
+/*
+ * nysipm.h -- C ABI of the MI355X (gfx950) implementation of the hot path of
+ * Nys-IP-PMM (Chu, Santos, Udell: "Randomized Nystrom Preconditioned Interior
+ * Point-Proximal Method of Multipliers", arXiv 2404.14524) for the separable
+ * convex QP
+ *
+ *     (P)  min 1/2 x^T Q x + c^T x   s.t.  A x = b,  x >= 0,   Q = diag(q) >= 0
+ *     (D)  max b^T y - 1/2 x^T Q x   s.t.  A^T y + z = Q x + c,  z >= 0
+ *
+ * (paper, section 1).  All compute runs in the library's HIP kernels.
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * - Arrays are DEVICE pointers on the handle's device, allocated and owned by
+ *   the caller, contiguous; matrices are row-major with a leading dimension
+ *   (elements) >= the number of columns.  The library never frees caller
+ *   memory; it owns only the handle and the workspace the handle allocates.
+ * - FP64 vectors throughout; the constraint matrix may be stored in FP64,
+ *   FP32 or BF16 (nys_matrix.dtype).  Products with A always accumulate in
+ *   FP64, whatever the storage.
+ * - Work is enqueued on the handle's HIP stream.  Entry points that make host
+ *   decisions (nys_sketch, nys_pcg_solve, nys_newton_solve, ipm_solve,
+ *   ipm_adjoint) synchronise that stream before returning; the others
+ *   (nys_normal_apply, nys_precond_apply, nys_test_matrix) only enqueue.
+ * - Return codes: 0 = NYS_OK; > 0 = warning, outputs valid; < 0 = error.
+ *   Arguments are validated before any launch, so on NYS_EINVAL outputs are
+ *   untouched.  nys_last_error(h) gives a message.  Nothing aborts and no
+ *   exception crosses the ABI.  A handle is not thread-safe: one per stream.
+ */
+#ifndef NYSIPM_H
+#define NYSIPM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  NYS_OK = 0,
+  NYS_MAXIT = 1,          /* iteration limit reached; last iterate returned      */
+  NYS_EINVAL = -1,        /* null or inconsistent argument, non-finite scalar,
+                             q < 0, d < 0, delta <= 0 where required, ell not in
+                             [1, m], NaN/Inf in the data of ipm_solve            */
+  NYS_ENOMEM = -2,        /* workspace allocation failed                          */
+  NYS_EHIP = -3,          /* a HIP runtime call failed                            */
+  NYS_ENOTPD = -4,        /* Cholesky of a Gram matrix failed after the retries  */
+  NYS_EBREAKDOWN = -5,    /* PCG breakdown: p^T M p <= 0 or not finite            */
+  NYS_ENUMERIC = -6       /* NaN/Inf appeared in the interior-point iterates      */
+};
+
+typedef enum { NYS_F64 = 0, NYS_F32 = 1, NYS_BF16 = 2 } nys_dtype;
+
+typedef struct nys_handle_s* nys_handle;
+
+/* A: m x n, row-major, leading dimension ld (elements), storage dtype. */
+typedef struct {
+  int64_t m, n, ld;
+  nys_dtype dtype;
+  const void* data;
+} nys_matrix;
+
+/* Nystrom preconditioner {U_hat, Lambda_hat} (Algorithm 2; eq. Nys_precond).
+   U: m x ell FP64 row-major with orthonormal columns; lambda: ell FP64,
+   descending, >= 0.  delta is supplied at apply time. */
+typedef struct {
+  int64_t m;
+  int32_t ell;
+  double* U;
+  double* lambda;
+} nys_precond;
+
+/* ---------------------------------------------------------------- handle */
+
+/* Create a handle on HIP device `device`, enqueuing on `hip_stream`
+   (a hipStream_t; NULL = the null stream).  Returns NYS_EINVAL / NYS_EHIP. */
+int nys_create(nys_handle* h, int device, void* hip_stream);
+int nys_destroy(nys_handle h);
+int nys_set_stream(nys_handle h, void* hip_stream);
+const char* nys_last_error(nys_handle h);
+/* Milliseconds of GPU time spent in the last call, split as in the paper's
+   time breakdown (section 5.2.3): preconditioner construction, PCG, other.
+   Valid after ipm_solve / ipm_adjoint; otherwise zeros. */
+int nys_last_timing(nys_handle h, double* t_sketch_ms, double* t_pcg_ms, double* t_other_ms);
+
+/* ---------------------------------------------------------------- operators */
+
+/* out = (A diag(d) A^T + delta I) v : the regularised normal-equation operator
+   N + delta I of eq. normal-eq with d = (Q + Theta^{-1} + rho I)^{-1}.
+   Two passes over A: w = d .* (A^T v), then out = A w + delta v.
+   d: n FP64 (>= 0 is not checked here: any d gives the product), v, out: m
+   FP64, out must not alias v.  Enqueue only. */
+int nys_normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                     const double* v, double* out);
+
+/* Gaussian test matrix (Algorithm 1, first step): out (m x ell FP64,
+   row-major) = standard normals from Philox4x32-10 keyed by `seed`, with the
+   64-bit draw `counter`; entry e = i*ell + j uses the pair index e/2 as the
+   counter's low half and Box-Muller on the four outputs.  Enqueue only. */
+int nys_test_matrix(nys_handle h, int64_t m, int32_t ell, uint64_t seed, uint64_t counter,
+                    double* out);
+
+/* Randomized Nystrom approximation of N = A diag(d) A^T (Algorithm 1; the
+   sketched matrix is N, not N + delta I) and the data of the Nystrom
+   preconditioner (Algorithm 2).
+   Omega = omega (m x ell FP64) if non-NULL, else nys_test_matrix(seed,
+   counter); Omega is orthonormalised by a thin QR; Y = N Omega computed as
+   W = d .* (A^T Omega), Y = A W, in FP64 (sketch_dtype NYS_F64, A must then be
+   FP64 or FP32) or on BF16 matrix cores with FP32 accumulation (NYS_BF16;
+   A must then be BF16 storage); nu = c_nu * eps(||Y||_F) in the sketch
+   precision; Y_nu = Y + nu Omega; C = chol(Omega^T Y_nu) (upper, C^T C = G);
+   B = Y_nu C^{-1}; thin SVD of B by Cholesky-QR and a one-sided Jacobi SVD of
+   the triangular factor; U_hat = left singular vectors, Lambda_hat =
+   max(0, Sigma^2 - nu), descending.  On a failed Cholesky nu grows by 10x, up
+   to 6 times, then NYS_ENOTPD.
+   P->m must equal A->m, 1 <= P->ell <= m; P->U, P->lambda are caller buffers.
+   nu_out (host, may be NULL) receives the final shift.  Synchronises. */
+int nys_sketch(nys_handle h, const nys_matrix* A, const double* d, int32_t ell,
+               uint64_t seed, uint64_t counter, nys_dtype sketch_dtype,
+               const double* omega_or_null, nys_precond* P, double* nu_out);
+
+/* out = P^{-1} r with eq. Nys_precond_inv:
+   P^{-1} = (lambda_ell + delta) U (Lambda + delta I)^{-1} U^T + (I - U U^T).
+   delta > 0.  r, out: m FP64, may not alias.  Enqueue only. */
+int nys_precond_apply(nys_handle h, const nys_precond* P, double delta, const double* r,
+                      double* out);
+
+/* ---------------------------------------------------------------- PCG */
+
+typedef struct {
+  double rtol;            /* stop when ||rhs - M y|| <= max(rtol ||rhs||, atol) */
+  double atol;
+  int32_t maxit;          /* <= 0: min(m, 2000)                                  */
+  int32_t replace_every;  /* FP64 true-residual replacement period; <= 0: 50     */
+  int32_t poll_every;     /* host convergence poll period; <= 0: 8               */
+} nys_pcg_opts;
+
+typedef struct {
+  int32_t iters;
+  int32_t status;         /* NYS_OK, NYS_MAXIT or NYS_EBREAKDOWN                 */
+  double true_res;        /* ||rhs - M y||_2 recomputed at exit                  */
+  double rel_res;         /* true_res / ||rhs||_2                                */
+} nys_pcg_info;
+
+/* Preconditioned CG (section 2.2) on (A diag(d) A^T + delta I) y = rhs with
+   the Nystrom preconditioner P (NULL: plain CG).  y holds the initial guess on
+   entry (NULL-equivalent: pass zeros) and the solution on exit.  The stopping
+   test is on the true residual; the recursion is refreshed with an
+   FP64-accumulated true residual every replace_every iterations.
+   Returns NYS_OK, NYS_MAXIT (warning, last iterate in y) or NYS_EBREAKDOWN.
+   Synchronises. */
+int nys_pcg_solve(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                  const nys_precond* P, const double* rhs, double* y,
+                  const nys_pcg_opts* opts, nys_pcg_info* info);
+
+/* One Newton direction of IP-PMM for non-negative variables (Algorithm 5 with
+   F = J = empty; eq. normal-eq, delta_x, delta_z):
+   D = (Q + Z X^{-1} + rho I)^{-1}; xi_au = -X^{-1} r_xz;
+   xi = r_p + A D (r_d + xi_au); PCG for (A D A^T + delta I) dy = xi;
+   dx = D (A^T dy - r_d - xi_au); dz = X^{-1} (r_xz - Z dx).
+   x, z > 0 and q >= 0 (n), rho >= 0, delta > 0; P may be NULL.  Outputs dx,
+   dz (n), dy (m).  Synchronises. */
+int nys_newton_solve(nys_handle h, const nys_matrix* A, const double* q, const double* x,
+                     const double* z, double rho, double delta, const nys_precond* P,
+                     const double* r_d, const double* r_p, const double* r_xz,
+                     const nys_pcg_opts* opts, double* dx, double* dy, double* dz,
+                     nys_pcg_info* info);
+
+/* ---------------------------------------------------------------- IP-PMM */
+
+typedef struct {
+  const nys_matrix* A;      /* problem-defining matrix (FP64 or FP32 storage)   */
+  const nys_matrix* A_lo;   /* BF16 copy for the sketch, or NULL                */
+  const double* b;          /* m */
+  const double* c;          /* n */
+  const double* q;          /* n, diag(Q) >= 0 */
+} nys_qp;
+
+typedef struct {
+  double tol;               /* max(rp_rel, rd_rel, mu) target; <= 0: 1e-6      */
+  int32_t max_iter;         /* IP-PMM iterations; <= 0: 100                     */
+  int32_t ell;              /* sketch size, 1 <= ell <= m                        */
+  uint64_t seed;            /* Philox key of the test matrices                  */
+  nys_dtype sketch_dtype;   /* NYS_F64 or NYS_BF16 (needs A_lo or converts A)   */
+  double c_nu;              /* shift constant of the sketch; <= 0: 1             */
+  nys_pcg_opts pcg;
+  int32_t verbose;          /* 1: one line per iteration on stderr              */
+} nys_ipm_opts;
+
+typedef struct {
+  int32_t iters, pcg_iters_total, status;
+  double kkt_rel, rp_rel, rd_rel, mu, rho, delta;
+  double t_sketch_ms, t_pcg_ms, t_other_ms;
+} nys_ipm_info;
+
+/* Nys-IP-PMM (Algorithm 4 with the predictor-corrector of Algorithm 6 and the
+   Newton solve of Algorithm 5) for (P): initial point from the regularised
+   (A A^T + 10 I) systems solved by Nystrom-PCG; rho_0 = delta_0 = 8; per
+   iteration a fresh Nystrom preconditioner of N_k shared by predictor and
+   corrector; step lengths with factor 0.995; parameter update
+   rho = delta = max(5e-10, min(rho, mu)); stop when
+   max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
+   Outputs x, z (n) and y (m) FP64.  Returns NYS_OK, NYS_MAXIT, or an error.
+   Synchronises. */
+int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* x, double* y,
+              double* z, nys_ipm_info* info);
+
+/* Adjoint of the converged KKT system (not in the paper; derived from the
+   optimality conditions of (P)/(D)).  With g = dL/dx at the solution (x, y, z)
+   returned by ipm_solve with final parameters (rho, delta):
+   D_j = 0 where x_j <= z_j, else (q_j + z_j/x_j + rho)^{-1};
+   (A D A^T + delta I) u2 = A (D g) by Nystrom-PCG; u1 = D (g - A^T u2);
+   grad_c = -u1, grad_b = u2, grad_q = -u1 .* x, grad_A = y u1^T - u2 x^T.
+   Any output pointer may be NULL (skipped); grad_A is m x n row-major FP64
+   with leading dimension n.  Synchronises. */
+int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, const double* x,
+                const double* y, const double* z, double rho, double delta, const double* g,
+                double* grad_c, double* grad_b, double* grad_q, double* grad_A,
+                nys_pcg_info* info);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NYSIPM_H */

@@ -1,0 +1,15 @@
+"""MI355X (gfx950) implementation of the hot path of Nys-IP-PMM (randomized
+Nystrom preconditioned IP-PMM, arXiv 2404.14524) for separable convex QPs.
+
+The compute lives in libnysipm.so (HIP kernels behind the C ABI declared in
+include/nysipm.h); ``nysipm`` is its ctypes binding and ``autograd`` wraps
+the solver and its adjoint in a torch.autograd.Function.
+"""
+
+from .nysipm import (NysError, Precond, ipm_adjoint, ipm_solve, load_library, nys_last_timing,
+                     nys_newton_solve, nys_normal_apply, nys_pcg_solve, nys_precond_apply,
+                     nys_sketch, nys_test_matrix)
+
+__all__ = ["NysError", "Precond", "ipm_adjoint", "ipm_solve", "load_library", "nys_last_timing",
+           "nys_newton_solve", "nys_normal_apply", "nys_pcg_solve", "nys_precond_apply",
+           "nys_sketch", "nys_test_matrix"]

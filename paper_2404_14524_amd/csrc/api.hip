@@ -1,0 +1,658 @@
+// C ABI of libnysipm: handle and workspace, argument validation, and the host
+// drivers of the Nystrom sketch (Algorithms 1-2), PCG, the Newton step
+// (Algorithm 5), Nys-IP-PMM (Algorithms 4 and 6) and the KKT adjoint.
+// Every arithmetic step runs in the kernels of this library; the host only
+// sequences launches and takes the scalar decisions of the algorithms.
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mapreduce.hpp"
+
+namespace nys {
+
+int set_error(nys_handle h, int code, const char* fmt, ...) {
+  if (!h) return code;
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  h->err = buf;
+  return code;
+}
+
+int ws_get(nys_handle h, int slot, size_t bytes, void** out) {
+  if (bytes == 0) bytes = 8;
+  if (h->slot_bytes[slot] < bytes) {
+    if (h->slot_ptr[slot]) {
+      // a kernel still queued may use the old buffer
+      NYS_HIP(h, hipStreamSynchronize(h->stream));
+      NYS_HIP(h, hipFree(h->slot_ptr[slot]));
+      h->slot_ptr[slot] = nullptr;
+      h->slot_bytes[slot] = 0;
+    }
+    const size_t rounded = (bytes + (1u << 20) - 1) & ~(size_t)((1u << 20) - 1);
+    void* p = nullptr;
+    if (hipMalloc(&p, rounded) != hipSuccess || !p) {
+      (void)hipGetLastError();
+      return set_error(h, NYS_ENOMEM, "workspace allocation of %zu bytes failed", rounded);
+    }
+    h->slot_ptr[slot] = p;
+    h->slot_bytes[slot] = rounded;
+  }
+  *out = h->slot_ptr[slot];
+  return NYS_OK;
+}
+
+int read_scalars(nys_handle h, int first, int count) {
+  NYS_HIP(h, hipMemcpyAsync(h->hscal + first, h->dscal + first, sizeof(double) * count,
+                            hipMemcpyDeviceToHost, h->stream));
+  NYS_HIP(h, hipStreamSynchronize(h->stream));
+  return NYS_OK;
+}
+
+int sync(nys_handle h) {
+  NYS_HIP(h, hipStreamSynchronize(h->stream));
+  return NYS_OK;
+}
+
+namespace {
+
+// ---------------------------------------------------------------- small kernels
+__global__ void k_set_scalars(double* s, int n, int i0, double v0, int i1, double v1, int i2,
+                              double v2, int i3, double v3) {
+  if (threadIdx.x != 0) return;
+  if (n > 0) s[i0] = v0;
+  if (n > 1) s[i1] = v1;
+  if (n > 2) s[i2] = v2;
+  if (n > 3) s[i3] = v3;
+}
+
+int set_scalars(nys_handle h, int n, int i0, double v0, int i1 = 0, double v1 = 0, int i2 = 0,
+                double v2 = 0, int i3 = 0, double v3 = 0) {
+  hipLaunchKernelGGL(k_set_scalars, dim3(1), dim3(64), 0, h->stream, h->dscal, n, i0, v0, i1, v1,
+                     i2, v2, i3, v3);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+// lambda_hat = max(0, sig2 - nu)
+struct LamF {
+  const double* sig2;
+  double* lam;
+  double nu;
+  __device__ void operator()(int64_t j, double*, double*) const { lam[j] = fmax(0.0, sig2[j] - nu); }
+};
+// Y_nu = Y + nu Omega
+struct ShiftF {
+  double* out;
+  const double* Y;
+  const double* O;
+  double nu;
+  __device__ void operator()(int64_t j, double*, double*) const { out[j] = fma(nu, O[j], Y[j]); }
+};
+// r = rhs - Mv (FP64) and ||r||^2
+struct ResF {
+  double* r;
+  const double* rhs;
+  const double* mv;
+  __device__ void operator()(int64_t j, double* s, double*) const {
+    const double v = rhs[j] - mv[j];
+    r[j] = v;
+    s[0] = fma(v, v, s[0]);
+  }
+};
+
+// rank-2 update grad_A = y u1^T - u2 x^T (m x n, ld n)
+__global__ __launch_bounds__(NYS_BLOCK) void k_grad_A(int64_t m, int64_t n, const double* y,
+                                                      const double* u1, const double* u2,
+                                                      const double* x, double* G) {
+  const int64_t total = m * n;
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    const int64_t i = idx / n, j = idx % n;
+    G[idx] = y[i] * u1[j] - u2[i] * x[j];
+  }
+}
+
+// ---------------------------------------------------------------- validation
+bool is_fin(double v) { return std::isfinite(v); }
+
+int check_matrix(nys_handle h, const nys_matrix* A, const char* who) {
+  if (!A) return set_error(h, NYS_EINVAL, "%s: matrix is NULL", who);
+  if (A->m < 0 || A->n < 0 || A->ld < A->n || A->ld < 1)
+    return set_error(h, NYS_EINVAL, "%s: bad shape m=%lld n=%lld ld=%lld", who, (long long)A->m,
+                     (long long)A->n, (long long)A->ld);
+  if (A->dtype != NYS_F64 && A->dtype != NYS_F32 && A->dtype != NYS_BF16)
+    return set_error(h, NYS_EINVAL, "%s: bad dtype %d", who, (int)A->dtype);
+  if (A->m > 0 && A->n > 0 && !A->data) return set_error(h, NYS_EINVAL, "%s: data is NULL", who);
+  return NYS_OK;
+}
+
+int check_precond(nys_handle h, const nys_precond* P, int64_t m, const char* who) {
+  if (!P) return NYS_OK;
+  if (P->m != m || P->ell < 1 || P->ell > m || !P->U || !P->lambda)
+    return set_error(h, NYS_EINVAL, "%s: bad preconditioner (m=%lld ell=%d)", who, (long long)P->m,
+                     P->ell);
+  return NYS_OK;
+}
+
+struct PcgCfg {
+  double rtol = 1e-10, atol = 0.0;
+  int maxit = 0, replace_every = 50, poll_every = 8;
+  // mu rule of the interior-point inner solves (mu_abs >= 0):
+  // tol = max(floor_rel ||rhs||, min(rtol ||rhs||, mu_abs))
+  double mu_abs = -1.0, floor_rel = 1e-12;
+};
+
+PcgCfg pcg_cfg(const nys_pcg_opts* o, int64_t m) {
+  PcgCfg c;
+  if (o) {
+    c.rtol = o->rtol;
+    c.atol = o->atol;
+    c.maxit = o->maxit;
+    c.replace_every = o->replace_every;
+    c.poll_every = o->poll_every;
+  }
+  if (c.maxit <= 0) c.maxit = (int)std::min<int64_t>(std::max<int64_t>(m, 1), 2000);
+  if (c.replace_every <= 0) c.replace_every = 50;
+  if (c.poll_every <= 0) c.poll_every = 8;
+  if (!(c.rtol >= 0)) c.rtol = 0;
+  if (!(c.atol >= 0)) c.atol = 0;
+  return c;
+}
+
+// ---------------------------------------------------------------- PCG driver
+struct Precond {
+  const double* U = nullptr;
+  const double* lam = nullptr;
+  int ell = 0;
+};
+
+// Solves (A diag(d) A^T + delta I) y = rhs.  y_zero: y is taken as 0 (and set).
+int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, const Precond& P,
+            const double* rhs, double* y, bool y_zero, const PcgCfg& cfg, nys_pcg_info* info) {
+  const int64_t m = A->m;
+  const bool pre = P.U != nullptr;
+  double* base;
+  NYS_CHECK(ws(h, WS_PCG, (size_t)6 * m + P.ell + 8, &base));
+  double* r = base;
+  double* s = base + m;
+  double* pa = base + 2 * m;
+  double* pb = base + 3 * m;
+  double* q = base + 4 * m;
+  double* tmp = base + 5 * m;
+  double* t = base + 6 * m;
+  double* sc = h->dscal;
+  nys_pcg_info out{0, NYS_OK, 0.0, 0.0};
+
+  NYS_CHECK(dot(h, rhs, rhs, m, sc + SC_RED0));
+  NYS_CHECK(read_scalars(h, SC_RED0, 1));
+  const double bnorm = std::sqrt(h->hscal[SC_RED0]);
+  const double tol = cfg.mu_abs >= 0
+                         ? std::max(cfg.floor_rel * bnorm, std::min(cfg.rtol * bnorm, cfg.mu_abs))
+                         : std::max(cfg.rtol * bnorm, cfg.atol);
+
+  // true residual r = rhs - M y into `dst`, ||.||^2 -> sc[SC_RED0 + 1]
+  auto true_residual = [&](double* dst) -> int {
+    NYS_CHECK(normal_apply(h, A, d, delta, y, q, nullptr));
+    return map_reduce<1, 0>(h, m, ResF{dst, rhs, q}, sc + SC_RED0 + 1);
+  };
+  // s = P^{-1} r and rs = r^T s (or rs = ||r||^2 without a preconditioner)
+  auto refresh_s = [&]() -> int {
+    if (pre) {
+      NYS_CHECK(precond_reduce(h, P.U, P.lam, m, P.ell, delta, r, t));
+      return precond_expand(h, P.U, m, P.ell, r, t, s, sc + SC_RS);
+    }
+    return dot(h, r, r, m, sc + SC_RS);
+  };
+
+  if (y_zero) NYS_CHECK(fill(h, y, m, 0.0));
+  if (bnorm == 0.0 && y_zero) {
+    if (info) *info = out;
+    return NYS_OK;
+  }
+  if (y_zero) NYS_CHECK(copy(h, r, rhs, m));
+  else NYS_CHECK(true_residual(r));
+  NYS_CHECK(set_scalars(h, 4, SC_DONE, 0.0, SC_BREAK, 0.0, SC_ITERS, 0.0, SC_BETA, 0.0));
+  NYS_CHECK(set_scalars(h, 1, SC_TOL2, tol * tol));
+  NYS_CHECK(fill(h, pa, m, 0.0));
+  NYS_CHECK(refresh_s());
+  const double* sdir = pre ? s : r;
+
+  int status = NYS_MAXIT;
+  bool final_res_known = false;
+  double final_res = 0.0;
+  int it = 0;
+  while (it < cfg.maxit) {
+    double* pold = (it % 2 == 0) ? pa : pb;
+    double* pnew = (it % 2 == 0) ? pb : pa;
+    GemvT g1;
+    g1.A = A;
+    g1.skip = sc + SC_DONE;
+    g1.s = sdir;
+    g1.pold = pold;
+    g1.pnew = pnew;
+    g1.beta = sc + SC_BETA;
+    g1.d = d;
+    double* w;
+    NYS_CHECK(ws(h, WS_W, (size_t)std::max<int64_t>(A->n, 1), &w));
+    g1.w = w;
+    NYS_CHECK(gemv_t(h, g1));
+    GemvN g2;
+    g2.A = A;
+    g2.skip = sc + SC_DONE;
+    g2.w = w;
+    g2.v = pnew;
+    g2.sV = delta;
+    g2.out = q;
+    g2.dot_out = sc + SC_PQ;
+    NYS_CHECK(gemv_n(h, g2));
+    NYS_CHECK(pcg_update(h, m, y, r, pnew, q, P.U, P.lam, P.ell, delta, t));
+    if (pre) NYS_CHECK(pcg_expand(h, m, P.U, P.ell, r, t, s));
+    ++it;
+    const bool poll = (it % cfg.poll_every == 0) || it == cfg.maxit;
+    if (poll) {
+      NYS_CHECK(read_scalars(h, 0, SC_RED0));
+      if (h->hscal[SC_BREAK] != 0.0) {
+        status = NYS_EBREAKDOWN;
+        break;
+      }
+      if (h->hscal[SC_DONE] != 0.0) {
+        NYS_CHECK(true_residual(tmp));
+        NYS_CHECK(read_scalars(h, SC_RED0 + 1, 1));
+        const double tr = std::sqrt(h->hscal[SC_RED0 + 1]);
+        if (tr <= tol) {
+          status = NYS_OK;
+          final_res_known = true;
+          final_res = tr;
+          break;
+        }
+        // the recursion drifted: restart from the true residual
+        NYS_CHECK(copy(h, r, tmp, m));
+        NYS_CHECK(refresh_s());
+        NYS_CHECK(set_scalars(h, 2, SC_DONE, 0.0, SC_BETA, 0.0));
+        continue;
+      }
+    }
+    if (it % cfg.replace_every == 0 && it < cfg.maxit) {
+      NYS_CHECK(true_residual(r));
+      NYS_CHECK(refresh_s());
+    }
+  }
+  NYS_CHECK(read_scalars(h, 0, SC_RED0));
+  out.iters = (int)h->hscal[SC_ITERS];
+  if (!final_res_known) {
+    NYS_CHECK(true_residual(tmp));
+    NYS_CHECK(read_scalars(h, SC_RED0 + 1, 1));
+    final_res = std::sqrt(h->hscal[SC_RED0 + 1]);
+    if (status == NYS_MAXIT && final_res <= tol) status = NYS_OK;
+  }
+  out.status = status;
+  out.true_res = final_res;
+  out.rel_res = bnorm > 0 ? final_res / bnorm : final_res;
+  if (info) *info = out;
+  if (status == NYS_EBREAKDOWN)
+    return set_error(h, NYS_EBREAKDOWN, "PCG breakdown after %d iterations (p^T M p <= 0)", out.iters);
+  return status;
+}
+
+// ---------------------------------------------------------------- Nystrom sketch
+struct SketchOut {
+  double* U;
+  double* lam;
+  double nu;
+};
+
+int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint64_t seed,
+               uint64_t counter, nys_dtype mode, double c_nu, const double* omega,
+               SketchOut* outp) {
+  const int64_t m = A->m;
+  double *Om, *Y, *B, *Q1, *small;
+  NYS_CHECK(ws(h, WS_OMEGA, (size_t)m * ell, &Om));
+  NYS_CHECK(ws(h, WS_Y, (size_t)m * ell, &Y));
+  NYS_CHECK(ws(h, WS_B, (size_t)m * ell, &B));
+  NYS_CHECK(ws(h, WS_Q1, (size_t)m * ell, &Q1));
+  const int64_t l2 = (int64_t)ell * ell;
+  NYS_CHECK(ws(h, WS_SMALL, (size_t)8 * l2 + 2 * ell + 16, &small));
+  double* G = small;
+  double* Cinv = small + l2;
+  double* R1 = small + 2 * l2;
+  double* R2 = small + 3 * l2;
+  double* T = small + 4 * l2;
+  double* jw = small + 5 * l2;          // Jacobi work: l2 + 1 words
+  double* sig2 = small + 7 * l2;
+  double* fail = h->dscal + SC_FAIL;
+
+  // test matrix and its thin QR (two passes of Cholesky-QR: a Gaussian
+  // m x ell block with m >= ell is well conditioned)
+  if (omega) NYS_CHECK(copy(h, Om, omega, m * ell));
+  else NYS_CHECK(philox_gaussian(h, m, ell, seed, counter, Om));
+  auto cholqr_pass = [&](double* X, double* Xout, double shift_rel, double* Rout) -> int {
+    NYS_CHECK(gemm_f64(h, true, false, ell, ell, m, X, NYS_F64, ell, X, ell, G, ell, nullptr));
+    NYS_CHECK(chol_upper(h, G, ell, 0.0, shift_rel, fail));
+    NYS_CHECK(read_scalars(h, SC_FAIL, 1));
+    if (h->hscal[SC_FAIL] != 0.0) return set_error(h, NYS_ENOTPD, "Cholesky-QR: Gram matrix not positive definite");
+    NYS_CHECK(tri_inv_upper(h, G, Cinv, ell));
+    NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, X, NYS_F64, ell, Cinv, ell, Xout, ell, nullptr));
+    if (Rout) NYS_CHECK(copy(h, Rout, G, l2));
+    return NYS_OK;
+  };
+  NYS_CHECK(cholqr_pass(Om, Q1, 0.0, nullptr));
+  NYS_CHECK(cholqr_pass(Q1, Om, 0.0, nullptr));
+
+  // Y = N Omega
+  NYS_CHECK(sketch_product(h, A, d, Om, ell, mode, Y));
+  NYS_CHECK(sumsq(h, Y, m * ell, h->dscal + SC_RED0));
+  NYS_CHECK(read_scalars(h, SC_RED0, 1));
+  const double ynorm = std::sqrt(h->hscal[SC_RED0]);
+  if (!std::isfinite(ynorm)) return set_error(h, NYS_ENUMERIC, "sketch: non-finite Y");
+  const int pbits = (mode == NYS_BF16) ? 8 : 53;
+  double nu = ynorm > 0 ? c_nu * std::ldexp(1.0, std::ilogb(ynorm) - (pbits - 1)) : c_nu * 1e-300;
+
+  // C = chol(Omega^T Y_nu) with retries; B = Y_nu C^{-1}
+  bool ok = false;
+  for (int attempt = 0; attempt <= 6; ++attempt) {
+    NYS_CHECK(map_reduce<0, 0>(h, m * ell, ShiftF{B, Y, Om, nu}, nullptr));
+    NYS_CHECK(gemm_f64(h, true, false, ell, ell, m, Om, NYS_F64, ell, B, ell, G, ell, nullptr));
+    NYS_CHECK(chol_upper(h, G, ell, 0.0, 0.0, fail));
+    NYS_CHECK(read_scalars(h, SC_FAIL, 1));
+    if (h->hscal[SC_FAIL] == 0.0) {
+      ok = true;
+      break;
+    }
+    nu *= 10.0;
+  }
+  if (!ok) return set_error(h, NYS_ENOTPD, "sketch: chol(Omega^T Y_nu) failed after 6 shift increases (nu=%g)", nu);
+  NYS_CHECK(tri_inv_upper(h, G, Cinv, ell));
+  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, B, NYS_F64, ell, Cinv, ell, Q1, ell, nullptr));
+  // thin QR of B (now in Q1) by shifted Cholesky-QR3:
+  // R1 = chol(B^T B + s I), s = 11 (m ell + ell(ell+1)) u ||B||_F^2; then two plain passes.
+  const double u = 1.1102230246251565e-16;
+  const double srel = 11.0 * ((double)m * ell + (double)ell * (ell + 1)) * u;
+  NYS_CHECK(cholqr_pass(Q1, B, srel, R1));
+  NYS_CHECK(cholqr_pass(B, Q1, 0.0, R2));
+  NYS_CHECK(small_mm(h, R2, R1, T, ell));           // T = R2 R1
+  NYS_CHECK(cholqr_pass(Q1, B, 0.0, R1));           // Q in B, R3 in R1
+  NYS_CHECK(small_mm(h, R1, T, R2, ell));           // R = R3 R2 R1 in R2
+  // SVD of the triangular factor: left singular vectors U_R, Sigma^2
+  NYS_CHECK(jacobi_svd(h, R2, ell, sig2, jw));
+  // U_hat = Q U_R ; Lambda_hat = max(0, Sigma^2 - nu)
+  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, B, NYS_F64, ell, R2, ell, outp->U, ell, nullptr));
+  NYS_CHECK(map_reduce<0, 0>(h, ell, LamF{sig2, outp->lam, nu}, nullptr));
+  outp->nu = nu;
+  return NYS_OK;
+}
+
+// ---------------------------------------------------------------- Newton step (Alg. 5)
+struct NewtonPre {
+  // tn = D (r_d + xi_au), x0n = -(r_d + xi_au), xi_au = -r_xz / x
+  double* tn;
+  double* x0n;
+  const double* D;
+  const double* rd;   // may be NULL (zero)
+  const double* rxz;
+  const double* x;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    const double a = (rd ? rd[j] : 0.0) - rxz[j] / x[j];
+    tn[j] = D[j] * a;
+    x0n[j] = -a;
+  }
+};
+struct NewtonDz {
+  double* dz;
+  const double* rxz;
+  const double* z;
+  const double* dx;
+  const double* x;
+  __device__ void operator()(int64_t j, double*, double*) const { dz[j] = (rxz[j] - z[j] * dx[j]) / x[j]; }
+};
+struct ScalingF {
+  double* D;
+  const double* q;
+  const double* x;
+  const double* z;
+  double rho;
+  __device__ void operator()(int64_t j, double*, double*) const { D[j] = 1.0 / (q[j] + z[j] / x[j] + rho); }
+};
+
+int newton_run(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
+               double delta, const Precond& P, const double* rd, const double* rp, const double* rxz,
+               const PcgCfg& cfg, double* dx, double* dy, double* dz, nys_pcg_info* info) {
+  const int64_t m = A->m, n = A->n;
+  double* base;
+  NYS_CHECK(ws(h, WS_NEWTON, (size_t)2 * n + m + 8, &base));
+  double* tn = base;
+  double* x0n = base + n;
+  double* xi = base + 2 * n;
+  NYS_CHECK(map_reduce<0, 0>(h, n, NewtonPre{tn, x0n, D, rd, rxz, x}, nullptr));
+  GemvN g2;
+  g2.A = A;
+  g2.w = tn;
+  g2.x0 = rp;
+  g2.out = xi;
+  if (!rp) {
+    // xi = A tn
+    g2.x0 = nullptr;
+  }
+  NYS_CHECK(gemv_n(h, g2));
+  int rc = pcg_run(h, A, D, delta, P, xi, dy, true, cfg, info);
+  if (rc < 0) return rc;
+  GemvT g1;
+  g1.A = A;
+  g1.v = dy;
+  g1.x0 = x0n;
+  g1.d = D;
+  g1.w = dx;
+  NYS_CHECK(gemv_t(h, g1));
+  NYS_CHECK(map_reduce<0, 0>(h, n, NewtonDz{dz, rxz, z, dx, x}, nullptr));
+  return rc;
+}
+
+}  // namespace
+}  // namespace nys
+
+using namespace nys;
+
+// ================================================================== C ABI
+
+extern "C" int nys_create(nys_handle* out, int device, void* stream) {
+  if (!out) return NYS_EINVAL;
+  *out = nullptr;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev) return NYS_EINVAL;
+  auto* h = new (std::nothrow) nys_handle_s();
+  if (!h) return NYS_ENOMEM;
+  h->device = device;
+  h->stream = (hipStream_t)stream;
+  if (hipSetDevice(device) != hipSuccess) {
+    delete h;
+    return NYS_EHIP;
+  }
+  h->ncounters = 1 << 16;
+  if (hipMalloc(&h->counters, h->ncounters * sizeof(unsigned)) != hipSuccess ||
+      hipMemset(h->counters, 0, h->ncounters * sizeof(unsigned)) != hipSuccess ||
+      hipMalloc(&h->dscal, SC_NSCAL * sizeof(double)) != hipSuccess ||
+      hipMemset(h->dscal, 0, SC_NSCAL * sizeof(double)) != hipSuccess ||
+      hipHostMalloc(&h->hscal, SC_NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess ||
+      hipDeviceSynchronize() != hipSuccess) {
+    (void)hipGetLastError();
+    nys_destroy(h);
+    return NYS_EHIP;
+  }
+  *out = h;
+  return NYS_OK;
+}
+
+extern "C" int nys_destroy(nys_handle h) {
+  if (!h) return NYS_OK;
+  (void)hipSetDevice(h->device);
+  (void)hipStreamSynchronize(h->stream);
+  for (int s = 0; s < WS_NSLOTS; ++s)
+    if (h->slot_ptr[s]) (void)hipFree(h->slot_ptr[s]);
+  if (h->counters) (void)hipFree(h->counters);
+  if (h->dscal) (void)hipFree(h->dscal);
+  if (h->hscal) (void)hipHostFree(h->hscal);
+  delete h;
+  return NYS_OK;
+}
+
+extern "C" int nys_set_stream(nys_handle h, void* stream) {
+  if (!h) return NYS_EINVAL;
+  (void)hipStreamSynchronize(h->stream);
+  h->stream = (hipStream_t)stream;
+  return NYS_OK;
+}
+
+extern "C" const char* nys_last_error(nys_handle h) { return h ? h->err.c_str() : "null handle"; }
+
+extern "C" int nys_last_timing(nys_handle h, double* ts, double* tp, double* to) {
+  if (!h) return NYS_EINVAL;
+  if (ts) *ts = h->t_sketch;
+  if (tp) *tp = h->t_pcg;
+  if (to) *to = h->t_other;
+  return NYS_OK;
+}
+
+extern "C" int nys_normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                                const double* v, double* out) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_normal_apply"));
+  if (!is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_normal_apply: non-finite delta");
+  if (A->m > 0 && (!v || !out)) return set_error(h, NYS_EINVAL, "nys_normal_apply: NULL vector");
+  if (A->n > 0 && A->m > 0 && !d) return set_error(h, NYS_EINVAL, "nys_normal_apply: NULL d");
+  if (v == out && A->m > 0) return set_error(h, NYS_EINVAL, "nys_normal_apply: out aliases v");
+  NYS_HIP(h, hipSetDevice(h->device));
+  if (A->m == 0) return NYS_OK;
+  return normal_apply(h, A, d, delta, v, out, nullptr);
+}
+
+extern "C" int nys_test_matrix(nys_handle h, int64_t m, int32_t ell, uint64_t seed, uint64_t counter,
+                               double* out) {
+  if (!h) return NYS_EINVAL;
+  if (m < 0 || ell < 0 || (m * ell > 0 && !out)) return set_error(h, NYS_EINVAL, "nys_test_matrix: bad arguments");
+  NYS_HIP(h, hipSetDevice(h->device));
+  if (m * ell == 0) return NYS_OK;
+  return philox_gaussian(h, m, ell, seed, counter, out);
+}
+
+extern "C" int nys_sketch(nys_handle h, const nys_matrix* A, const double* d, int32_t ell,
+                          uint64_t seed, uint64_t counter, nys_dtype sketch_dtype,
+                          const double* omega, nys_precond* P, double* nu_out) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_sketch"));
+  if (!P || !P->U || !P->lambda) return set_error(h, NYS_EINVAL, "nys_sketch: NULL output");
+  if (P->m != A->m || ell != P->ell || ell < 1 || ell > A->m)
+    return set_error(h, NYS_EINVAL, "nys_sketch: need 1 <= ell <= m and P sized m x ell");
+  if (!d) return set_error(h, NYS_EINVAL, "nys_sketch: NULL d");
+  if (sketch_dtype == NYS_BF16 && A->dtype != NYS_BF16)
+    return set_error(h, NYS_EINVAL, "nys_sketch: a BF16 sketch needs BF16 storage of A");
+  if (sketch_dtype != NYS_BF16 && sketch_dtype != NYS_F64)
+    return set_error(h, NYS_EINVAL, "nys_sketch: sketch dtype must be NYS_F64 or NYS_BF16");
+  NYS_HIP(h, hipSetDevice(h->device));
+  SketchOut so{P->U, P->lambda, 0.0};
+  int rc = sketch_run(h, A, d, ell, seed, counter, sketch_dtype, 1.0, omega, &so);
+  if (rc < 0) return rc;
+  NYS_CHECK(sync(h));
+  if (nu_out) *nu_out = so.nu;
+  return NYS_OK;
+}
+
+extern "C" int nys_precond_apply(nys_handle h, const nys_precond* P, double delta, const double* r,
+                                 double* out) {
+  if (!h) return NYS_EINVAL;
+  if (!P || !r || !out) return set_error(h, NYS_EINVAL, "nys_precond_apply: NULL argument");
+  NYS_CHECK(check_precond(h, P, P->m, "nys_precond_apply"));
+  if (!(delta > 0) || !is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_precond_apply: delta must be > 0");
+  if (r == out) return set_error(h, NYS_EINVAL, "nys_precond_apply: out aliases r");
+  NYS_HIP(h, hipSetDevice(h->device));
+  double* base;
+  NYS_CHECK(ws(h, WS_PCG, (size_t)6 * P->m + P->ell + 8, &base));
+  double* t = base + 6 * P->m;
+  NYS_CHECK(precond_reduce(h, P->U, P->lambda, P->m, P->ell, delta, r, t));
+  return precond_expand(h, P->U, P->m, P->ell, r, t, out, nullptr);
+}
+
+extern "C" int nys_pcg_solve(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                             const nys_precond* P, const double* rhs, double* y,
+                             const nys_pcg_opts* opts, nys_pcg_info* info) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_pcg_solve"));
+  NYS_CHECK(check_precond(h, P, A->m, "nys_pcg_solve"));
+  if (!(delta >= 0) || !is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_pcg_solve: delta must be finite and >= 0");
+  if (P && !(delta > 0)) return set_error(h, NYS_EINVAL, "nys_pcg_solve: the Nystrom preconditioner needs delta > 0");
+  if (A->m > 0 && (!rhs || !y || !d)) return set_error(h, NYS_EINVAL, "nys_pcg_solve: NULL vector");
+  NYS_HIP(h, hipSetDevice(h->device));
+  if (A->m == 0) {
+    if (info) *info = nys_pcg_info{0, NYS_OK, 0.0, 0.0};
+    return NYS_OK;
+  }
+  Precond pc;
+  if (P) pc = Precond{P->U, P->lambda, P->ell};
+  return pcg_run(h, A, d, delta, pc, rhs, y, false, pcg_cfg(opts, A->m), info);
+}
+
+extern "C" int nys_newton_solve(nys_handle h, const nys_matrix* A, const double* q, const double* x,
+                                const double* z, double rho, double delta, const nys_precond* P,
+                                const double* r_d, const double* r_p, const double* r_xz,
+                                const nys_pcg_opts* opts, double* dx, double* dy, double* dz,
+                                nys_pcg_info* info) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_newton_solve"));
+  NYS_CHECK(check_precond(h, P, A->m, "nys_newton_solve"));
+  if (!(delta > 0) || !is_fin(delta) || !(rho >= 0) || !is_fin(rho))
+    return set_error(h, NYS_EINVAL, "nys_newton_solve: need delta > 0, rho >= 0");
+  if (!q || !x || !z || !r_d || !r_p || !r_xz || !dx || !dy || !dz)
+    return set_error(h, NYS_EINVAL, "nys_newton_solve: NULL vector");
+  NYS_HIP(h, hipSetDevice(h->device));
+  double* D;
+  NYS_CHECK(ws(h, WS_IPM, (size_t)A->n + 8, &D));
+  NYS_CHECK(map_reduce<0, 0>(h, A->n, ScalingF{D, q, x, z, rho}, nullptr));
+  Precond pc;
+  if (P) pc = Precond{P->U, P->lambda, P->ell};
+  int rc = newton_run(h, A, x, z, D, delta, pc, r_d, r_p, r_xz, pcg_cfg(opts, A->m), dx, dy, dz, info);
+  if (rc < 0) return rc;
+  NYS_CHECK(sync(h));
+  return rc;
+}
+
+// ipm_solve and ipm_adjoint live in ipm.hip; they reuse the drivers above
+// through these internal entry points.
+namespace nys {
+int ipm_pcg(nys_handle h, const nys_matrix* A, const double* d, double delta, const double* U,
+            const double* lam, int ell, const double* rhs, double* y, const nys_pcg_opts* o,
+            nys_pcg_info* info) {
+  Precond pc{U, lam, U ? ell : 0};
+  return pcg_run(h, A, d, delta, pc, rhs, y, true, pcg_cfg(o, A->m), info);
+}
+int ipm_sketch(nys_handle h, const nys_matrix* A, const double* d, int ell, uint64_t seed,
+               uint64_t counter, nys_dtype mode, double c_nu, double* U, double* lam, double* nu) {
+  SketchOut so{U, lam, 0.0};
+  NYS_CHECK(sketch_run(h, A, d, ell, seed, counter, mode, c_nu, nullptr, &so));
+  if (nu) *nu = so.nu;
+  return NYS_OK;
+}
+int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
+               double delta, const double* U, const double* lam, int ell, const double* rd,
+               const double* rp, const double* rxz, const nys_pcg_opts* o, double mu_abs, double* dx,
+               double* dy, double* dz, nys_pcg_info* info) {
+  Precond pc{U, lam, U ? ell : 0};
+  PcgCfg cfg = pcg_cfg(o, A->m);
+  cfg.rtol = (o && o->rtol > 0) ? o->rtol : 1e-2;
+  cfg.atol = 0.0;
+  cfg.mu_abs = mu_abs;
+  return newton_run(h, A, x, z, D, delta, pc, rd, rp, rxz, cfg, dx, dy, dz, info);
+}
+int grad_A_rank2(nys_handle h, int64_t m, int64_t n, const double* y, const double* u1,
+                 const double* u2, const double* x, double* G) {
+  int64_t nb = std::min<int64_t>(std::max<int64_t>((m * n + NYS_BLOCK - 1) / NYS_BLOCK, 1), 16384);
+  hipLaunchKernelGGL(k_grad_A, dim3((unsigned)nb), dim3(NYS_BLOCK), 0, h->stream, m, n, y, u1, u2, x, G);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+}  // namespace nys

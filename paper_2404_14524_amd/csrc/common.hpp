@@ -1,0 +1,139 @@
+// Device helpers shared by the nysipm kernels (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "nysipm.h"
+
+#define NYS_WAVE 64
+#define NYS_BLOCK 256
+
+namespace nys {
+
+// ------------------------------------------------------------------ storage types
+// Tag types for the three storage formats of the constraint matrix.
+struct F64 { using raw = double;   static constexpr int vec = 2; };   // 16 B = 2 values
+struct F32 { using raw = float;    static constexpr int vec = 4; };   // 16 B = 4 values
+struct BF16 { using raw = uint16_t; static constexpr int vec = 8; };  // 16 B = 8 values
+
+__device__ __forceinline__ double to_f64(double v) { return v; }
+__device__ __forceinline__ double to_f64(float v) { return (double)v; }
+__device__ __forceinline__ double to_f64(uint16_t v) {
+  return (double)__uint_as_float(((uint32_t)v) << 16);
+}
+
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+// Unpack a 16-byte vector into VEC doubles.
+template <class T> struct Unpack;
+template <> struct Unpack<F64> {
+  __device__ __forceinline__ static void run(const u32x4& u, double* o) {
+    o[0] = __hiloint2double((int)u.y, (int)u.x);
+    o[1] = __hiloint2double((int)u.w, (int)u.z);
+  }
+};
+template <> struct Unpack<F32> {
+  __device__ __forceinline__ static void run(const u32x4& u, double* o) {
+    o[0] = (double)__uint_as_float(u.x);
+    o[1] = (double)__uint_as_float(u.y);
+    o[2] = (double)__uint_as_float(u.z);
+    o[3] = (double)__uint_as_float(u.w);
+  }
+};
+template <> struct Unpack<BF16> {
+  __device__ __forceinline__ static void run(const u32x4& u, double* o) {
+    o[0] = (double)__uint_as_float(u.x << 16);
+    o[1] = (double)__uint_as_float(u.x & 0xFFFF0000u);
+    o[2] = (double)__uint_as_float(u.y << 16);
+    o[3] = (double)__uint_as_float(u.y & 0xFFFF0000u);
+    o[4] = (double)__uint_as_float(u.z << 16);
+    o[5] = (double)__uint_as_float(u.z & 0xFFFF0000u);
+    o[6] = (double)__uint_as_float(u.w << 16);
+    o[7] = (double)__uint_as_float(u.w & 0xFFFF0000u);
+  }
+};
+
+// Non-temporal 16-byte load of a streamed operand (A is read once per pass).
+__device__ __forceinline__ u32x4 ld_stream16(const void* p) {
+  return __builtin_nontemporal_load((const u32x4*)p);
+}
+__device__ __forceinline__ u32x4 ld16(const void* p) { return *(const u32x4*)p; }
+
+// ------------------------------------------------------------------ reductions
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, NYS_WAVE);
+  return v;
+}
+__device__ __forceinline__ double wave_min(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v = fmin(v, __shfl_xor(v, off, NYS_WAVE));
+  return v;
+}
+
+// Block-wide sum of K values per thread; result valid in every thread.
+// `smem` needs K * (blockDim/64) doubles.  Fixed order: deterministic.
+template <int K>
+__device__ __forceinline__ void block_sum(double* v, double* smem) {
+  const int lane = threadIdx.x & (NYS_WAVE - 1);
+  const int wid = threadIdx.x / NYS_WAVE;
+  const int nw = blockDim.x / NYS_WAVE;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_sum(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) smem[k * nw + wid] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = 0.0;
+    for (int w = 0; w < nw; ++w) s += smem[k * nw + w];
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+template <int K>
+__device__ __forceinline__ void block_min(double* v, double* smem) {
+  const int lane = threadIdx.x & (NYS_WAVE - 1);
+  const int wid = threadIdx.x / NYS_WAVE;
+  const int nw = blockDim.x / NYS_WAVE;
+#pragma unroll
+  for (int k = 0; k < K; ++k) v[k] = wave_min(v[k]);
+  __syncthreads();
+  if (lane == 0) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) smem[k * nw + wid] = v[k];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    double s = smem[k * nw];
+    for (int w = 1; w < nw; ++w) s = fmin(s, smem[k * nw + w]);
+    v[k] = s;
+  }
+  __syncthreads();
+}
+
+// "Last block done" election for two-stage reductions without a second launch.
+// Every block calls this once after writing its partial results; it returns
+// true in exactly one block (the last to arrive), after which that block may
+// read every other block's partials.  The counter is reset for the next launch.
+__device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned nblocks) {
+  __shared__ bool is_last;
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == nblocks - 1);
+    if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (is_last) __threadfence();
+  return is_last;
+}
+
+}  // namespace nys

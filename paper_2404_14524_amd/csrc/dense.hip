@@ -1,0 +1,463 @@
+// Small and tall-skinny dense FP64 kernels of the Nystrom construction
+// (Algorithm 1): tiled GEMM with split-K, Cholesky, triangular inverse,
+// one-sided Jacobi SVD, the Philox test matrix and BF16 rounding.
+
+#include <cmath>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mapreduce.hpp"
+
+namespace nys {
+namespace {
+
+// ---------------------------------------------------------------- GEMM (VALU FP64)
+constexpr int GBM = 64, GBN = 64, GBK = 16;
+
+template <class TA, bool TRA, bool TRB>
+__global__ __launch_bounds__(NYS_BLOCK) void k_gemm64(int64_t M, int64_t N, int64_t K,
+                                                      const void* Av, int64_t lda, const double* B,
+                                                      int64_t ldb, double* C, int64_t ldc,
+                                                      const double* rs, int64_t klen) {
+  using raw = typename TA::raw;
+  const raw* A = (const raw*)Av;
+  __shared__ double As[GBK][GBM];
+  __shared__ double Bs[GBK][GBN];
+  const int tid = threadIdx.x;
+  const int tx = tid % 16, ty = tid / 16;
+  const int64_t m0 = (int64_t)blockIdx.y * GBM, n0 = (int64_t)blockIdx.x * GBN;
+  const int64_t kb = (int64_t)blockIdx.z * klen;
+  const int64_t ke = min(K, kb + klen);
+  double c[4][4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int j = 0; j < 4; ++j) c[i][j] = 0.0;
+
+  for (int64_t k0 = kb; k0 < ke; k0 += GBK) {
+    // A tile: op(A)[m0 + i][k0 + k]
+    if (!TRA) {
+      const int i = tid / 4, kk = (tid % 4) * 4;
+      const int64_t gi = m0 + i;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gk = k0 + kk + e;
+        As[kk + e][i] = (gi < M && gk < ke) ? to_f64(A[gi * lda + gk]) : 0.0;
+      }
+    } else {
+      const int kk = tid / 16, i = (tid % 16) * 4;
+      const int64_t gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gi = m0 + i + e;
+        As[kk][i + e] = (gi < M && gk < ke) ? to_f64(A[gk * lda + gi]) : 0.0;
+      }
+    }
+    // B tile: op(B)[k0 + k][n0 + j]
+    if (!TRB) {
+      const int kk = tid / 16, j = (tid % 16) * 4;
+      const int64_t gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gj = n0 + j + e;
+        Bs[kk][j + e] = (gj < N && gk < ke) ? B[gk * ldb + gj] : 0.0;
+      }
+    } else {
+      const int j = tid / 4, kk = (tid % 4) * 4;
+      const int64_t gj = n0 + j;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t gk = k0 + kk + e;
+        Bs[kk + e][j] = (gj < N && gk < ke) ? B[gj * ldb + gk] : 0.0;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < GBK; ++k) {
+      double a[4], b[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) a[i] = As[k][ty * 4 + i];
+#pragma unroll
+      for (int j = 0; j < 4; ++j) b[j] = Bs[k][tx * 4 + j];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) c[i][j] = fma(a[i], b[j], c[i][j]);
+    }
+    __syncthreads();
+  }
+  // split-K writes raw partial tiles to C + z * M * ldc (no scaling)
+  double* Cz = C + (int64_t)blockIdx.z * M * ldc;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    const int64_t gi = m0 + ty * 4 + i;
+    if (gi >= M) continue;
+    const double sc = (rs && gridDim.z == 1) ? rs[gi] : 1.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int64_t gj = n0 + tx * 4 + j;
+      if (gj < N) Cz[gi * ldc + gj] = c[i][j] * sc;
+    }
+  }
+}
+
+__global__ __launch_bounds__(NYS_BLOCK) void k_splitk_reduce(int64_t M, int64_t N, int nsplit,
+                                                             const double* part, double* C,
+                                                             int64_t ldc, const double* rs) {
+  const int64_t total = M * N;
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    const int64_t i = idx / N, j = idx % N;
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += part[(int64_t)z * total + idx];
+    C[i * ldc + j] = rs ? s * rs[i] : s;
+  }
+}
+
+template <class TA>
+int gemm_dispatch(nys_handle h, bool ta, bool tb, dim3 g, int64_t M, int64_t N, int64_t K,
+                  const void* A, int64_t lda, const double* B, int64_t ldb, double* C, int64_t ldc,
+                  const double* rs, int64_t klen) {
+  dim3 b(NYS_BLOCK);
+  if (!ta && !tb) hipLaunchKernelGGL((k_gemm64<TA, false, false>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, C, ldc, rs, klen);
+  else if (ta && !tb) hipLaunchKernelGGL((k_gemm64<TA, true, false>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, C, ldc, rs, klen);
+  else if (!ta && tb) hipLaunchKernelGGL((k_gemm64<TA, false, true>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, C, ldc, rs, klen);
+  else hipLaunchKernelGGL((k_gemm64<TA, true, true>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, C, ldc, rs, klen);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+// ---------------------------------------------------------------- Cholesky (one block)
+constexpr int DB = 1024;   // threads of the one-block dense kernels
+
+// G (ell x ell, row-major) -> upper C with C^T C = sym(G) + (shift_abs + shift_rel*trace) I.
+__global__ __launch_bounds__(DB) void k_chol_upper(double* G, int ell, double shift_abs,
+                                                   double shift_rel, double* fail) {
+  __shared__ double piv;
+  __shared__ int bad;
+  __shared__ double red[DB / NYS_WAVE];
+  const int tid = threadIdx.x;
+  // symmetrise into the upper triangle, trace
+  double tr[1] = {0.0};
+  for (int64_t idx = tid; idx < (int64_t)ell * ell; idx += DB) {
+    const int i = (int)(idx / ell), j = (int)(idx % ell);
+    if (i < j) G[idx] = 0.5 * (G[idx] + G[(int64_t)j * ell + i]);
+    if (i == j) tr[0] += G[idx];
+  }
+  block_sum<1>(tr, red);
+  const double shift = shift_abs + shift_rel * tr[0];
+  for (int i = tid; i < ell; i += DB) G[(int64_t)i * ell + i] += shift;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int k = 0; k < ell; ++k) {
+    if (tid == 0) {
+      const double g = G[(int64_t)k * ell + k];
+      if (!(g > 0.0) || !isfinite(g)) {
+        bad = 1;
+        piv = 1.0;
+      } else {
+        piv = sqrt(g);
+      }
+    }
+    __syncthreads();
+    if (bad) break;
+    const double p = piv;
+    for (int j = k + 1 + tid; j < ell; j += DB) G[(int64_t)k * ell + j] /= p;
+    if (tid == 0) G[(int64_t)k * ell + k] = p;
+    __syncthreads();
+    const int r = ell - k - 1;
+    for (int64_t idx = tid; idx < (int64_t)r * r; idx += DB) {
+      const int i = k + 1 + (int)(idx / r), j = k + 1 + (int)(idx % r);
+      if (j >= i) G[(int64_t)i * ell + j] -= G[(int64_t)k * ell + i] * G[(int64_t)k * ell + j];
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < (int64_t)ell * ell; idx += DB) {
+    const int i = (int)(idx / ell), j = (int)(idx % ell);
+    if (i > j) G[idx] = 0.0;
+  }
+  if (tid == 0) *fail = bad ? 1.0 : 0.0;
+}
+
+// Cinv = C^{-1}, C upper triangular: rows of Cinv from the bottom up, each row
+// in parallel over its columns: Cinv[i][j] = -(sum_{k=i+1..j} C[i][k] Cinv[k][j]) / C[i][i].
+__global__ __launch_bounds__(DB) void k_tri_inv_upper(const double* C, double* X, int ell) {
+  const int tid = threadIdx.x;
+  for (int64_t idx = tid; idx < (int64_t)ell * ell; idx += DB) X[idx] = 0.0;
+  __syncthreads();
+  for (int i = ell - 1; i >= 0; --i) {
+    const double cii = C[(int64_t)i * ell + i];
+    for (int j = i + tid; j < ell; j += DB) {
+      if (j == i) {
+        X[(int64_t)i * ell + i] = 1.0 / cii;
+      } else {
+        double s = 0.0;
+        for (int k = i + 1; k <= j; ++k) s = fma(C[(int64_t)i * ell + k], X[(int64_t)k * ell + j], s);
+        X[(int64_t)i * ell + j] = -s / cii;
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- one-sided Jacobi SVD
+// Xc holds the columns contiguously (column k at Xc + k*ell).  One launch per
+// round of the round-robin ordering; one wave per column pair.
+__device__ __forceinline__ int rr_player(int p, int round, int np) {
+  // np players 0..np-1 (np even); player 0 fixed, others rotate
+  return p == 0 ? 0 : 1 + (p - 1 + round) % (np - 1);
+}
+
+__global__ __launch_bounds__(NYS_WAVE) void k_jacobi_round(double* Xc, int ell, int np, int round,
+                                                           double tol, unsigned* rotations) {
+  const int k = blockIdx.x;                 // pair index 0 .. np/2-1
+  const int a = rr_player(k, round, np);
+  const int b = rr_player(np - 1 - k, round, np);
+  int p = min(a, b), q = max(a, b);
+  if (q >= ell) return;                     // pairs with the padding player
+  double* xp = Xc + (int64_t)p * ell;
+  double* xq = Xc + (int64_t)q * ell;
+  const int lane = threadIdx.x;
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = lane; i < ell; i += NYS_WAVE) {
+    const double u = xp[i], v = xq[i];
+    al = fma(u, u, al);
+    be = fma(v, v, be);
+    ga = fma(u, v, ga);
+  }
+  al = wave_sum(al);
+  be = wave_sum(be);
+  ga = wave_sum(ga);
+  if (!(fabs(ga) > tol * sqrt(al * be))) return;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+  for (int i = lane; i < ell; i += NYS_WAVE) {
+    const double u = xp[i], v = xq[i];
+    xp[i] = c * u - s * v;
+    xq[i] = s * u + c * v;
+  }
+  if (lane == 0) atomicAdd(rotations, 1u);
+}
+
+__global__ __launch_bounds__(DB) void k_transpose_sq(const double* X, double* Y, int ell) {
+  for (int64_t idx = (int64_t)blockIdx.x * DB + threadIdx.x; idx < (int64_t)ell * ell;
+       idx += (int64_t)gridDim.x * DB) {
+    const int i = (int)(idx / ell), j = (int)(idx % ell);
+    Y[(int64_t)j * ell + i] = X[idx];
+  }
+}
+
+// Normalise columns, sort by descending norm, write row-major U and sig2.
+__global__ __launch_bounds__(DB) void k_jacobi_finish(const double* Xc, int ell, double* U,
+                                                      double* sig2) {
+  extern __shared__ double nrm[];
+  for (int k = threadIdx.x; k < ell; k += DB) {
+    double s = 0.0;
+    for (int i = 0; i < ell; ++i) s = fma(Xc[(int64_t)k * ell + i], Xc[(int64_t)k * ell + i], s);
+    nrm[k] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < ell; k += DB) {
+    int rank = 0;
+    for (int j = 0; j < ell; ++j)
+      if (nrm[j] > nrm[k] || (nrm[j] == nrm[k] && j < k)) ++rank;
+    const double s2 = nrm[k];
+    const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
+    sig2[rank] = s2;
+    for (int i = 0; i < ell; ++i) U[(int64_t)i * ell + rank] = Xc[(int64_t)k * ell + i] * inv;
+  }
+}
+
+// ---------------------------------------------------------------- Philox4x32-10
+__device__ __forceinline__ void philox10(uint32_t c[4], uint32_t k0, uint32_t k1) {
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    if (r > 0) {
+      k0 += 0x9E3779B9u;
+      k1 += 0xBB67AE85u;
+    }
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c[2];
+    const uint32_t hi0 = (uint32_t)(p0 >> 32), lo0 = (uint32_t)p0;
+    const uint32_t hi1 = (uint32_t)(p1 >> 32), lo1 = (uint32_t)p1;
+    const uint32_t n0 = hi1 ^ c[1] ^ k0, n2 = hi0 ^ c[3] ^ k1;
+    c[0] = n0;
+    c[1] = lo1;
+    c[2] = n2;
+    c[3] = lo0;
+  }
+}
+
+__device__ __forceinline__ double u53(uint32_t a, uint32_t b) {
+  const uint64_t v = ((uint64_t)a << 32) | b;
+  return (double)(v >> 11) * 0x1.0p-53 + 0x1.0p-54;
+}
+
+__global__ __launch_bounds__(NYS_BLOCK) void k_philox_gauss(int64_t count, uint64_t seed,
+                                                            uint64_t counter, double* out) {
+  const int64_t npairs = (count + 1) / 2;
+  for (int64_t pi = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; pi < npairs;
+       pi += (int64_t)gridDim.x * NYS_BLOCK) {
+    uint32_t c[4] = {(uint32_t)pi, (uint32_t)((uint64_t)pi >> 32), (uint32_t)counter,
+                     (uint32_t)(counter >> 32)};
+    philox10(c, (uint32_t)seed, (uint32_t)(seed >> 32));
+    const double u1 = u53(c[0], c[1]), u2 = u53(c[2], c[3]);
+    const double r = sqrt(-2.0 * log(u1));
+    double sn, cs;
+    sincos(2.0 * M_PI * u2, &sn, &cs);
+    const int64_t e = 2 * pi;
+    out[e] = r * cs;
+    if (e + 1 < count) out[e + 1] = r * sn;
+  }
+}
+
+// ---------------------------------------------------------------- BF16 rounding
+__device__ __forceinline__ uint16_t f32_bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+__global__ __launch_bounds__(NYS_BLOCK) void k_to_bf16(const double* x, uint16_t* out, int64_t n) {
+  for (int64_t j = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * NYS_BLOCK)
+    out[j] = f32_bf16_rne((float)x[j]);
+}
+
+__global__ __launch_bounds__(NYS_BLOCK) void k_f32_to_bf16(const float* x, int64_t rows, int64_t cols,
+                                                           int64_t ld, uint16_t* out) {
+  const int64_t total = rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    const int64_t i = idx / cols, j = idx % cols;
+    out[i * cols + j] = f32_bf16_rne(x[i * ld + j]);
+  }
+}
+
+__global__ void k_zero_u32(unsigned* p, int64_t n) {
+  for (int64_t j = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; j < n; j += (int64_t)gridDim.x * NYS_BLOCK) p[j] = 0u;
+}
+
+unsigned grid_for(int64_t n) {
+  int64_t b = (n + NYS_BLOCK - 1) / NYS_BLOCK;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+}  // namespace
+
+int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
+             const void* A, nys_dtype adt, int64_t lda, const double* B, int64_t ldb, double* C,
+             int64_t ldc, const double* row_scale) {
+  if (M == 0 || N == 0) return NYS_OK;
+  const int64_t tiles = ((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
+  int64_t nsplit = 1;
+  if (tiles < 512 && K > 512) {
+    nsplit = std::min<int64_t>((1024 + tiles - 1) / tiles, (K + 255) / 256);
+    nsplit = std::max<int64_t>(1, std::min<int64_t>(nsplit, 256));
+  }
+  int64_t klen = (K + nsplit - 1) / nsplit;
+  klen = std::max<int64_t>(GBK, (klen + GBK - 1) / GBK * GBK);
+  nsplit = std::max<int64_t>(1, (K + klen - 1) / klen);
+  double* out = C;
+  int64_t ldo = ldc;
+  if (nsplit > 1) {
+    NYS_CHECK(ws(h, WS_SK_SPLIT, (size_t)nsplit * M * N, &out));
+    ldo = N;
+  }
+  dim3 g((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), (unsigned)nsplit);
+  const double* rs = nsplit > 1 ? nullptr : row_scale;
+  if (K == 0) {
+    // empty contraction: C = 0
+    dim3 g1((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), 1);
+    NYS_CHECK(gemm_dispatch<F64>(h, transA, transB, g1, M, N, K, A, lda, B, ldb, C, ldc, nullptr, GBK));
+    return NYS_OK;
+  }
+  switch (adt) {
+    case NYS_F64: NYS_CHECK(gemm_dispatch<F64>(h, transA, transB, g, M, N, K, A, lda, B, ldb, out, ldo, rs, klen)); break;
+    case NYS_F32: NYS_CHECK(gemm_dispatch<F32>(h, transA, transB, g, M, N, K, A, lda, B, ldb, out, ldo, rs, klen)); break;
+    default: NYS_CHECK(gemm_dispatch<BF16>(h, transA, transB, g, M, N, K, A, lda, B, ldb, out, ldo, rs, klen)); break;
+  }
+  if (nsplit > 1) {
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(M * N)), dim3(NYS_BLOCK), 0, h->stream, M, N,
+                       (int)nsplit, out, C, ldc, row_scale);
+    NYS_LAUNCH_CHECK(h);
+  }
+  return NYS_OK;
+}
+
+int chol_upper(nys_handle h, double* G, int ell, double shift_abs, double shift_rel, double* fail) {
+  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(DB), 0, h->stream, G, ell, shift_abs, shift_rel, fail);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell) {
+  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(DB), 0, h->stream, C, Cinv, ell);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int small_mm(nys_handle h, const double* C1, const double* C2, double* C3, int ell) {
+  return gemm_f64(h, false, false, ell, ell, ell, C1, NYS_F64, ell, C2, ell, C3, ell, nullptr);
+}
+
+int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
+  // work: ell*ell doubles (column storage) followed by one counter word
+  double* Xc = work;
+  unsigned* rot = reinterpret_cast<unsigned*>(work + (int64_t)ell * ell);
+  hipLaunchKernelGGL(k_transpose_sq, dim3(grid_for((int64_t)ell * ell)), dim3(DB), 0, h->stream, X, Xc, ell);
+  NYS_LAUNCH_CHECK(h);
+  const int np = ell + (ell & 1);
+  const double tol = sqrt((double)ell) * 2.220446049250313e-16;
+  int sweep = 0;
+  const int max_sweeps = 40;
+  if (np >= 2) {
+    for (; sweep < max_sweeps; ++sweep) {
+      NYS_CHECK(zero_u32(h, rot, 1));
+      for (int round = 0; round < np - 1; ++round) {
+        hipLaunchKernelGGL(k_jacobi_round, dim3(np / 2), dim3(NYS_WAVE), 0, h->stream, Xc, ell, np,
+                           round, tol, rot);
+      }
+      NYS_LAUNCH_CHECK(h);
+      unsigned hrot = 0;
+      NYS_HIP(h, hipMemcpyAsync(&hrot, rot, sizeof(unsigned), hipMemcpyDeviceToHost, h->stream));
+      NYS_HIP(h, hipStreamSynchronize(h->stream));
+      if (hrot == 0) break;
+    }
+  }
+  hipLaunchKernelGGL(k_jacobi_finish, dim3(1), dim3(DB), (size_t)ell * sizeof(double), h->stream, Xc,
+                     ell, X, sig2);
+  NYS_LAUNCH_CHECK(h);
+  if (sweep == max_sweeps) return set_error(h, NYS_ENOTPD, "Jacobi SVD did not converge in %d sweeps", max_sweeps);
+  return NYS_OK;
+}
+
+int zero_u32(nys_handle h, unsigned* p, int64_t count) {
+  hipLaunchKernelGGL(k_zero_u32, dim3(grid_for(count)), dim3(NYS_BLOCK), 0, h->stream, p, count);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int philox_gaussian(nys_handle h, int64_t m, int ell, uint64_t seed, uint64_t counter, double* out) {
+  const int64_t count = m * ell;
+  hipLaunchKernelGGL(k_philox_gauss, dim3(grid_for((count + 1) / 2)), dim3(NYS_BLOCK), 0, h->stream,
+                     count, seed, counter, out);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int to_bf16(nys_handle h, const double* x, uint16_t* out, int64_t count) {
+  hipLaunchKernelGGL(k_to_bf16, dim3(grid_for(count)), dim3(NYS_BLOCK), 0, h->stream, x, out, count);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int f32_to_bf16(nys_handle h, const float* x, int64_t rows, int64_t cols, int64_t ld, uint16_t* out) {
+  hipLaunchKernelGGL(k_f32_to_bf16, dim3(grid_for(rows * cols)), dim3(NYS_BLOCK), 0, h->stream, x, rows,
+                     cols, ld, out);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+}  // namespace nys

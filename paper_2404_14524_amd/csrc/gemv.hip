@@ -1,0 +1,364 @@
+// The fused two-pass normal-equation operator v -> A diag(d) A^T v + delta v
+// (eq. normal-eq).  Both passes stream A from HBM once with 16-byte
+// non-temporal loads and accumulate in FP64 whatever the storage of A.
+//
+// Pass 1 (w = d .* A^T v): a 2-D grid of (column tile) x (row chunk) blocks.
+//   Thread t of a block owns VEC consecutive columns (16 bytes of a row) and
+//   walks the rows of its chunk, four rows in flight; v_i is a wave-uniform
+//   value.  Partial column sums go to a workspace array; the last block of a
+//   column tile to finish (arrival counter) sums the chunks in a fixed order,
+//   so the result is deterministic and no second launch is needed.
+// Pass 2 (out = A w + delta v): each block owns RB consecutive rows; every
+//   16-byte piece of w it loads is reused for RB rows.  Row sums are finished
+//   by wave shuffles and LDS.  An optional p^T (M p) dot product is fused in
+//   the same way as pass 1's second stage.
+
+#include "common.hpp"
+#include "kernels.hpp"
+
+namespace nys {
+namespace {
+
+struct T1Args {
+  const double* skip;
+  const char* A;
+  int64_t m, n, row_bytes;
+  const double* v;
+  const double* s;
+  const double* pold;
+  double* pnew;
+  const double* beta;
+  const double* d;
+  const double* x0;
+  double sA;
+  double* w;
+  double* part;
+  unsigned* cnt;
+  int rows_per_chunk;
+  int nchunks;
+};
+
+template <class T, bool FUSEDP, bool VECLOAD>
+__global__ __launch_bounds__(NYS_BLOCK) void k_gemv_t(T1Args a) {
+  using raw = typename T::raw;
+  constexpr int VEC = T::vec;
+  if (a.skip && *a.skip != 0.0) return;
+  const int64_t col0 = ((int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x) * VEC;
+  const int64_t r0 = (int64_t)blockIdx.y * a.rows_per_chunk;
+  const int64_t r1 = min(a.m, r0 + (int64_t)a.rows_per_chunk);
+  const double beta = FUSEDP ? *a.beta : 0.0;
+  auto rowv = [&](int64_t i) -> double {
+    if constexpr (FUSEDP) return a.s[i] + beta * a.pold[i];
+    else return a.v[i];
+  };
+  double acc[VEC];
+#pragma unroll
+  for (int e = 0; e < VEC; ++e) acc[e] = 0.0;
+
+  if (VECLOAD && col0 + VEC <= a.n) {
+    const char* p = a.A + r0 * a.row_bytes + col0 * (int64_t)sizeof(raw);
+    int64_t i = r0;
+    for (; i + 4 <= r1; i += 4) {
+      const u32x4 u0 = ld_stream16(p);
+      const u32x4 u1 = ld_stream16(p + a.row_bytes);
+      const u32x4 u2 = ld_stream16(p + 2 * a.row_bytes);
+      const u32x4 u3 = ld_stream16(p + 3 * a.row_bytes);
+      const double v0 = rowv(i), v1 = rowv(i + 1), v2 = rowv(i + 2), v3 = rowv(i + 3);
+      double e0[VEC], e1[VEC], e2[VEC], e3[VEC];
+      Unpack<T>::run(u0, e0);
+      Unpack<T>::run(u1, e1);
+      Unpack<T>::run(u2, e2);
+      Unpack<T>::run(u3, e3);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        acc[e] = fma(e0[e], v0, acc[e]);
+        acc[e] = fma(e1[e], v1, acc[e]);
+        acc[e] = fma(e2[e], v2, acc[e]);
+        acc[e] = fma(e3[e], v3, acc[e]);
+      }
+      p += 4 * a.row_bytes;
+    }
+    for (; i < r1; ++i) {
+      const u32x4 u0 = ld_stream16(p);
+      double e0[VEC];
+      Unpack<T>::run(u0, e0);
+      const double v0 = rowv(i);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) acc[e] = fma(e0[e], v0, acc[e]);
+      p += a.row_bytes;
+    }
+  } else if (col0 < a.n) {
+    for (int64_t i = r0; i < r1; ++i) {
+      const raw* row = (const raw*)(a.A + i * a.row_bytes);
+      const double v0 = rowv(i);
+#pragma unroll
+      for (int e = 0; e < VEC; ++e)
+        if (col0 + e < a.n) acc[e] = fma(to_f64(row[col0 + e]), v0, acc[e]);
+    }
+  }
+
+  if constexpr (FUSEDP) {
+    if (blockIdx.x == 0)
+      for (int64_t i = r0 + threadIdx.x; i < r1; i += NYS_BLOCK) a.pnew[i] = a.s[i] + beta * a.pold[i];
+  }
+
+  auto finish = [&](int64_t j, double sum) {
+    double val = a.sA * sum + (a.x0 ? a.x0[j] : 0.0);
+    if (a.d) val *= a.d[j];
+    a.w[j] = val;
+  };
+
+  if (a.nchunks == 1) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e)
+      if (col0 + e < a.n) finish(col0 + e, acc[e]);
+    return;
+  }
+  double* mypart = a.part + (int64_t)blockIdx.y * a.n;
+#pragma unroll
+  for (int e = 0; e < VEC; ++e)
+    if (col0 + e < a.n) mypart[col0 + e] = acc[e];
+  if (last_block_arrives(a.cnt + blockIdx.x, a.nchunks)) {
+#pragma unroll
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t j = col0 + e;
+      if (j < a.n) {
+        double s = 0.0;
+        for (int c = 0; c < a.nchunks; ++c) s += __builtin_nontemporal_load(a.part + (int64_t)c * a.n + j);
+        finish(j, s);
+      }
+    }
+  }
+}
+
+struct T2Args {
+  const double* skip;
+  const char* A;
+  int64_t m, n, row_bytes;
+  const double* w;
+  const double* v;
+  const double* x0;
+  double sA, sV;
+  double* out;
+  double* dot_out;
+  double* dpart;
+  unsigned* cnt;
+};
+
+template <class T, int RB, bool VECLOAD>
+__global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
+  using raw = typename T::raw;
+  constexpr int VEC = T::vec;
+  __shared__ double smem[RB * (NYS_BLOCK / NYS_WAVE) + NYS_BLOCK / NYS_WAVE];
+  if (a.skip && *a.skip != 0.0) return;
+  const int64_t i0 = (int64_t)blockIdx.x * RB;
+  int nr = (int)min((int64_t)RB, a.m - i0);
+  double acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+
+  int64_t jtail = 0;
+  if (VECLOAD) {
+    const int64_t nv = a.n / VEC;   // full 16-byte pieces per row
+    const char* base = a.A + i0 * a.row_bytes;
+    for (int64_t jv = threadIdx.x; jv < nv; jv += NYS_BLOCK) {
+      const int64_t j = jv * VEC;
+      double wv[VEC];
+#pragma unroll
+      for (int e = 0; e < VEC; e += 2) {
+        const u32x4 u = ld16(a.w + j + e);
+        wv[e] = __hiloint2double((int)u.y, (int)u.x);
+        wv[e + 1] = __hiloint2double((int)u.w, (int)u.z);
+      }
+      u32x4 u[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < nr) u[r] = ld_stream16(base + r * a.row_bytes + j * (int64_t)sizeof(raw));
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (r < nr) {
+          double e[VEC];
+          Unpack<T>::run(u[r], e);
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) acc[r] = fma(e[k], wv[k], acc[r]);
+        }
+      }
+    }
+    jtail = nv * VEC;
+  }
+  for (int64_t j = jtail + threadIdx.x; j < a.n; j += NYS_BLOCK) {
+    const double wj = a.w[j];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < nr) acc[r] = fma(to_f64(((const raw*)(a.A + (i0 + r) * a.row_bytes))[j]), wj, acc[r]);
+  }
+  block_sum<RB>(acc, smem);
+  double dotc = 0.0;
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (r < nr) {
+        const int64_t i = i0 + r;
+        const double vi = a.v ? a.v[i] : 0.0;
+        const double o = a.sA * acc[r] + a.sV * vi + (a.x0 ? a.x0[i] : 0.0);
+        a.out[i] = o;
+        dotc += o * vi;
+      }
+    }
+  }
+  if (!a.dot_out) return;
+  if (threadIdx.x == 0) a.dpart[blockIdx.x] = dotc;
+  if (last_block_arrives(a.cnt, gridDim.x)) {
+    double s[1] = {0.0};
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += NYS_BLOCK) s[0] += a.dpart[b];
+    block_sum<1>(s, smem);
+    if (threadIdx.x == 0) *a.dot_out = s[0];
+  }
+}
+
+int elem_size(nys_dtype dt) { return dt == NYS_F64 ? 8 : dt == NYS_F32 ? 4 : 2; }
+
+bool vec_ok(const nys_matrix* A) {
+  const int es = elem_size(A->dtype);
+  return ((uintptr_t)A->data % 16 == 0) && ((A->ld * es) % 16 == 0);
+}
+
+template <class T, bool FUSEDP, bool VECLOAD>
+void launch_t(dim3 g, T1Args& k, hipStream_t st) {
+  hipLaunchKernelGGL((k_gemv_t<T, FUSEDP, VECLOAD>), g, dim3(NYS_BLOCK), 0, st, k);
+}
+
+template <class T>
+void dispatch_t(dim3 g, T1Args& k, bool fused, bool vecload, hipStream_t st) {
+  if (fused) {
+    if (vecload) launch_t<T, true, true>(g, k, st);
+    else launch_t<T, true, false>(g, k, st);
+  } else {
+    if (vecload) launch_t<T, false, true>(g, k, st);
+    else launch_t<T, false, false>(g, k, st);
+  }
+}
+
+template <class T, int RB>
+void launch_n_rb(T2Args& k, bool vecload, hipStream_t st) {
+  dim3 g((unsigned)((k.m + RB - 1) / RB));
+  if (vecload) hipLaunchKernelGGL((k_gemv_n<T, RB, true>), g, dim3(NYS_BLOCK), 0, st, k);
+  else hipLaunchKernelGGL((k_gemv_n<T, RB, false>), g, dim3(NYS_BLOCK), 0, st, k);
+}
+
+template <class T>
+void dispatch_n(T2Args& k, bool vecload, hipStream_t st) {
+  const int64_t m = k.m;
+  if (m >= 8 * 1536) launch_n_rb<T, 8>(k, vecload, st);
+  else if (m >= 4 * 1024) launch_n_rb<T, 4>(k, vecload, st);
+  else if (m >= 2 * 1024) launch_n_rb<T, 2>(k, vecload, st);
+  else launch_n_rb<T, 1>(k, vecload, st);
+}
+
+int n_blocks_pass2(int64_t m) {
+  const int rb = m >= 8 * 1536 ? 8 : m >= 4 * 1024 ? 4 : m >= 2 * 1024 ? 2 : 1;
+  return (int)((m + rb - 1) / rb);
+}
+
+}  // namespace
+
+int gemv_t(nys_handle h, const GemvT& a) {
+  const nys_matrix* A = a.A;
+  const int es = elem_size(A->dtype);
+  const int vec = 16 / es;
+  const int64_t ncol = (A->n + (int64_t)NYS_BLOCK * vec - 1) / ((int64_t)NYS_BLOCK * vec);
+  // enough blocks to cover the chip several times, rows per chunk >= 32
+  int64_t nch = std::max<int64_t>(1, std::min<int64_t>((A->m + 31) / 32, (2048 + ncol - 1) / ncol));
+  int64_t rpc = (A->m + nch - 1) / nch;
+  rpc = std::max<int64_t>(4, (rpc + 3) / 4 * 4);
+  nch = std::max<int64_t>(1, (A->m + rpc - 1) / rpc);
+  T1Args k{};
+  k.skip = a.skip;
+  k.A = (const char*)A->data;
+  k.m = A->m;
+  k.n = A->n;
+  k.row_bytes = A->ld * es;
+  k.v = a.v;
+  k.s = a.s;
+  k.pold = a.pold;
+  k.pnew = a.pnew;
+  k.beta = a.beta;
+  k.d = a.d;
+  k.x0 = a.x0;
+  k.sA = a.sA;
+  k.w = a.w;
+  k.rows_per_chunk = (int)rpc;
+  k.nchunks = (int)nch;
+  if (nch > 1) {
+    NYS_CHECK(ws(h, WS_PART, (size_t)nch * A->n, &k.part));
+    if ((size_t)ncol > h->ncounters)
+      return set_error(h, NYS_EINVAL, "gemv_t: %lld column tiles exceed the counter array", (long long)ncol);
+    k.cnt = h->counters;
+  }
+  if (A->n == 0) return NYS_OK;
+  dim3 g((unsigned)ncol, (unsigned)nch);
+  const bool fused = a.s != nullptr;
+  const bool vl = vec_ok(A);
+  switch (A->dtype) {
+    case NYS_F64: dispatch_t<F64>(g, k, fused, vl, h->stream); break;
+    case NYS_F32: dispatch_t<F32>(g, k, fused, vl, h->stream); break;
+    case NYS_BF16: dispatch_t<BF16>(g, k, fused, vl, h->stream); break;
+    default: return set_error(h, NYS_EINVAL, "gemv_t: bad dtype");
+  }
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int gemv_n(nys_handle h, const GemvN& a) {
+  const nys_matrix* A = a.A;
+  if (A->m == 0) return NYS_OK;
+  const int es = elem_size(A->dtype);
+  T2Args k{};
+  k.skip = a.skip;
+  k.A = (const char*)A->data;
+  k.m = A->m;
+  k.n = A->n;
+  k.row_bytes = A->ld * es;
+  k.w = a.w;
+  k.v = a.v;
+  k.x0 = a.x0;
+  k.sA = a.sA;
+  k.sV = a.sV;
+  k.out = a.out;
+  k.dot_out = a.dot_out;
+  if (a.dot_out) {
+    NYS_CHECK(ws(h, WS_PART2, (size_t)n_blocks_pass2(A->m), &k.dpart));
+    k.cnt = h->counters;
+  }
+  const bool vl = vec_ok(A) && ((uintptr_t)a.w % 16 == 0);
+  switch (A->dtype) {
+    case NYS_F64: dispatch_n<F64>(k, vl, h->stream); break;
+    case NYS_F32: dispatch_n<F32>(k, vl, h->stream); break;
+    case NYS_BF16: dispatch_n<BF16>(k, vl, h->stream); break;
+    default: return set_error(h, NYS_EINVAL, "gemv_n: bad dtype");
+  }
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                 const double* v, double* out, double* dot_out) {
+  double* w;
+  NYS_CHECK(ws(h, WS_W, (size_t)std::max<int64_t>(A->n, 1), &w));
+  GemvT t;
+  t.A = A;
+  t.v = v;
+  t.d = d;
+  t.w = w;
+  NYS_CHECK(gemv_t(h, t));
+  GemvN nn;
+  nn.A = A;
+  nn.w = w;
+  nn.v = v;
+  nn.sV = delta;
+  nn.out = out;
+  nn.dot_out = dot_out;
+  return gemv_n(h, nn);
+}
+
+}  // namespace nys

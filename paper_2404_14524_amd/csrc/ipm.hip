@@ -1,0 +1,558 @@
+// Nys-IP-PMM for (P) with non-negative variables (Algorithm 4 with the
+// Mehrotra predictor-corrector of Algorithm 6 and the Newton solve of
+// Algorithm 5), and the adjoint of the converged KKT system.
+//
+// Readings where the paper is silent or defers to the original IP-PMM:
+// * initial point: the supplement's construction with F = J = empty; the
+//   regularised systems (A A^T + 10 I) are solved by Nystrom-PCG; the dual
+//   centring shift uses (x~ + delta_p); non-positive entries left after the
+//   shifts (possible only when the product gamma is zero) are set to 1.
+// * parameter update: zeta <- x, lambda <- y every iteration and
+//   rho = delta = max(5e-10, min(rho, mu)).
+// * stopping test: max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
+// * inner tolerance: ||xi - M dy|| <= max(1e-12 ||xi||, min(1e-2 ||xi||, 0.1 mu))
+//   on the true residual (the theory asks for a residual of order mu).
+// * a fresh test matrix per iteration (Philox key = seed, counter = k), shared
+//   by predictor and corrector.
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mapreduce.hpp"
+
+namespace nys {
+int ipm_pcg(nys_handle h, const nys_matrix* A, const double* d, double delta, const double* U,
+            const double* lam, int ell, const double* rhs, double* y, const nys_pcg_opts* o,
+            nys_pcg_info* info);
+int ipm_sketch(nys_handle h, const nys_matrix* A, const double* d, int ell, uint64_t seed,
+               uint64_t counter, nys_dtype mode, double c_nu, double* U, double* lam, double* nu);
+int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
+               double delta, const double* U, const double* lam, int ell, const double* rd,
+               const double* rp, const double* rxz, const nys_pcg_opts* o, double mu_abs, double* dx,
+               double* dy, double* dz, nys_pcg_info* info);
+int grad_A_rank2(nys_handle h, int64_t m, int64_t n, const double* y, const double* u1,
+                 const double* u2, const double* x, double* G);
+
+namespace {
+
+constexpr double STEP = 0.995;
+constexpr double REG0 = 8.0;
+constexpr double REG_FLOOR = 5e-10;
+constexpr double INIT_REG = 10.0;
+constexpr uint64_t CTR_INIT = 0xFFFFFFFFFFFFFFFFull;
+constexpr uint64_t CTR_ADJ = 0xFFFFFFFFFFFFFFFEull;
+
+using clk = std::chrono::steady_clock;
+double ms_since(clk::time_point t0) {
+  return std::chrono::duration<double, std::milli>(clk::now() - t0).count();
+}
+
+// ---------------------------------------------------------------- element-wise steps
+struct ResidD {       // r_d = c + Q x - A^T y - z ; ||r_d||^2, x^T z, #non-finite
+  double* rd;
+  const double *c, *q, *x, *aty, *z;
+  __device__ void operator()(int64_t j, double* s, double*) const {
+    const double v = c[j] + q[j] * x[j] - aty[j] - z[j];
+    rd[j] = v;
+    s[0] = fma(v, v, s[0]);
+    s[1] = fma(x[j], z[j], s[1]);
+    if (!isfinite(x[j]) || !isfinite(z[j])) s[2] += 1.0;
+  }
+};
+struct Scaling {      // D = (Q + Z X^{-1} + rho I)^{-1}
+  double* D;
+  const double *q, *x, *z;
+  double rho;
+  __device__ void operator()(int64_t j, double*, double*) const { D[j] = 1.0 / (q[j] + z[j] / x[j] + rho); }
+};
+struct PredN {        // R_d = r_d + rho (x - zeta), R_xz = -X Z 1
+  double *Rd, *Rxz;
+  const double *rd, *x, *zeta, *z;
+  double rho;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    Rd[j] = rd[j] + rho * (x[j] - zeta[j]);
+    Rxz[j] = -x[j] * z[j];
+  }
+};
+struct PredM {        // R_p = r_p - delta (y - lambda)
+  double* Rp;
+  const double *rp, *y, *lam;
+  double delta;
+  __device__ void operator()(int64_t j, double*, double*) const { Rp[j] = rp[j] - delta * (y[j] - lam[j]); }
+};
+struct Ratio {        // min over dx<0 of -x/dx, and over dz<0 of -z/dz
+  const double *x, *dx, *z, *dz;
+  __device__ void operator()(int64_t j, double*, double* mn) const {
+    if (dx[j] < 0.0) mn[0] = fmin(mn[0], -x[j] / dx[j]);
+    if (dz[j] < 0.0) mn[1] = fmin(mn[1], -z[j] / dz[j]);
+  }
+};
+struct MuAff {        // (x + ap dx)^T (z + ad dz)
+  const double *x, *dx, *z, *dz;
+  double ap, ad;
+  __device__ void operator()(int64_t j, double* s, double*) const {
+    s[0] = fma(fma(ap, dx[j], x[j]), fma(ad, dz[j], z[j]), s[0]);
+  }
+};
+struct CorrRxz {      // R_xz = mu~ 1 - dxp .* dzp
+  double* R;
+  const double *dxp, *dzp;
+  double mut;
+  __device__ void operator()(int64_t j, double*, double*) const { R[j] = mut - dxp[j] * dzp[j]; }
+};
+struct AddTo {        // a += b
+  double* a;
+  const double* b;
+  __device__ void operator()(int64_t j, double*, double*) const { a[j] += b[j]; }
+};
+struct UpdXZ {        // x += ap dx, z += ad dz, zeta = x ; x^T z, #non-finite
+  double *x, *z, *zeta;
+  const double *dx, *dz;
+  double ap, ad;
+  __device__ void operator()(int64_t j, double* s, double*) const {
+    const double xn = fma(ap, dx[j], x[j]), zn = fma(ad, dz[j], z[j]);
+    x[j] = xn;
+    z[j] = zn;
+    zeta[j] = xn;
+    s[0] = fma(xn, zn, s[0]);
+    if (!isfinite(xn) || !isfinite(zn)) s[1] += 1.0;
+  }
+};
+struct UpdY {         // y += ad dy, lambda = y ; #non-finite
+  double *y, *lam;
+  const double* dy;
+  double ad;
+  __device__ void operator()(int64_t j, double* s, double*) const {
+    const double yn = fma(ad, dy[j], y[j]);
+    y[j] = yn;
+    lam[j] = yn;
+    if (!isfinite(yn)) s[0] += 1.0;
+  }
+};
+struct CPlusQX {      // t = c + Q x
+  double* t;
+  const double *c, *q, *x;
+  __device__ void operator()(int64_t j, double*, double*) const { t[j] = c[j] + q[j] * x[j]; }
+};
+struct MinXZ {
+  const double *x, *z;
+  __device__ void operator()(int64_t j, double*, double* mn) const {
+    mn[0] = fmin(mn[0], x[j]);
+    mn[1] = fmin(mn[1], z[j]);
+  }
+};
+struct InitSums {     // (x+dp)^T (z+dd), sum(z+dd), sum(x+dp)
+  const double *x, *z;
+  double dp, dd;
+  __device__ void operator()(int64_t j, double* s, double*) const {
+    const double a = x[j] + dp, b = z[j] + dd;
+    s[0] = fma(a, b, s[0]);
+    s[1] += b;
+    s[2] += a;
+  }
+};
+struct InitShift {
+  double *x, *z, *zeta;
+  double sp, sd;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    double xn = x[j] + sp, zn = z[j] + sd;
+    if (!(xn > 0.0)) xn = 1.0;
+    if (!(zn > 0.0)) zn = 1.0;
+    x[j] = xn;
+    z[j] = zn;
+    zeta[j] = xn;
+  }
+};
+struct AdjD {         // D_adj = 0 where x <= z, else (q + z/x + rho)^{-1}; tn = D g
+  double *D, *tn;
+  const double *q, *x, *z, *g;
+  double rho;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    const double d = x[j] > z[j] ? 1.0 / (q[j] + z[j] / x[j] + rho) : 0.0;
+    D[j] = d;
+    tn[j] = d * g[j];
+  }
+};
+struct AdjOut {       // grad_c = -u1, grad_q = -u1 x
+  double *gc, *gq;
+  const double *u1, *x;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    if (gc) gc[j] = -u1[j];
+    if (gq) gq[j] = -u1[j] * x[j];
+  }
+};
+
+int check_qp(nys_handle h, const nys_qp* qp, const char* who) {
+  if (!qp || !qp->A || !qp->b || !qp->c || !qp->q) return set_error(h, NYS_EINVAL, "%s: NULL problem data", who);
+  const nys_matrix* A = qp->A;
+  if (A->m < 1 || A->n < 1 || A->ld < A->n || !A->data)
+    return set_error(h, NYS_EINVAL, "%s: bad A (m=%lld n=%lld)", who, (long long)A->m, (long long)A->n);
+  if (A->dtype != NYS_F64 && A->dtype != NYS_F32)
+    return set_error(h, NYS_EINVAL, "%s: A must be FP64 or FP32 storage", who);
+  if (qp->A_lo) {
+    const nys_matrix* L = qp->A_lo;
+    if (L->m != A->m || L->n != A->n || L->ld < L->n || L->dtype != NYS_BF16 || !L->data)
+      return set_error(h, NYS_EINVAL, "%s: A_lo must be a BF16 matrix of A's shape", who);
+  }
+  return NYS_OK;
+}
+
+// BF16 storage for the matrix-core sketch: the caller's copy, or one made here.
+int lo_matrix(nys_handle h, const nys_qp* qp, nys_matrix* out) {
+  if (qp->A_lo) {
+    *out = *qp->A_lo;
+    return NYS_OK;
+  }
+  const nys_matrix* A = qp->A;
+  uint16_t* lo;
+  NYS_CHECK(ws(h, WS_ALO, (size_t)A->m * A->n, &lo));
+  if (A->dtype == NYS_F32) {
+    NYS_CHECK(f32_to_bf16(h, (const float*)A->data, A->m, A->n, A->ld, lo));
+  } else {
+    for (int64_t i = 0; i < A->m; ++i)
+      NYS_CHECK(to_bf16(h, (const double*)A->data + i * A->ld, lo + i * A->n, A->n));
+  }
+  *out = nys_matrix{A->m, A->n, A->n, NYS_BF16, lo};
+  return NYS_OK;
+}
+
+struct Opts {
+  double tol = 1e-6;
+  int max_iter = 100;
+  int ell = 0;
+  uint64_t seed = 0;
+  nys_dtype sk = NYS_F64;
+  double c_nu = 1.0;
+  nys_pcg_opts pcg{};
+  int verbose = 0;
+};
+
+Opts read_opts(const nys_ipm_opts* o) {
+  Opts r;
+  if (!o) return r;
+  if (o->tol > 0) r.tol = o->tol;
+  if (o->max_iter > 0) r.max_iter = o->max_iter;
+  r.ell = o->ell;
+  r.seed = o->seed;
+  r.sk = o->sketch_dtype;
+  if (o->c_nu > 0) r.c_nu = o->c_nu;
+  r.pcg = o->pcg;
+  r.verbose = o->verbose;
+  return r;
+}
+
+
+}  // namespace
+}  // namespace nys
+
+using namespace nys;
+
+extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in, double* x,
+                         double* y, double* z, nys_ipm_info* info) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_qp(h, qp, "ipm_solve"));
+  if (!x || !y || !z) return set_error(h, NYS_EINVAL, "ipm_solve: NULL output");
+  Opts o = read_opts(opts_in);
+  const nys_matrix* A = qp->A;
+  const int64_t m = A->m, n = A->n;
+  if (o.ell < 1 || o.ell > m) return set_error(h, NYS_EINVAL, "ipm_solve: ell must be in [1, m]");
+  if (o.sk != NYS_F64 && o.sk != NYS_BF16) return set_error(h, NYS_EINVAL, "ipm_solve: bad sketch dtype");
+  if (o.sk == NYS_F64 && A->dtype != NYS_F64 && A->dtype != NYS_F32) return set_error(h, NYS_EINVAL, "ipm_solve: bad A");
+  NYS_HIP(h, hipSetDevice(h->device));
+  const auto t_start = clk::now();
+  h->t_sketch = h->t_pcg = h->t_other = 0.0;
+  double* sc = h->dscal;
+
+  // ---- data validation: NaN/Inf anywhere, q < 0
+  NYS_CHECK(count_nonfinite_matrix(h, A, sc + SC_RED0));
+  NYS_CHECK(count_bad(h, qp->b, m, sc + SC_RED0 + 1));
+  NYS_CHECK(count_bad(h, qp->c, n, sc + SC_RED0 + 3));
+  NYS_CHECK(count_bad(h, qp->q, n, sc + SC_RED0 + 5));
+  NYS_CHECK(read_scalars(h, SC_RED0, 7));
+  {
+    const double* hs = h->hscal + SC_RED0;
+    if (hs[0] + hs[1] + hs[3] + hs[5] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: non-finite problem data");
+    if (hs[6] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: q has negative entries");
+  }
+
+  // ---- workspace
+  double* base;
+  NYS_CHECK(ws(h, WS_IPM, (size_t)12 * n + 8 * m + 64, &base));
+  double* D = base;
+  double* zeta = base + n;
+  double* aty = base + 2 * n;
+  double* rd = base + 3 * n;
+  double* Rd = base + 4 * n;
+  double* Rxz = base + 5 * n;
+  double* dxp = base + 6 * n;
+  double* dzp = base + 7 * n;
+  double* dxc = base + 8 * n;
+  double* dzc = base + 9 * n;
+  double* tn = base + 10 * n;
+  double* ones = base + 11 * n;
+  double* mb = base + 12 * n;
+  double* lam = mb;
+  double* rp = mb + m;
+  double* Rp = mb + 2 * m;
+  double* dyp = mb + 3 * m;
+  double* dyc = mb + 4 * m;
+  double* rhs = mb + 5 * m;
+  double* tm = mb + 6 * m;
+  double *U, *lamh;
+  NYS_CHECK(ws(h, WS_PCU, (size_t)m * o.ell, &U));
+  NYS_CHECK(ws(h, WS_PCL, (size_t)o.ell + 8, &lamh));
+  nys_matrix Alo{};
+  const nys_matrix* Ask = A;
+  if (o.sk == NYS_BF16) {
+    NYS_CHECK(lo_matrix(h, qp, &Alo));
+    Ask = &Alo;
+  }
+  int pcg_total = 0;
+
+  auto timed_sketch = [&](const double* d, uint64_t ctr) -> int {
+    const auto t0 = clk::now();
+    double nu = 0;
+    NYS_CHECK(ipm_sketch(h, Ask, d, o.ell, o.seed, ctr, o.sk, o.c_nu, U, lamh, &nu));
+    NYS_CHECK(sync(h));
+    h->t_sketch += ms_since(t0);
+    return NYS_OK;
+  };
+
+  // ---- norms of b, c
+  NYS_CHECK(dot(h, qp->b, qp->b, m, sc + SC_RED0));
+  NYS_CHECK(dot(h, qp->c, qp->c, n, sc + SC_RED0 + 1));
+  NYS_CHECK(read_scalars(h, SC_RED0, 2));
+  const double bnorm = std::sqrt(h->hscal[SC_RED0]), cnorm = std::sqrt(h->hscal[SC_RED0 + 1]);
+
+  // ---- initial point
+  {
+    NYS_CHECK(fill(h, ones, n, 1.0));
+    NYS_CHECK(timed_sketch(ones, CTR_INIT));
+    nys_pcg_opts ip = o.pcg;
+    ip.rtol = 1e-10;
+    ip.atol = 0.0;
+    nys_pcg_info pi{};
+    auto t0 = clk::now();
+    int rc = ipm_pcg(h, A, ones, INIT_REG, U, lamh, o.ell, qp->b, tm, &ip, &pi);
+    h->t_pcg += ms_since(t0);
+    if (rc < 0) return rc;
+    pcg_total += pi.iters;
+    GemvT g1;
+    g1.A = A;
+    g1.v = tm;
+    g1.w = x;
+    NYS_CHECK(gemv_t(h, g1));                                          // x~ = A^T t
+    NYS_CHECK(map_reduce<0, 0>(h, n, CPlusQX{tn, qp->c, qp->q, x}, nullptr));
+    GemvN g2;
+    g2.A = A;
+    g2.w = tn;
+    g2.out = rhs;
+    NYS_CHECK(gemv_n(h, g2));                                          // A (c + Q x~)
+    t0 = clk::now();
+    rc = ipm_pcg(h, A, ones, INIT_REG, U, lamh, o.ell, rhs, y, &ip, &pi);
+    h->t_pcg += ms_since(t0);
+    if (rc < 0) return rc;
+    pcg_total += pi.iters;
+    GemvT g3;
+    g3.A = A;
+    g3.v = y;
+    g3.sA = -1.0;
+    g3.x0 = tn;
+    g3.w = z;
+    NYS_CHECK(gemv_t(h, g3));                                          // z~ = c + Q x~ - A^T y~
+    NYS_CHECK((map_reduce<0, 2>(h, n, MinXZ{x, z}, sc + SC_RED0)));
+    NYS_CHECK(read_scalars(h, SC_RED0, 2));
+    const double dp = std::max(-1.5 * h->hscal[SC_RED0], 0.0);
+    const double dd = std::max(-1.5 * h->hscal[SC_RED0 + 1], 0.0);
+    NYS_CHECK((map_reduce<3, 0>(h, n, InitSums{x, z, dp, dd}, sc + SC_RED0)));
+    NYS_CHECK(read_scalars(h, SC_RED0, 3));
+    const double gamma = h->hscal[SC_RED0];
+    const double sz = h->hscal[SC_RED0 + 1], sx = h->hscal[SC_RED0 + 2];
+    const double sp = dp + (sz != 0 ? 0.5 * gamma / sz : 0.0);
+    const double sd = dd + (sx != 0 ? 0.5 * gamma / sx : 0.0);
+    NYS_CHECK(map_reduce<0, 0>(h, n, InitShift{x, z, zeta, sp, sd}, nullptr));
+    NYS_CHECK(copy(h, lam, y, m));
+  }
+
+  double rho = REG0, delta = REG0;
+  nys_ipm_info inf{};
+  int status = NYS_MAXIT;
+  int k = 0;
+  for (k = 0;; ++k) {
+    // residuals and stopping test
+    GemvT ga;
+    ga.A = A;
+    ga.v = y;
+    ga.w = aty;
+    NYS_CHECK(gemv_t(h, ga));
+    GemvN gp;
+    gp.A = A;
+    gp.w = x;
+    gp.sA = -1.0;
+    gp.x0 = qp->b;
+    gp.out = rp;
+    NYS_CHECK(gemv_n(h, gp));                                          // r_p = b - A x
+    NYS_CHECK((map_reduce<3, 0>(h, n, ResidD{rd, qp->c, qp->q, x, aty, z}, sc + SC_RED0)));
+    NYS_CHECK(dot(h, rp, rp, m, sc + SC_RED0 + 3));
+    NYS_CHECK(read_scalars(h, SC_RED0, 4));
+    const double* hs = h->hscal + SC_RED0;
+    if (hs[2] > 0) {
+      status = set_error(h, NYS_ENUMERIC, "ipm_solve: non-finite iterate at iteration %d", k);
+      break;
+    }
+    const double mu = hs[1] / n;
+    const double rp_rel = std::sqrt(hs[3]) / (1.0 + bnorm);
+    const double rd_rel = std::sqrt(hs[0]) / (1.0 + cnorm);
+    const double kkt = std::max(std::max(rp_rel, rd_rel), mu);
+    inf.kkt_rel = kkt;
+    inf.rp_rel = rp_rel;
+    inf.rd_rel = rd_rel;
+    inf.mu = mu;
+    if (o.verbose)
+      std::fprintf(stderr, "[nysipm] k=%d rp=%.2e rd=%.2e mu=%.2e rho=%.2e pcg_total=%d t=%.1fms\n", k,
+                   rp_rel, rd_rel, mu, rho, pcg_total, ms_since(t_start));
+    if (kkt <= o.tol) {
+      status = NYS_OK;
+      break;
+    }
+    if (k >= o.max_iter) break;
+
+    NYS_CHECK(map_reduce<0, 0>(h, n, Scaling{D, qp->q, x, z, rho}, nullptr));
+    NYS_CHECK(timed_sketch(D, (uint64_t)k));
+
+    // predictor
+    NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho}, nullptr));
+    NYS_CHECK(map_reduce<0, 0>(h, m, PredM{Rp, rp, y, lam, delta}, nullptr));
+    // inner tolerance: max(1e-12 ||xi||, min(cap ||xi||, 0.1 mu)), cap = pcg.rtol or 1e-2
+    nys_pcg_info pi{};
+    auto t0 = clk::now();
+    int rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, Rd, Rp, Rxz, &o.pcg, 0.1 * mu, dxp, dyp,
+                        dzp, &pi);
+    h->t_pcg += ms_since(t0);
+    if (rc < 0) {
+      status = rc;
+      break;
+    }
+    pcg_total += pi.iters;
+    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp}, sc + SC_RED0)));
+    NYS_CHECK(read_scalars(h, SC_RED0, 2));
+    double ap = STEP * std::min(1.0, h->hscal[SC_RED0]);
+    double ad = STEP * std::min(1.0, h->hscal[SC_RED0 + 1]);
+    NYS_CHECK((map_reduce<1, 0>(h, n, MuAff{x, dxp, z, dzp, ap, ad}, sc + SC_RED0)));
+    NYS_CHECK(read_scalars(h, SC_RED0, 1));
+    const double mu_aff = h->hscal[SC_RED0] / n;
+    const double mut = mu_aff * mu_aff * mu_aff / (mu * mu);
+
+    // corrector
+    NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut}, nullptr));
+    t0 = clk::now();
+    rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, nullptr, nullptr, Rxz, &o.pcg, 0.1 * mu, dxc,
+                    dyc, dzc, &pi);
+    h->t_pcg += ms_since(t0);
+    if (rc < 0) {
+      status = rc;
+      break;
+    }
+    pcg_total += pi.iters;
+    NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dxp, dxc}, nullptr));
+    NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dzp, dzc}, nullptr));
+    NYS_CHECK(map_reduce<0, 0>(h, m, AddTo{dyp, dyc}, nullptr));
+    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp}, sc + SC_RED0)));
+    NYS_CHECK(read_scalars(h, SC_RED0, 2));
+    ap = STEP * std::min(1.0, h->hscal[SC_RED0]);
+    ad = STEP * std::min(1.0, h->hscal[SC_RED0 + 1]);
+    NYS_CHECK((map_reduce<2, 0>(h, n, UpdXZ{x, z, zeta, dxp, dzp, ap, ad}, sc + SC_RED0)));
+    NYS_CHECK((map_reduce<1, 0>(h, m, UpdY{y, lam, dyp, ad}, sc + SC_RED0 + 2)));
+    NYS_CHECK(read_scalars(h, SC_RED0, 3));
+    if (h->hscal[SC_RED0 + 1] + h->hscal[SC_RED0 + 2] > 0) {
+      status = set_error(h, NYS_ENUMERIC, "ipm_solve: non-finite iterate at iteration %d", k);
+      break;
+    }
+    const double mu_new = h->hscal[SC_RED0] / n;
+    rho = delta = std::max(REG_FLOOR, std::min(rho, mu_new));
+  }
+  NYS_CHECK(sync(h));
+  const double total = ms_since(t_start);
+  h->t_other = std::max(0.0, total - h->t_sketch - h->t_pcg);
+  inf.iters = k;
+  inf.pcg_iters_total = pcg_total;
+  inf.status = status;
+  inf.rho = rho;
+  inf.delta = delta;
+  inf.t_sketch_ms = h->t_sketch;
+  inf.t_pcg_ms = h->t_pcg;
+  inf.t_other_ms = h->t_other;
+  if (info) *info = inf;
+  if (status == NYS_MAXIT)
+    set_error(h, NYS_MAXIT, "ipm_solve: %d iterations without reaching tol (KKT %.3e)", k, inf.kkt_rel);
+  return status;
+}
+
+extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in, const double* x,
+                           const double* y, const double* z, double rho, double delta, const double* g,
+                           double* grad_c, double* grad_b, double* grad_q, double* grad_A,
+                           nys_pcg_info* info) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_qp(h, qp, "ipm_adjoint"));
+  if (!x || !y || !z || !g) return set_error(h, NYS_EINVAL, "ipm_adjoint: NULL input");
+  if (!(delta > 0) || !std::isfinite(delta) || !(rho >= 0) || !std::isfinite(rho))
+    return set_error(h, NYS_EINVAL, "ipm_adjoint: need delta > 0 and rho >= 0");
+  Opts o = read_opts(opts_in);
+  const nys_matrix* A = qp->A;
+  const int64_t m = A->m, n = A->n;
+  if (o.ell < 1 || o.ell > m) return set_error(h, NYS_EINVAL, "ipm_adjoint: ell must be in [1, m]");
+  NYS_HIP(h, hipSetDevice(h->device));
+  const auto t_start = clk::now();
+  h->t_sketch = h->t_pcg = h->t_other = 0.0;
+  double* base;
+  NYS_CHECK(ws(h, WS_IPM, (size_t)12 * n + 8 * m + 64, &base));
+  double* D = base;
+  double* tn = base + n;
+  double* u1 = base + 2 * n;
+  double* rhs = base + 12 * n;
+  double* u2 = rhs + m;
+  double *U, *lamh;
+  NYS_CHECK(ws(h, WS_PCU, (size_t)m * o.ell, &U));
+  NYS_CHECK(ws(h, WS_PCL, (size_t)o.ell + 8, &lamh));
+  nys_matrix Alo{};
+  const nys_matrix* Ask = A;
+  if (o.sk == NYS_BF16) {
+    NYS_CHECK(lo_matrix(h, qp, &Alo));
+    Ask = &Alo;
+  }
+  NYS_CHECK(map_reduce<0, 0>(h, n, AdjD{D, tn, qp->q, x, z, g, rho}, nullptr));
+  GemvN g2;
+  g2.A = A;
+  g2.w = tn;
+  g2.out = rhs;
+  NYS_CHECK(gemv_n(h, g2));                                            // A D g
+  auto t0 = clk::now();
+  double nu = 0;
+  NYS_CHECK(ipm_sketch(h, Ask, D, o.ell, o.seed, CTR_ADJ, o.sk, o.c_nu, U, lamh, &nu));
+  NYS_CHECK(sync(h));
+  h->t_sketch += ms_since(t0);
+  nys_pcg_opts po = o.pcg;
+  if (!(po.rtol > 0)) po.rtol = 1e-10;
+  t0 = clk::now();
+  int rc = ipm_pcg(h, A, D, delta, U, lamh, o.ell, rhs, u2, &po, info);
+  h->t_pcg += ms_since(t0);
+  if (rc < 0) return rc;
+  GemvT g1;
+  g1.A = A;
+  g1.v = u2;
+  g1.sA = -1.0;
+  g1.x0 = g;
+  g1.d = D;
+  g1.w = u1;
+  NYS_CHECK(gemv_t(h, g1));                                            // u1 = D (g - A^T u2)
+  if (grad_c || grad_q) NYS_CHECK(map_reduce<0, 0>(h, n, AdjOut{grad_c, grad_q, u1, x}, nullptr));
+  if (grad_b) NYS_CHECK(copy(h, grad_b, u2, m));
+  if (grad_A) NYS_CHECK(grad_A_rank2(h, m, n, y, u1, u2, x, grad_A));
+  NYS_CHECK(sync(h));
+  h->t_other = std::max(0.0, ms_since(t_start) - h->t_sketch - h->t_pcg);
+  return rc;
+}

@@ -1,0 +1,366 @@
+// Vector kernels: BLAS-1 helpers, data validation, the Nystrom
+// preconditioner apply (eq. Nys_precond_inv) and the fused PCG updates.
+
+#include <cmath>
+
+#include "common.hpp"
+#include "kernels.hpp"
+#include "mapreduce.hpp"
+
+namespace nys {
+namespace {
+
+struct FillF {
+  double* x;
+  double v;
+  __device__ void operator()(int64_t j, double*, double*) const { x[j] = v; }
+};
+struct CopyF {
+  double* d;
+  const double* s;
+  __device__ void operator()(int64_t j, double*, double*) const { d[j] = s[j]; }
+};
+struct AxpbyF {
+  double* d;
+  double a, b;
+  const double* x;
+  const double* y;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    d[j] = a * x[j] + (y ? b * y[j] : 0.0);
+  }
+};
+struct DotF {
+  const double* x;
+  const double* y;
+  __device__ void operator()(int64_t j, double* s, double*) const { s[0] = fma(x[j], y[j], s[0]); }
+};
+struct SumsqF {
+  const double* x;
+  __device__ void operator()(int64_t j, double* s, double*) const { s[0] = fma(x[j], x[j], s[0]); }
+};
+struct BadF {
+  const double* x;
+  __device__ void operator()(int64_t j, double* s, double*) const {
+    const double v = x[j];
+    if (!isfinite(v)) s[0] += 1.0;
+    if (v < 0.0) s[1] += 1.0;
+  }
+};
+
+template <class T>
+__global__ __launch_bounds__(NYS_BLOCK) void k_nonfinite(const char* A, int64_t m, int64_t n,
+                                                         int64_t row_bytes, double* part,
+                                                         unsigned* cnt, double* out) {
+  using raw = typename T::raw;
+  __shared__ double smem[NYS_BLOCK / NYS_WAVE];
+  double c[1] = {0.0};
+  for (int64_t i = blockIdx.x; i < m; i += gridDim.x) {
+    const raw* row = (const raw*)(A + i * row_bytes);
+    for (int64_t j = threadIdx.x; j < n; j += NYS_BLOCK)
+      if (!isfinite(to_f64(row[j]))) c[0] += 1.0;
+  }
+  block_sum<1>(c, smem);
+  if (threadIdx.x == 0) part[blockIdx.x] = c[0];
+  if (last_block_arrives(cnt, gridDim.x)) {
+    double s[1] = {0.0};
+    for (unsigned b = threadIdx.x; b < gridDim.x; b += NYS_BLOCK) s[0] += part[b];
+    block_sum<1>(s, smem);
+    if (threadIdx.x == 0) *out = s[0];
+  }
+}
+
+// ---------------------------------------------------------------- PCG / P^{-1}
+// Rows per block of the update/reduce kernel (one row per thread in phase 1).
+constexpr int RBU = NYS_BLOCK;
+
+struct UpdArgs {
+  int64_t m;
+  int ell;
+  double* y;            // UPDATE: y += alpha p
+  double* r;            // UPDATE: r -= alpha q (else read only)
+  const double* p;
+  const double* q;
+  const double* U;      // PRECOND: m x ell
+  const double* lam;
+  double delta;
+  double* t;            // PRECOND: ell-vector result
+  double* scal;         // device scalar block
+  double* part;
+  unsigned* cnt;
+};
+
+// UPDATE:  alpha = rs/pq (0 once done; breakdown if pq <= 0 or not finite);
+//          y += alpha p; r -= alpha q.
+// PRECOND: t = f .* (U^T r), f_k = (lam_l + delta)/(lam_k + delta) - 1.
+// !PRECOND (plain CG, UPDATE only): rs_new = ||r||^2, beta = rs_new/rs.
+// Always: ||r||^2 -> scal[SC_RR]; done when ||r||^2 <= tol2.
+template <bool UPDATE, bool PRECOND>
+__global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update(UpdArgs a) {
+  __shared__ double rl[RBU];
+  __shared__ double smem[NYS_BLOCK / NYS_WAVE];
+  const int64_t r0 = (int64_t)blockIdx.x * RBU;
+  const int nr = (int)min((int64_t)RBU, a.m - r0);
+  double alpha = 0.0;
+  bool done0 = false, brk = false;
+  if constexpr (UPDATE) {
+    done0 = a.scal[SC_DONE] != 0.0;
+    const double pq = a.scal[SC_PQ], rs = a.scal[SC_RS];
+    if (!done0) {
+      const double al = rs / pq;
+      if (!(pq > 0.0) || !isfinite(al)) brk = true;
+      else alpha = al;
+    }
+  }
+  double rr[1] = {0.0};
+  if (threadIdx.x < nr) {
+    const int64_t i = r0 + threadIdx.x;
+    double ri = a.r[i];
+    if constexpr (UPDATE) {
+      if (alpha != 0.0) {
+        a.y[i] = fma(alpha, a.p[i], a.y[i]);
+        ri = fma(-alpha, a.q[i], ri);
+        a.r[i] = ri;
+      }
+    }
+    rl[threadIdx.x] = ri;
+    rr[0] = ri * ri;
+  }
+  __syncthreads();
+  block_sum<1>(rr, smem);
+  const int ell = PRECOND ? a.ell : 0;
+  if constexpr (PRECOND) {
+    for (int k = threadIdx.x; k < ell; k += NYS_BLOCK) {
+      double acc = 0.0;
+      const double* u = a.U + r0 * ell + k;
+      for (int i = 0; i < nr; ++i) acc = fma(u[(int64_t)i * ell], rl[i], acc);
+      a.part[(int64_t)blockIdx.x * (ell + 1) + k] = acc;
+    }
+  }
+  if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * (ell + 1) + ell] = rr[0];
+  if (!last_block_arrives(a.cnt, gridDim.x)) return;
+  // ---- last block: finish the reductions and the scalar recurrences
+  const int nb = gridDim.x;
+  if constexpr (PRECOND) {
+    __shared__ double laml;
+    if (threadIdx.x == 0) {
+      double mn = a.lam[0];
+      for (int k = 1; k < ell; ++k) mn = fmin(mn, a.lam[k]);
+      laml = mn;
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < ell; k += NYS_BLOCK) {
+      double s = 0.0;
+      for (int b = 0; b < nb; ++b) s += a.part[(int64_t)b * (ell + 1) + k];
+      const double f = (laml + a.delta) / (a.lam[k] + a.delta) - 1.0;
+      a.t[k] = f * s;
+    }
+  }
+  double s1[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += NYS_BLOCK) s1[0] += a.part[(int64_t)b * (ell + 1) + ell];
+  block_sum<1>(s1, smem);
+  if (threadIdx.x == 0) {
+    const double rrt = s1[0];
+    a.scal[SC_RR] = rrt;
+    if constexpr (UPDATE) {
+      if (!done0) a.scal[SC_ITERS] += 1.0;
+      if (brk) {
+        a.scal[SC_BREAK] = 1.0;
+        a.scal[SC_DONE] = 1.0;
+      } else if (!done0 && rrt <= a.scal[SC_TOL2]) {
+        a.scal[SC_DONE] = 1.0;
+      }
+      if constexpr (!PRECOND) {
+        const bool dn = a.scal[SC_DONE] != 0.0;
+        const double rs = a.scal[SC_RS];
+        a.scal[SC_BETA] = dn ? 0.0 : rrt / rs;
+        a.scal[SC_RS] = rrt;
+      }
+    }
+  }
+}
+
+struct ExpArgs {
+  int64_t m;
+  int ell;
+  const double* U;
+  const double* r;
+  const double* t;
+  double* out;
+  double* scal;         // PCG: rs_new, beta (else NULL)
+  double* dot_out;      // standalone dot (may be NULL)
+  double* part;
+  unsigned* cnt;
+};
+
+// out_i = r_i + sum_k U[i,k] t_k (one wave per row); fused r^T out.
+__global__ __launch_bounds__(NYS_BLOCK) void k_precond_expand(ExpArgs a) {
+  extern __shared__ double tl[];
+  __shared__ double smem[NYS_BLOCK / NYS_WAVE];
+  for (int k = threadIdx.x; k < a.ell; k += NYS_BLOCK) tl[k] = a.t[k];
+  __syncthreads();
+  const int lane = threadIdx.x & (NYS_WAVE - 1);
+  const int wid = threadIdx.x / NYS_WAVE;
+  const int64_t wstride = (int64_t)gridDim.x * (NYS_BLOCK / NYS_WAVE);
+  double dotc[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * (NYS_BLOCK / NYS_WAVE) + wid; i < a.m; i += wstride) {
+    const double* u = a.U + i * a.ell;
+    double acc = 0.0;
+    for (int k = lane; k < a.ell; k += NYS_WAVE) acc = fma(u[k], tl[k], acc);
+    acc = wave_sum(acc);
+    if (lane == 0) {
+      const double ri = a.r[i];
+      const double o = ri + acc;
+      a.out[i] = o;
+      dotc[0] = fma(ri, o, dotc[0]);
+    }
+  }
+  if (!a.scal && !a.dot_out) return;
+  block_sum<1>(dotc, smem);
+  if (threadIdx.x == 0) a.part[blockIdx.x] = dotc[0];
+  if (!last_block_arrives(a.cnt, gridDim.x)) return;
+  double s[1] = {0.0};
+  for (unsigned b = threadIdx.x; b < gridDim.x; b += NYS_BLOCK) s[0] += a.part[b];
+  block_sum<1>(s, smem);
+  if (threadIdx.x == 0) {
+    if (a.dot_out) *a.dot_out = s[0];
+    if (a.scal) {
+      const bool dn = a.scal[SC_DONE] != 0.0;
+      const double rs = a.scal[SC_RS];
+      a.scal[SC_BETA] = dn ? 0.0 : s[0] / rs;
+      a.scal[SC_RS] = s[0];
+    }
+  }
+}
+
+unsigned expand_blocks(int64_t m) {
+  int64_t b = (m + (NYS_BLOCK / NYS_WAVE) - 1) / (NYS_BLOCK / NYS_WAVE);
+  if (b > 2048) b = 2048;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+int launch_update(nys_handle h, bool update, bool precond, UpdArgs& k) {
+  const unsigned nb = (unsigned)std::max<int64_t>(1, (k.m + RBU - 1) / RBU);
+  NYS_CHECK(ws(h, WS_PART, (size_t)nb * ((precond ? k.ell : 0) + 1), &k.part));
+  k.cnt = h->counters;
+  k.scal = h->dscal;
+  dim3 g(nb), b(NYS_BLOCK);
+  if (update && precond) hipLaunchKernelGGL((k_pcg_update<true, true>), g, b, 0, h->stream, k);
+  else if (update) hipLaunchKernelGGL((k_pcg_update<true, false>), g, b, 0, h->stream, k);
+  else if (precond) hipLaunchKernelGGL((k_pcg_update<false, true>), g, b, 0, h->stream, k);
+  else hipLaunchKernelGGL((k_pcg_update<false, false>), g, b, 0, h->stream, k);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int launch_expand(nys_handle h, ExpArgs& k) {
+  const unsigned nb = expand_blocks(k.m);
+  NYS_CHECK(ws(h, WS_PART, (size_t)nb, &k.part));
+  k.cnt = h->counters;
+  hipLaunchKernelGGL(k_precond_expand, dim3(nb), dim3(NYS_BLOCK), (size_t)k.ell * sizeof(double),
+                     h->stream, k);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+}  // namespace
+
+int fill(nys_handle h, double* x, int64_t n, double value) {
+  return map_reduce<0, 0>(h, n, FillF{x, value}, nullptr);
+}
+int copy(nys_handle h, double* dst, const double* src, int64_t n) {
+  return map_reduce<0, 0>(h, n, CopyF{dst, src}, nullptr);
+}
+int axpby(nys_handle h, double* dst, double a, const double* x, double b, const double* y, int64_t n) {
+  return map_reduce<0, 0>(h, n, AxpbyF{dst, a, b, x, y}, nullptr);
+}
+int dot(nys_handle h, const double* x, const double* y, int64_t n, double* out) {
+  return map_reduce<1, 0>(h, n, DotF{x, y}, out);
+}
+int sumsq(nys_handle h, const double* x, int64_t count, double* out) {
+  return map_reduce<1, 0>(h, count, SumsqF{x}, out);
+}
+int count_bad(nys_handle h, const double* x, int64_t n, double* out) {
+  return map_reduce<2, 0>(h, n, BadF{x}, out);
+}
+
+int count_nonfinite_matrix(nys_handle h, const nys_matrix* A, double* out) {
+  const int es = A->dtype == NYS_F64 ? 8 : A->dtype == NYS_F32 ? 4 : 2;
+  unsigned nb = (unsigned)std::min<int64_t>(std::max<int64_t>(A->m, 1), 4096);
+  double* part;
+  NYS_CHECK(ws(h, WS_PART2, nb, &part));
+  const char* p = (const char*)A->data;
+  const int64_t rb = A->ld * es;
+  switch (A->dtype) {
+    case NYS_F64: hipLaunchKernelGGL(k_nonfinite<F64>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part, h->counters, out); break;
+    case NYS_F32: hipLaunchKernelGGL(k_nonfinite<F32>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part, h->counters, out); break;
+    default: hipLaunchKernelGGL(k_nonfinite<BF16>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part, h->counters, out); break;
+  }
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int precond_reduce(nys_handle h, const double* U, const double* lam, int64_t m, int ell,
+                   double delta, const double* r, double* t) {
+  UpdArgs k{};
+  k.m = m;
+  k.ell = ell;
+  k.r = const_cast<double*>(r);
+  k.U = U;
+  k.lam = lam;
+  k.delta = delta;
+  k.t = t;
+  return launch_update(h, false, true, k);
+}
+
+int precond_expand(nys_handle h, const double* U, int64_t m, int ell, const double* r,
+                   const double* t, double* out, double* dot_out) {
+  ExpArgs k{};
+  k.m = m;
+  k.ell = ell;
+  k.U = U;
+  k.r = r;
+  k.t = t;
+  k.out = out;
+  k.dot_out = dot_out;
+  return launch_expand(h, k);
+}
+
+int pcg_update(nys_handle h, int64_t m, double* y, double* r, const double* p, const double* q,
+               const double* U, const double* lam, int ell, double delta, double* t) {
+  UpdArgs k{};
+  k.m = m;
+  k.ell = ell;
+  k.y = y;
+  k.r = r;
+  k.p = p;
+  k.q = q;
+  k.U = U;
+  k.lam = lam;
+  k.delta = delta;
+  k.t = t;
+  return launch_update(h, true, U != nullptr, k);
+}
+
+int pcg_expand(nys_handle h, int64_t m, const double* U, int ell, const double* r,
+               const double* t, double* s) {
+  ExpArgs k{};
+  k.m = m;
+  k.ell = ell;
+  k.U = U;
+  k.r = r;
+  k.t = t;
+  k.out = s;
+  k.scal = h->dscal;
+  return launch_expand(h, k);
+}
+
+// ||r||^2 and, without a preconditioner, rs = ||r||^2 (start of a solve).
+int residual_norm(nys_handle h, int64_t m, double* r) {
+  UpdArgs k{};
+  k.m = m;
+  k.r = r;
+  return launch_update(h, false, false, k);
+}
+
+}  // namespace nys

@@ -1,0 +1,332 @@
+"""Python binding of libnysipm (include/nysipm.h): argument marshalling only.
+
+Every function here has the name of the C entry point it calls and does no
+arithmetic of its own: torch supplies device memory and the current HIP
+stream, the library's kernels compute.  There is no CPU fallback: if the
+library is not built, or no GPU is visible, the calls raise.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+import threading
+from dataclasses import dataclass
+from typing import Optional
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libnysipm.so")
+
+NYS_OK, NYS_MAXIT = 0, 1
+NYS_EINVAL, NYS_ENOMEM, NYS_EHIP, NYS_ENOTPD, NYS_EBREAKDOWN, NYS_ENUMERIC = -1, -2, -3, -4, -5, -6
+NYS_F64, NYS_F32, NYS_BF16 = 0, 1, 2
+_DT = {torch.float64: NYS_F64, torch.float32: NYS_F32, torch.bfloat16: NYS_BF16}
+_SK = {"f64": NYS_F64, "bf16": NYS_BF16, NYS_F64: NYS_F64, NYS_BF16: NYS_BF16}
+
+
+class NysError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"nysipm error {code}: {msg}")
+        self.code = code
+
+
+class nys_matrix(C.Structure):
+    _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("ld", C.c_int64), ("dtype", C.c_int),
+                ("data", C.c_void_p)]
+
+
+class nys_precond(C.Structure):
+    _fields_ = [("m", C.c_int64), ("ell", C.c_int32), ("U", C.c_void_p), ("lambda_", C.c_void_p)]
+
+
+class nys_pcg_opts(C.Structure):
+    _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("maxit", C.c_int32),
+                ("replace_every", C.c_int32), ("poll_every", C.c_int32)]
+
+
+class nys_pcg_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("status", C.c_int32), ("true_res", C.c_double),
+                ("rel_res", C.c_double)]
+
+
+class nys_qp(C.Structure):
+    _fields_ = [("A", C.POINTER(nys_matrix)), ("A_lo", C.POINTER(nys_matrix)), ("b", C.c_void_p),
+                ("c", C.c_void_p), ("q", C.c_void_p)]
+
+
+class nys_ipm_opts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ell", C.c_int32),
+                ("seed", C.c_uint64), ("sketch_dtype", C.c_int), ("c_nu", C.c_double),
+                ("pcg", nys_pcg_opts), ("verbose", C.c_int32)]
+
+
+class nys_ipm_info(C.Structure):
+    _fields_ = [("iters", C.c_int32), ("pcg_iters_total", C.c_int32), ("status", C.c_int32),
+                ("kkt_rel", C.c_double), ("rp_rel", C.c_double), ("rd_rel", C.c_double),
+                ("mu", C.c_double), ("rho", C.c_double), ("delta", C.c_double),
+                ("t_sketch_ms", C.c_double), ("t_pcg_ms", C.c_double), ("t_other_ms", C.c_double)]
+
+
+EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
+           "nys_normal_apply", "nys_test_matrix", "nys_sketch", "nys_precond_apply",
+           "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint"]
+
+_lib = None
+_lock = threading.Lock()
+_handles: dict = {}
+
+
+def load_library(path: str = LIB_PATH) -> C.CDLL:
+    """Load libnysipm.so (no GPU needed) and declare the signatures."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_2404_14524_amd.build` "
+                              "or __graft_entry__.build(); there is no CPU fallback")
+        lib = C.CDLL(path)
+        vp, i64, i32, u64, dbl = C.c_void_p, C.c_int64, C.c_int32, C.c_uint64, C.c_double
+        pm = C.POINTER(nys_matrix)
+        sig = {
+            "nys_create": [C.POINTER(vp), C.c_int, vp],
+            "nys_destroy": [vp],
+            "nys_set_stream": [vp, vp],
+            "nys_last_timing": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)],
+            "nys_normal_apply": [vp, pm, vp, dbl, vp, vp],
+            "nys_test_matrix": [vp, i64, i32, u64, u64, vp],
+            "nys_sketch": [vp, pm, vp, i32, u64, u64, C.c_int, vp, C.POINTER(nys_precond), C.POINTER(dbl)],
+            "nys_precond_apply": [vp, C.POINTER(nys_precond), dbl, vp, vp],
+            "nys_pcg_solve": [vp, pm, vp, dbl, C.POINTER(nys_precond), vp, vp, C.POINTER(nys_pcg_opts),
+                              C.POINTER(nys_pcg_info)],
+            "nys_newton_solve": [vp, pm, vp, vp, vp, dbl, dbl, C.POINTER(nys_precond), vp, vp, vp,
+                                 C.POINTER(nys_pcg_opts), vp, vp, vp, C.POINTER(nys_pcg_info)],
+            "ipm_solve": [vp, C.POINTER(nys_qp), C.POINTER(nys_ipm_opts), vp, vp, vp,
+                          C.POINTER(nys_ipm_info)],
+            "ipm_adjoint": [vp, C.POINTER(nys_qp), C.POINTER(nys_ipm_opts), vp, vp, vp, dbl, dbl, vp,
+                            vp, vp, vp, vp, C.POINTER(nys_pcg_info)],
+        }
+        for name, args in sig.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = C.c_int
+        lib.nys_last_error.argtypes = [vp]
+        lib.nys_last_error.restype = C.c_char_p
+        _lib = lib
+        return lib
+
+
+def _handle(device: torch.device):
+    lib = load_library()
+    if not torch.cuda.is_available():
+        raise RuntimeError("nysipm needs a HIP GPU; none is visible (no CPU fallback)")
+    idx = device.index if device.index is not None else torch.cuda.current_device()
+    h = _handles.get(idx)
+    if h is None:
+        h = C.c_void_p()
+        rc = lib.nys_create(C.byref(h), idx, None)
+        if rc != 0:
+            raise NysError(rc, f"nys_create failed on device {idx}")
+        _handles[idx] = h
+    stream = torch.cuda.current_stream(idx).cuda_stream
+    lib.nys_set_stream(h, C.c_void_p(stream))
+    return lib, h
+
+
+def _check(lib, h, rc: int, allow=(NYS_OK, NYS_MAXIT)):
+    if rc not in allow:
+        raise NysError(rc, lib.nys_last_error(h).decode())
+    return rc
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _vec(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
+    if t.dtype != torch.float64 or t.device != device or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous float64 tensor of {n} elements on {device}")
+    return t
+
+
+def _mat(A: torch.Tensor) -> nys_matrix:
+    if A.dim() != 2 or A.dtype not in _DT or not A.is_cuda or A.stride(1) != 1:
+        raise ValueError("A: need a 2-D row-major float64/float32/bfloat16 CUDA tensor")
+    return nys_matrix(A.shape[0], A.shape[1], max(A.stride(0), A.shape[1], 1), _DT[A.dtype],
+                      A.data_ptr())
+
+
+@dataclass
+class Precond:
+    U: torch.Tensor        # m x ell float64, orthonormal columns
+    lam: torch.Tensor      # ell float64, descending
+    nu: float = 0.0
+
+    def c(self) -> nys_precond:
+        return nys_precond(self.U.shape[0], self.U.shape[1], self.U.data_ptr(), self.lam.data_ptr())
+
+
+def _pcg_opts(rtol=1e-10, atol=0.0, maxit=0, replace_every=0, poll_every=0) -> nys_pcg_opts:
+    return nys_pcg_opts(rtol, atol, maxit, replace_every, poll_every)
+
+
+def nys_normal_apply(A: torch.Tensor, d: torch.Tensor, delta: float, v: torch.Tensor,
+                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    _vec(d, n, "d", A.device)
+    _vec(v, m, "v", A.device)
+    out = torch.empty(m, dtype=torch.float64, device=A.device) if out is None else _vec(out, m, "out", A.device)
+    Am = _mat(A)
+    _check(lib, h, lib.nys_normal_apply(h, C.byref(Am), _ptr(d), float(delta), _ptr(v), _ptr(out)))
+    return out
+
+
+def nys_test_matrix(m: int, ell: int, seed: int, counter: int, device="cuda") -> torch.Tensor:
+    device = torch.device(device)
+    lib, h = _handle(device)
+    out = torch.empty((m, ell), dtype=torch.float64, device=device)
+    _check(lib, h, lib.nys_test_matrix(h, m, ell, seed, counter, _ptr(out)))
+    return out
+
+
+def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,
+               sketch_dtype="f64", omega: Optional[torch.Tensor] = None) -> Precond:
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    _vec(d, n, "d", A.device)
+    if omega is not None:
+        _vec(omega.reshape(-1), m * ell, "omega", A.device)
+    U = torch.empty((m, ell), dtype=torch.float64, device=A.device)
+    lam = torch.empty(ell, dtype=torch.float64, device=A.device)
+    P = nys_precond(m, ell, U.data_ptr(), lam.data_ptr())
+    nu = C.c_double(0.0)
+    Am = _mat(A)
+    _check(lib, h, lib.nys_sketch(h, C.byref(Am), _ptr(d), ell, seed, counter, _SK[sketch_dtype],
+                                  _ptr(omega), C.byref(P), C.byref(nu)))
+    return Precond(U, lam, nu.value)
+
+
+def nys_precond_apply(P: Precond, delta: float, r: torch.Tensor,
+                      out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    lib, h = _handle(r.device)
+    m = P.U.shape[0]
+    _vec(r, m, "r", r.device)
+    out = torch.empty_like(r) if out is None else _vec(out, m, "out", r.device)
+    Pc = P.c()
+    _check(lib, h, lib.nys_precond_apply(h, C.byref(Pc), float(delta), _ptr(r), _ptr(out)))
+    return out
+
+
+def nys_pcg_solve(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Tensor,
+                  P: Optional[Precond] = None, y0: Optional[torch.Tensor] = None, **opts):
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    _vec(d, n, "d", A.device)
+    _vec(rhs, m, "rhs", A.device)
+    y = torch.zeros(m, dtype=torch.float64, device=A.device) if y0 is None else _vec(y0, m, "y0", A.device).clone()
+    Am = _mat(A)
+    o = _pcg_opts(**opts)
+    info = nys_pcg_info()
+    Pc = P.c() if P is not None else None
+    rc = lib.nys_pcg_solve(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc) if Pc else None,
+                           _ptr(rhs), _ptr(y), C.byref(o), C.byref(info))
+    _check(lib, h, rc)
+    return y, info
+
+
+def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond] = None, **opts):
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    dev = A.device
+    for t, k, nm in ((q, n, "q"), (x, n, "x"), (z, n, "z"), (r_d, n, "r_d"), (r_p, m, "r_p"),
+                     (r_xz, n, "r_xz")):
+        _vec(t, k, nm, dev)
+    dx = torch.empty(n, dtype=torch.float64, device=dev)
+    dz = torch.empty(n, dtype=torch.float64, device=dev)
+    dy = torch.empty(m, dtype=torch.float64, device=dev)
+    Am = _mat(A)
+    o = _pcg_opts(**opts)
+    info = nys_pcg_info()
+    Pc = P.c() if P is not None else None
+    rc = lib.nys_newton_solve(h, C.byref(Am), _ptr(q), _ptr(x), _ptr(z), float(rho), float(delta),
+                              C.byref(Pc) if Pc else None, _ptr(r_d), _ptr(r_p), _ptr(r_xz), C.byref(o),
+                              _ptr(dx), _ptr(dy), _ptr(dz), C.byref(info))
+    _check(lib, h, rc)
+    return dx, dy, dz, info
+
+
+def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0, verbose=False,
+              pcg_rtol=0.0, pcg_maxit=0, replace_every=0, poll_every=0) -> nys_ipm_opts:
+    return nys_ipm_opts(tol, max_iter, ell, seed, _SK[sketch_dtype], c_nu,
+                        _pcg_opts(pcg_rtol, 0.0, pcg_maxit, replace_every, poll_every), int(verbose))
+
+
+def _qp(A, b, c, q, A_lo):
+    Am = _mat(A)
+    Alo = _mat(A_lo) if A_lo is not None else None
+    keep = (Am, Alo)
+    qp = nys_qp(C.pointer(Am), C.pointer(Alo) if Alo is not None else None, b.data_ptr(),
+                c.data_ptr(), q.data_ptr())
+    return qp, keep
+
+
+def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor, ell: int,
+              A_lo: Optional[torch.Tensor] = None, **kw):
+    """Nys-IP-PMM.  Returns (x, y, z, info: nys_ipm_info)."""
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    dev = A.device
+    _vec(b, m, "b", dev)
+    _vec(c, n, "c", dev)
+    _vec(q, n, "q", dev)
+    x = torch.empty(n, dtype=torch.float64, device=dev)
+    z = torch.empty(n, dtype=torch.float64, device=dev)
+    y = torch.empty(m, dtype=torch.float64, device=dev)
+    qp, keep = _qp(A, b, c, q, A_lo)
+    o = _ipm_opts(ell, **kw)
+    info = nys_ipm_info()
+    rc = lib.ipm_solve(h, C.byref(qp), C.byref(o), _ptr(x), _ptr(y), _ptr(z), C.byref(info))
+    _check(lib, h, rc)
+    del keep
+    return x, y, z, info
+
+
+def ipm_adjoint(A, b, c, q, x, y, z, rho, delta, g, ell, A_lo=None, want=("c", "b", "q", "A"),
+                **kw):
+    """Gradients of L with dL/dx = g through the KKT conditions.  Returns
+    (dict of requested gradients, nys_pcg_info)."""
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    dev = A.device
+    for t, k, nm in ((b, m, "b"), (c, n, "c"), (q, n, "q"), (x, n, "x"), (z, n, "z"), (y, m, "y"),
+                     (g, n, "g")):
+        _vec(t, k, nm, dev)
+    out = {}
+    if "c" in want:
+        out["c"] = torch.empty(n, dtype=torch.float64, device=dev)
+    if "b" in want:
+        out["b"] = torch.empty(m, dtype=torch.float64, device=dev)
+    if "q" in want:
+        out["q"] = torch.empty(n, dtype=torch.float64, device=dev)
+    if "A" in want:
+        out["A"] = torch.empty((m, n), dtype=torch.float64, device=dev)
+    qp, keep = _qp(A, b, c, q, A_lo)
+    kw.pop("tol", None)
+    o = _ipm_opts(ell, **kw)
+    info = nys_pcg_info()
+    rc = lib.ipm_adjoint(h, C.byref(qp), C.byref(o), _ptr(x), _ptr(y), _ptr(z), float(rho), float(delta),
+                         _ptr(g), _ptr(out.get("c")), _ptr(out.get("b")), _ptr(out.get("q")),
+                         _ptr(out.get("A")), C.byref(info))
+    _check(lib, h, rc)
+    del keep
+    return out, info
+
+
+def nys_last_timing(device="cuda"):
+    lib, h = _handle(torch.device(device))
+    a, b, c = C.c_double(), C.c_double(), C.c_double()
+    lib.nys_last_timing(h, C.byref(a), C.byref(b), C.byref(c))
+    return a.value, b.value, c.value

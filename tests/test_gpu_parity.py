@@ -1,0 +1,265 @@
+"""GPU parity of every entry point of the C ABI against the FP64 CPU oracle,
+on the same seeded inputs.
+
+Tolerances are derived from the arithmetic (see the design notes):
+* products with A accumulate in FP64 in a different order than numpy, so an
+  entry may differ by a few units of 2^-53 times the matching entry of the
+  absolute-value product |A| (|d| (|A|^T |v|)); the tests use 1e-12 times
+  that bound;
+* quantities produced by an iterative method (PCG, IP-PMM) are compared at
+  the method's own stopping tolerance.
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from instances import make_instance
+from oracle import adjoint as oadj
+from oracle import ippmm as oipm
+from oracle import lowprec, normal_eq, nystrom, philox, problem
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def nys():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_14524_amd as pkg
+    return pkg
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def _case(m, n, seed, scale=1.0):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) * scale
+    d = rng.uniform(0.0, 2.0, n)
+    v = rng.standard_normal(m)
+    return A, d, v
+
+
+# ------------------------------------------------------------------ normal apply
+
+SHAPES = [(1, 1), (7, 5), (200, 500), (257, 1031), (1000, 3 * 1024 + 37), (3000, 2048), (5, 20000)]
+
+
+@pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
+@pytest.mark.parametrize("m,n", SHAPES)
+def test_normal_apply_parity(nys, dtype, m, n):
+    print(f"normal_apply {dtype} {m}x{n}", flush=True)
+    A, d, v = _case(m, n, seed=m * 7 + n)
+    At = _t(A).to(dtype)
+    Aq = _np(At)          # the values the GPU sees (exact FP64 promotion)
+    if dtype == torch.bfloat16:
+        np.testing.assert_array_equal(Aq, lowprec.round_bf16(A.astype(np.float32).astype(np.float64)))
+    delta = 0.37
+    out = nys.nys_normal_apply(At, _t(d), delta, _t(v))
+    ref = normal_eq.normal_apply(Aq, d, delta, v)
+    bound = np.abs(Aq) @ (np.abs(d) * (np.abs(Aq).T @ np.abs(v))) + delta * np.abs(v)
+    err = np.abs(_np(out) - ref)
+    assert np.all(err <= 1e-12 * bound + 1e-300), (err / bound).max()
+
+
+def test_normal_apply_strided_and_empty(nys):
+    A, d, v = _case(300, 777, seed=3)
+    big = _t(np.hstack([A, np.zeros((300, 5))]))      # ld = 782: 16-byte rows broken
+    At = big[:, :777]
+    out = nys.nys_normal_apply(At, _t(d), 0.0, _t(v))
+    ref = normal_eq.normal_apply(A, d, 0.0, v)
+    np.testing.assert_allclose(_np(out), ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    A32 = _t(np.hstack([A, np.zeros((300, 3))]), torch.float32)[:, :777]
+    out = nys.nys_normal_apply(A32, _t(d), 0.5, _t(v))
+    ref = normal_eq.normal_apply(_np(A32), d, 0.5, v)
+    np.testing.assert_allclose(_np(out), ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    # n = 0: out = delta v
+    out = nys.nys_normal_apply(torch.zeros((4, 0), dtype=torch.float64, device=DEV),
+                               torch.zeros(0, dtype=torch.float64, device=DEV), 2.0, _t(np.arange(4.0)))
+    np.testing.assert_array_equal(_np(out), 2.0 * np.arange(4.0))
+
+
+def test_normal_apply_rejects_bad_arguments(nys):
+    A, d, v = _case(10, 12, seed=4)
+    with pytest.raises(nys.NysError):
+        nys.nys_normal_apply(_t(A), _t(d), float("nan"), _t(v))
+
+
+# ------------------------------------------------------------------ test matrix (Philox)
+
+def test_test_matrix_matches_oracle_philox(nys):
+    G = nys.nys_test_matrix(1001, 37, seed=12345, counter=9)
+    ref = philox.gaussian_matrix(1001, 37, 12345, 9)
+    np.testing.assert_allclose(_np(G), ref, rtol=1e-13, atol=1e-13)
+
+
+# ------------------------------------------------------------------ preconditioner
+
+def test_precond_apply_parity(nys):
+    rng = np.random.default_rng(5)
+    m, ell = 3001, 45
+    U, _ = np.linalg.qr(rng.standard_normal((m, ell)))
+    lam = np.sort(rng.uniform(0, 100, ell))[::-1].copy()
+    lam[-1] = 0.0
+    r = rng.standard_normal(m)
+    P = nys.Precond(_t(U), _t(lam))
+    for delta in (1e-8, 0.3, 50.0):
+        out = nys.nys_precond_apply(P, delta, _t(r))
+        ref = nystrom.precond_inv_apply(U, lam, delta, r)
+        np.testing.assert_allclose(_np(out), ref, rtol=1e-12, atol=1e-12 * np.abs(r).max())
+    with pytest.raises(nys.NysError):
+        nys.nys_precond_apply(P, 0.0, _t(r))
+
+
+# ------------------------------------------------------------------ sketch
+
+def _nhat(U, lam):
+    return (U * lam) @ U.T
+
+
+@pytest.mark.parametrize("m,n,ell", [(120, 300, 10), (700, 2000, 64), (1500, 4000, 100)])
+def test_sketch_fp64_parity(nys, m, n, ell):
+    print(f"sketch {m}x{n} ell={ell}", flush=True)
+    inst = make_instance("lowrank_5000x20000", seed=11, m=m, n=n, rank=max(ell // 2, 4))
+    A = inst.A.double().numpy()
+    rng = np.random.default_rng(ell)
+    d = rng.uniform(0.01, 10.0, n)
+    Om = rng.standard_normal((m, ell))
+    P = nys.nys_sketch(_t(A), _t(d), ell, omega=_t(Om))
+    Omq = nystrom.orthonormalize(Om)
+    Uo, lo, nuo = nystrom.nystrom(lambda V: A @ (d[:, None] * (A.T @ V)), Omq)
+    Ug, lg = _np(P.U), _np(P.lam)
+    np.testing.assert_allclose(Ug.T @ Ug, np.eye(ell), atol=1e-12)
+    assert np.all(np.diff(lg) <= 0) and np.all(lg >= 0)
+    scale = lo[0]
+    np.testing.assert_allclose(lg, lo, rtol=1e-8, atol=1e-10 * scale)
+    Nh_g, Nh_o = _nhat(Ug, lg), _nhat(Uo, lo)
+    assert np.linalg.norm(Nh_g - Nh_o, 2) <= 1e-8 * scale
+    assert abs(P.nu - nuo) <= 1e-12 * max(nuo, 1e-300) or P.nu == nuo
+
+
+def test_sketch_exact_at_rank(nys):
+    # N of exact rank r < ell: the approximation reproduces N
+    m, n, r, ell = 600, 900, 12, 20
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((m, r)) @ rng.standard_normal((r, n)) / n
+    d = rng.uniform(0.5, 2.0, n)
+    P = nys.nys_sketch(_t(A), _t(d), ell, seed=3, counter=1)
+    N = normal_eq.normal_matrix(A, d)
+    Nh = _nhat(_np(P.U), _np(P.lam))
+    assert np.linalg.norm(N - Nh, 2) <= 1e-10 * np.linalg.norm(N, 2)
+
+
+def test_sketch_rejects_bad_sizes(nys):
+    A, d, v = _case(10, 12, seed=4)
+    with pytest.raises(nys.NysError):
+        nys.nys_sketch(_t(A), _t(d), 11)
+
+
+# ------------------------------------------------------------------ PCG
+
+@pytest.mark.parametrize("use_p", [False, True])
+def test_pcg_parity_with_dense_solve(nys, use_p):
+    inst = make_instance("lowrank_5000x20000", seed=12, m=800, n=3000, rank=40)
+    A = inst.A.double().numpy()
+    rng = np.random.default_rng(1)
+    d = rng.uniform(0.01, 5.0, 3000)
+    delta = 1e-3
+    xi = rng.standard_normal(800)
+    P = nys.nys_sketch(_t(A), _t(d), 60, seed=1) if use_p else None
+    y, info = nys.nys_pcg_solve(_t(A), _t(d), delta, _t(xi), P=P, rtol=1e-11, maxit=3000)
+    M = normal_eq.normal_matrix(A, d, delta)
+    ref = np.linalg.solve(M, xi)
+    assert info.status == 0
+    assert np.linalg.norm(xi - M @ _np(y)) <= 1.01e-11 * np.linalg.norm(xi) + 1e-14
+    np.testing.assert_allclose(_np(y), ref, rtol=0, atol=1e-6 * np.abs(ref).max())
+
+
+def test_pcg_one_iteration_with_exact_rank_preconditioner(nys):
+    m, n, r = 500, 700, 10
+    rng = np.random.default_rng(9)
+    A = rng.standard_normal((m, r)) @ rng.standard_normal((r, n)) / np.sqrt(n)
+    d = np.ones(n)
+    P = nys.nys_sketch(_t(A), _t(d), r + 6, seed=5)
+    xi = rng.standard_normal(m)
+    y, info = nys.nys_pcg_solve(_t(A), _t(d), 1e-2, _t(xi), P=P, rtol=1e-9, poll_every=1)
+    assert info.iters == 1 and info.status == 0
+
+
+# ------------------------------------------------------------------ Newton step
+
+def test_newton_step_parity(nys):
+    inst = make_instance("gauss_200x500", seed=4)
+    A = inst.A.double().numpy()
+    m, n = A.shape
+    rng = np.random.default_rng(2)
+    x = rng.uniform(0.01, 2, n)
+    z = rng.uniform(0.01, 2, n)
+    q = inst.q.numpy()
+    rho, delta = 0.1, 0.05
+    rd, rp, rxz = rng.standard_normal(n), rng.standard_normal(m), rng.standard_normal(n)
+    D = normal_eq.scaling(x, z, q, rho)
+    M = normal_eq.normal_matrix(A, D, delta)
+    ex, ey, ez, _ = normal_eq.newton_step(A, x, z, D, delta, rd, rp, rxz, lambda xi: np.linalg.solve(M, xi))
+    dx, dy, dz, info = nys.nys_newton_solve(_t(A), _t(q), _t(x), _t(z), rho, delta, _t(rd), _t(rp), _t(rxz),
+                                            rtol=1e-13, maxit=2000)
+    for g, e in ((dx, ex), (dy, ey), (dz, ez)):
+        assert np.linalg.norm(_np(g) - e) <= 1e-9 * (1 + np.linalg.norm(e))
+
+
+# ------------------------------------------------------------------ IP-PMM
+
+def test_ipm_solve_gauss_small(nys):
+    inst = make_instance("gauss_200x500", seed=1)
+    A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+    ref = oipm.solve(A, b, c, q, tol=1e-10)
+    x, y, z, info = nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=20, tol=1e-6, seed=0)
+    assert info.status == 0, info.kkt_rel
+    meas = problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))
+    assert meas["kkt"] <= 1e-6
+    assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-5 * np.linalg.norm(ref["x"])
+    assert np.all(_np(x) > 0) and np.all(_np(z) > 0)
+
+
+def test_ipm_solve_rejects_bad_data(nys):
+    inst = make_instance("gauss_200x500", seed=2)
+    A, b, c, q = (_t(inst.A.double().numpy()), _t(inst.b.numpy()), _t(inst.c.numpy()), _t(inst.q.numpy()))
+    qb = q.clone()
+    qb[3] = -1.0
+    with pytest.raises(nys.NysError) as e:
+        nys.ipm_solve(A, b, c, qb, ell=20)
+    assert e.value.code == -1
+    Ab = A.clone()
+    Ab[5, 7] = float("nan")
+    with pytest.raises(nys.NysError) as e:
+        nys.ipm_solve(Ab, b, c, q, ell=20)
+    assert e.value.code == -1
+    with pytest.raises(nys.NysError):
+        nys.ipm_solve(A, b, c, q, ell=0)
+
+
+def test_ipm_adjoint_parity(nys):
+    inst = make_instance("gauss_2000x8000", seed=3, m=150, n=400)
+    A32 = inst.A
+    A = A32.double().numpy()
+    b, c, q = inst.b.numpy(), inst.c.numpy(), inst.q.numpy()
+    x, y, z, info = nys.ipm_solve(_t(A32, torch.float32), _t(b), _t(c), _t(q), ell=30, tol=1e-9)
+    assert info.status == 0
+    xs, ys, zs = inst.x_star.numpy(), inst.y_star.numpy(), inst.z_star.numpy()
+    x_tgt = xs + 0.01 * np.random.default_rng(0).standard_normal(xs.shape)
+    g = _np(x) - x_tgt
+    ref = oadj.kkt_gradient(A, b, c, q, xs, ys, zs, xs - x_tgt)
+    grads, pinfo = nys.ipm_adjoint(_t(A32, torch.float32), _t(b), _t(c), _t(q), x, y, z, info.rho,
+                                   info.delta, _t(g), ell=30)
+    for k in ("c", "b", "q", "A"):
+        e = ref[k]
+        gk = _np(grads[k])
+        assert np.linalg.norm(gk - e) <= 1e-4 * np.linalg.norm(e), k

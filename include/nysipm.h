@@ -101,6 +101,16 @@ int nys_normal_apply(nys_handle h, const nys_matrix* A, const double* d, double 
 int nys_test_matrix(nys_handle h, int64_t m, int32_t ell, uint64_t seed, uint64_t counter,
                     double* out);
 
+/* The sketch Y = N Omega = A diag(d) A^T Omega of Algorithm 1 (second step),
+   as the product pair W = d .* (A^T Omega), Y = A W.  omega: m x ell FP64
+   row-major (used as given); Y: m x ell FP64 row-major, caller-owned.
+   sketch_dtype NYS_F64: FP64 arithmetic, A stored FP64 or FP32.
+   NYS_BF16: A stored BF16; Omega and W are rounded to BF16 (round to nearest
+   even, through FP32) and both products run on matrix cores with FP32
+   accumulation; Y's split partial sums are added in FP64.  Enqueue only. */
+int nys_sketch_product(nys_handle h, const nys_matrix* A, const double* d, const double* omega,
+                       int32_t ell, nys_dtype sketch_dtype, double* Y);
+
 /* Randomized Nystrom approximation of N = A diag(d) A^T (Algorithm 1; the
    sketched matrix is N, not N + delta I) and the data of the Nystrom
    preconditioner (Algorithm 2).

@@ -541,6 +541,22 @@ extern "C" int nys_test_matrix(nys_handle h, int64_t m, int32_t ell, uint64_t se
   return philox_gaussian(h, m, ell, seed, counter, out);
 }
 
+extern "C" int nys_sketch_product(nys_handle h, const nys_matrix* A, const double* d,
+                                  const double* omega, int32_t ell, nys_dtype sketch_dtype, double* Y) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_sketch_product"));
+  if (ell < 1 || !d || !omega || !Y) return set_error(h, NYS_EINVAL, "nys_sketch_product: bad arguments");
+  if (sketch_dtype == NYS_BF16 && A->dtype != NYS_BF16)
+    return set_error(h, NYS_EINVAL, "nys_sketch_product: a BF16 sketch needs BF16 storage of A");
+  if (sketch_dtype == NYS_F64 && A->dtype == NYS_BF16)
+    return set_error(h, NYS_EINVAL, "nys_sketch_product: an FP64 sketch needs FP64 or FP32 storage");
+  if (sketch_dtype != NYS_BF16 && sketch_dtype != NYS_F64)
+    return set_error(h, NYS_EINVAL, "nys_sketch_product: sketch dtype must be NYS_F64 or NYS_BF16");
+  NYS_HIP(h, hipSetDevice(h->device));
+  if (A->m == 0) return NYS_OK;
+  return sketch_product(h, A, d, omega, ell, sketch_dtype, Y);
+}
+
 extern "C" int nys_sketch(nys_handle h, const nys_matrix* A, const double* d, int32_t ell,
                           uint64_t seed, uint64_t counter, nys_dtype sketch_dtype,
                           const double* omega, nys_precond* P, double* nu_out) {

@@ -266,7 +266,11 @@ int gemv_t(nys_handle h, const GemvT& a) {
   const nys_matrix* A = a.A;
   const int es = elem_size(A->dtype);
   const int vec = 16 / es;
-  const int64_t ncol = (A->n + (int64_t)NYS_BLOCK * vec - 1) / ((int64_t)NYS_BLOCK * vec);
+  const bool fused = a.s != nullptr;
+  // n == 0: nothing to reduce; the fused direction update still has to run
+  if (A->n == 0 && !fused) return NYS_OK;
+  const int64_t ncol =
+      std::max<int64_t>(1, (A->n + (int64_t)NYS_BLOCK * vec - 1) / ((int64_t)NYS_BLOCK * vec));
   // enough blocks to cover the chip several times, rows per chunk >= 32
   int64_t nch = std::max<int64_t>(1, std::min<int64_t>((A->m + 31) / 32, (2048 + ncol - 1) / ncol));
   int64_t rpc = (A->m + nch - 1) / nch;
@@ -295,9 +299,7 @@ int gemv_t(nys_handle h, const GemvT& a) {
       return set_error(h, NYS_EINVAL, "gemv_t: %lld column tiles exceed the counter array", (long long)ncol);
     k.cnt = h->counters;
   }
-  if (A->n == 0) return NYS_OK;
   dim3 g((unsigned)ncol, (unsigned)nch);
-  const bool fused = a.s != nullptr;
   const bool vl = vec_ok(A);
   switch (A->dtype) {
     case NYS_F64: dispatch_t<F64>(g, k, fused, vl, h->stream); break;

@@ -1,9 +1,232 @@
-// BF16 matrix-core sketch (placeholder until the MFMA kernels land).
+// The sketch Y = A diag(d) A^T Omega (Algorithm 1, second step) on BF16
+// matrix cores with FP32 accumulation (v_mfma_f32_32x32x16_bf16, gfx950).
+//
+//   Ot   = bf16(Omega)^T                      ell x m  (k-contiguous operand)
+//   Wt   = bf16(d .* (A^T Omega))^T = bf16((Ot A) .* d)   ell x n
+//   Y    = A Wt^T                              m x ell (FP32 partial sums,
+//                                               reduced in FP64 across split-K)
+//
+// One kernel template computes C = Aop * Bop for Aop stored M x K (K
+// contiguous) and Bop stored either N x K (K contiguous, "NT") or K x N (N
+// contiguous, "NN"; transposed on its way into LDS).  Block tile 128 x 128 x
+// 32, four waves in a 2 x 2 arrangement, each wave a 64 x 64 tile made of
+// 2 x 2 MFMA 32 x 32 x 16 tiles.  Operands are staged through LDS in
+// [row][k] order so every MFMA operand is one 16-byte LDS read per lane.
+//
+// MFMA 32x32x16 lane layout (lane l, 8 bf16 per operand, 16 floats out):
+//   A operand: row l%32, k = 8*(l/32) .. +7;  B operand: column l%32, same k;
+//   D: column l%32, row 8*(r/4) + 4*(l/32) + r%4 for output register r.
+
 #include "common.hpp"
 #include "kernels.hpp"
 
 namespace nys {
-int sketch_bf16(nys_handle h, const nys_matrix*, const double*, const double*, int, double*) {
-  return set_error(h, NYS_EINVAL, "BF16 sketch not built");
+namespace {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+
+constexpr int TBM = 128, TBN = 128, TBK = 32;
+constexpr int LDK = TBK + 8;   // padded LDS row (bf16 elements): 80 bytes
+
+__device__ __forceinline__ uint16_t bf16_rne(float f) {
+  uint32_t u = __float_as_uint(f);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
 }
+
+// Load 8 consecutive K-direction elements of row `row` starting at k (zero
+// outside [0, rows) x [0, K)).
+__device__ __forceinline__ u16x8 load_k8(const uint16_t* P, int64_t ld, int64_t row, int64_t rows,
+                                         int64_t k, int64_t K, bool vec) {
+  u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (row >= rows) return v;
+  const uint16_t* p = P + row * ld + k;
+  if (vec && k + 8 <= K) return *(const u16x8*)p;
+#pragma unroll
+  for (int e = 0; e < 8; ++e)
+    if (k + e < K) v[e] = p[e];
+  return v;
+}
+
+struct EpiWt {      // Wt[c][j] = bf16(acc * d[j]); M = ell (c), N = n (j)
+  uint16_t* Wt;
+  int64_t ldw;
+  const double* d;
+  __device__ void operator()(int64_t c, int64_t j, float v) const {
+    Wt[c * ldw + j] = bf16_rne((float)((double)v * d[j]));
+  }
+};
+struct EpiPart {    // part[z][i][c] = acc; M = m (i), N = ell (c)
+  float* part;
+  int64_t M, N;
+  __device__ void operator()(int64_t i, int64_t c, float v) const {
+    part[((int64_t)blockIdx.z * M + i) * N + c] = v;
+  }
+};
+
+template <bool B_NK, class Epi>
+__global__ __launch_bounds__(NYS_BLOCK) void k_mfma_gemm(int64_t M, int64_t N, int64_t K,
+                                                         const uint16_t* A, int64_t lda,
+                                                         const uint16_t* B, int64_t ldb,
+                                                         int64_t klen, bool veca, bool vecb, Epi epi) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[TBM * LDK];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[TBN * LDK];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)blockIdx.y * TBM, n0 = (int64_t)blockIdx.x * TBN;
+  const int64_t kb = (int64_t)blockIdx.z * klen;
+  const int64_t ke = min(K, kb + klen);
+  f32x16 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+
+  for (int64_t k0 = kb; k0 < ke; k0 += TBK) {
+    // ---- A tile: 128 rows x 32 k, two 16-byte pieces per thread
+#pragma unroll
+    for (int p = 0; p < 2; ++p) {
+      const int row = (tid >> 2) + 64 * p;
+      const int kc = (tid & 3) * 8;
+      const u16x8 v = load_k8(A, lda, m0 + row, M, k0 + kc, ke, veca);
+      *(u16x8*)(As + row * LDK + kc) = v;
+    }
+    // ---- B tile: 128 columns x 32 k
+    if constexpr (B_NK) {
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int col = (tid >> 2) + 64 * p;
+        const int kc = (tid & 3) * 8;
+        const u16x8 v = load_k8(B, ldb, n0 + col, N, k0 + kc, ke, vecb);
+        *(u16x8*)(Bs + col * LDK + kc) = v;
+      }
+    } else {
+      // B stored K x N (N contiguous): read 8 columns of one k-row, write transposed
+#pragma unroll
+      for (int p = 0; p < 2; ++p) {
+        const int kr = (tid >> 4) + 16 * p;
+        const int nc = (tid & 15) * 8;
+        const int64_t gk = k0 + kr;
+        u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (gk < ke) {
+          const uint16_t* src = B + gk * ldb + n0 + nc;
+          if (vecb && n0 + nc + 8 <= N) {
+            v = *(const u16x8*)src;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+              if (n0 + nc + e < N) v[e] = src[e];
+          }
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[(nc + e) * LDK + kr] = v[e];
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int ks = 0; ks < TBK; ks += 16) {
+      const int kk = ks + 8 * (lane >> 5);
+      bf16x8 a[2], b[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        const int ar = wm * 64 + t * 32 + (lane & 31);
+        const int bc = wn * 64 + t * 32 + (lane & 31);
+        a[t] = __builtin_bit_cast(bf16x8, *(const u16x8*)(As + ar * LDK + kk));
+        b[t] = __builtin_bit_cast(bf16x8, *(const u16x8*)(Bs + bc * LDK + kk));
+      }
+#pragma unroll
+      for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 2; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int ti = 0; ti < 2; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 2; ++tj)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t row = m0 + wm * 64 + ti * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t col = n0 + wn * 64 + tj * 32 + (lane & 31);
+        if (row < M && col < N) epi(row, col, acc[ti][tj][r]);
+      }
+}
+
+// Ot[c][i] = bf16(fp32(Omega[i][c])), i < m; ld of Ot = ldo
+__global__ __launch_bounds__(NYS_BLOCK) void k_omega_t(const double* Om, int64_t m, int ell,
+                                                       uint16_t* Ot, int64_t ldo) {
+  const int64_t total = (int64_t)ell * m;
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    const int64_t c = idx / m, i = idx % m;
+    Ot[c * ldo + i] = bf16_rne((float)Om[i * ell + c]);
+  }
+}
+
+__global__ __launch_bounds__(NYS_BLOCK) void k_split_sum(const float* part, int nsplit, int64_t count,
+                                                         double* Y) {
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < count;
+       idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += (double)part[(int64_t)z * count + idx];
+    Y[idx] = s;
+  }
+}
+
+unsigned grid1d(int64_t n) {
+  int64_t b = (n + NYS_BLOCK - 1) / NYS_BLOCK;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(b, 8192));
+}
+
+}  // namespace
+
+int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double* Omega, int ell,
+                double* Y) {
+  if (A->dtype != NYS_BF16) return set_error(h, NYS_EINVAL, "BF16 sketch needs BF16 storage of A");
+  const int64_t m = A->m, n = A->n;
+  if (n == 0) return fill(h, Y, m * ell, 0.0);
+  const int64_t ldo = (m + 7) / 8 * 8, ldw = (n + 7) / 8 * 8;
+  uint16_t *Ot, *Wt;
+  NYS_CHECK(ws(h, WS_SK_LO, (size_t)ell * ldo, &Ot));
+  NYS_CHECK(ws(h, WS_SK_W, (size_t)ell * ldw, &Wt));
+  hipLaunchKernelGGL(k_omega_t, dim3(grid1d(m * ell)), dim3(NYS_BLOCK), 0, h->stream, Omega, m, ell, Ot, ldo);
+  NYS_LAUNCH_CHECK(h);
+  const uint16_t* Ad = (const uint16_t*)A->data;
+  const bool vecA = ((uintptr_t)Ad % 16 == 0) && (A->ld % 8 == 0);
+  // Wt (ell x n) = Ot (ell x m) * A (m x n, "NN"), scaled by d and rounded to BF16
+  {
+    dim3 g((unsigned)((n + TBN - 1) / TBN), (unsigned)((ell + TBM - 1) / TBM), 1);
+    EpiWt epi{Wt, ldw, d};
+    hipLaunchKernelGGL((k_mfma_gemm<false, EpiWt>), g, dim3(NYS_BLOCK), 0, h->stream, (int64_t)ell, n, m,
+                       (const uint16_t*)Ot, ldo, Ad, A->ld, m, true, vecA, epi);
+    NYS_LAUNCH_CHECK(h);
+  }
+  // Y (m x ell) = A (m x n) * Wt^T ("NT"), split over n
+  {
+    const int64_t tiles = ((m + TBM - 1) / TBM) * ((ell + TBN - 1) / TBN);
+    int64_t nsplit = std::max<int64_t>(1, std::min<int64_t>((1024 + tiles - 1) / tiles, 16));
+    int64_t klen = (n + nsplit - 1) / nsplit;
+    klen = std::max<int64_t>(4096, (klen + TBK - 1) / TBK * TBK);
+    nsplit = std::max<int64_t>(1, (n + klen - 1) / klen);
+    float* part;
+    NYS_CHECK(ws_get(h, WS_SK_SPLIT, (size_t)nsplit * m * ell * sizeof(float), (void**)&part));
+    dim3 g((unsigned)((ell + TBN - 1) / TBN), (unsigned)((m + TBM - 1) / TBM), (unsigned)nsplit);
+    EpiPart epi{part, m, ell};
+    hipLaunchKernelGGL((k_mfma_gemm<true, EpiPart>), g, dim3(NYS_BLOCK), 0, h->stream, m, (int64_t)ell, n,
+                       Ad, A->ld, (const uint16_t*)Wt, ldw, klen, vecA, true, epi);
+    NYS_LAUNCH_CHECK(h);
+    hipLaunchKernelGGL(k_split_sum, dim3(grid1d(m * ell)), dim3(NYS_BLOCK), 0, h->stream, part, (int)nsplit,
+                       m * ell, Y);
+    NYS_LAUNCH_CHECK(h);
+  }
+  return NYS_OK;
+}
+
 }  // namespace nys

@@ -70,7 +70,7 @@ class nys_ipm_info(C.Structure):
 
 
 EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
-           "nys_normal_apply", "nys_test_matrix", "nys_sketch", "nys_precond_apply",
+           "nys_normal_apply", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint"]
 
 _lib = None
@@ -97,6 +97,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
             "nys_last_timing": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)],
             "nys_normal_apply": [vp, pm, vp, dbl, vp, vp],
             "nys_test_matrix": [vp, i64, i32, u64, u64, vp],
+            "nys_sketch_product": [vp, pm, vp, vp, i32, C.c_int, vp],
             "nys_sketch": [vp, pm, vp, i32, u64, u64, C.c_int, vp, C.POINTER(nys_precond), C.POINTER(dbl)],
             "nys_precond_apply": [vp, C.POINTER(nys_precond), dbl, vp, vp],
             "nys_pcg_solve": [vp, pm, vp, dbl, C.POINTER(nys_precond), vp, vp, C.POINTER(nys_pcg_opts),
@@ -190,6 +191,21 @@ def nys_test_matrix(m: int, ell: int, seed: int, counter: int, device="cuda") ->
     out = torch.empty((m, ell), dtype=torch.float64, device=device)
     _check(lib, h, lib.nys_test_matrix(h, m, ell, seed, counter, _ptr(out)))
     return out
+
+
+def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sketch_dtype="f64",
+                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    ell = omega.shape[1]
+    _vec(d, n, "d", A.device)
+    _vec(omega.reshape(-1), m * ell, "omega", A.device)
+    Y = torch.empty((m, ell), dtype=torch.float64, device=A.device) if out is None else out
+    _vec(Y.reshape(-1), m * ell, "out", A.device)
+    Am = _mat(A)
+    _check(lib, h, lib.nys_sketch_product(h, C.byref(Am), _ptr(d), _ptr(omega), ell, _SK[sketch_dtype],
+                                          _ptr(Y)))
+    return Y
 
 
 def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,

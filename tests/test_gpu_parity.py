@@ -146,6 +146,55 @@ def test_sketch_fp64_parity(nys, m, n, ell):
     assert abs(P.nu - nuo) <= 1e-12 * max(nuo, 1e-300) or P.nu == nuo
 
 
+@pytest.mark.parametrize("m,n,ell", [(1, 9, 1), (130, 257, 7), (1000, 3000, 100), (2000, 8000, 50),
+                                     (777, 5001, 200)])
+def test_sketch_product_parity(nys, m, n, ell):
+    """Y = A diag(d) A^T Omega in FP64 and on BF16 matrix cores."""
+    print(f"sketch_product {m}x{n} ell={ell}", flush=True)
+    rng = np.random.default_rng(m + n + ell)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    d = rng.uniform(0.0, 3.0, n)
+    Om = rng.standard_normal((m, ell))
+    # FP64 arithmetic on FP64 storage
+    Y = nys.nys_sketch_product(_t(A), _t(d), _t(Om), "f64")
+    ref = A @ (d[:, None] * (A.T @ Om))
+    bound = np.abs(A) @ (d[:, None] * (np.abs(A).T @ np.abs(Om)))
+    assert np.all(np.abs(_np(Y) - ref) <= 1e-12 * bound + 1e-300)
+    # BF16 matrix cores, FP32 accumulation, against the emulated-BF16 oracle
+    A32 = A.astype(np.float32)
+    Abf = _t(A32, torch.float32).to(torch.bfloat16)
+    Yb = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16"))
+    refb = lowprec.sketch_bf16(A32.astype(np.float64), d, Om)
+    Ab = lowprec.round_bf16(A32.astype(np.float64))
+    boundb = np.abs(Ab) @ (d[:, None] * (np.abs(Ab).T @ np.abs(lowprec.round_bf16(Om))))
+    # Worst case per entry: FP32 accumulation errors (m + n terms) plus a BF16
+    # rounding of W that lands on the other side of a tie, at most 2^-8 |W|.
+    err = np.abs(Yb - refb)
+    assert np.all(err <= (2.0 ** -8 + 2.0 ** -24 * (m + n)) * boundb + 1e-300)
+    # typical: the flips are rare and the FP32 errors average out
+    assert np.linalg.norm(Yb - refb) <= 1e-4 * np.linalg.norm(refb)
+
+
+@pytest.mark.parametrize("m,n,ell", [(600, 2000, 40), (1500, 6000, 120)])
+def test_sketch_bf16_parity(nys, m, n, ell):
+    """Nystrom approximation from the BF16 matrix-core sketch vs the oracle's
+    Algorithm 1 run on the emulated-BF16 sketch (same Omega, BF16 shift)."""
+    inst = make_instance("lowrank_20000x100000", seed=21, m=m, n=n, rank=max(ell, 8))
+    A32 = inst.A.numpy()
+    rng = np.random.default_rng(ell)
+    d = rng.uniform(0.01, 10.0, n)
+    Om = rng.standard_normal((m, ell))
+    Abf = inst.A.to(DEV).to(torch.bfloat16)
+    P = nys.nys_sketch(Abf, _t(d), ell, omega=_t(Om), sketch_dtype="bf16")
+    Omq = nystrom.orthonormalize(Om)
+    Y = lowprec.sketch_bf16(A32.astype(np.float64), d, Omq)
+    Uo, lo, nuo = nystrom.nystrom_from_sketch(Y, Omq, precision="bf16")
+    assert P.nu == nuo
+    Ug, lg = _np(P.U), _np(P.lam)
+    np.testing.assert_allclose(Ug.T @ Ug, np.eye(ell), atol=1e-12)
+    assert np.linalg.norm(_nhat(Ug, lg) - _nhat(Uo, lo), 2) <= 1e-4 * lo[0]
+
+
 def test_sketch_exact_at_rank(nys):
     # N of exact rank r < ell: the approximation reproduces N
     m, n, r, ell = 600, 900, 12, 20
@@ -227,6 +276,23 @@ def test_ipm_solve_gauss_small(nys):
     assert meas["kkt"] <= 1e-6
     assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-5 * np.linalg.norm(ref["x"])
     assert np.all(_np(x) > 0) and np.all(_np(z) > 0)
+
+
+@pytest.mark.parametrize("sk", ["f64", "bf16"])
+def test_ipm_solve_mixed_precision_fp32_matrix(nys, sk):
+    """FP32-defined matrix, FP64-accumulated products, FP64 or BF16 sketch:
+    KKT <= 1e-6 and x within 1e-5 of the oracle's (polished) optimum."""
+    inst = make_instance("gauss_2000x8000", seed=5, m=400, n=1600)
+    A = inst.A.double().numpy()
+    b, c, q = inst.b.numpy(), inst.c.numpy(), inst.q.numpy()
+    At = inst.A.to(DEV)
+    x, y, z, info = nys.ipm_solve(At, _t(b), _t(c), _t(q), ell=50, tol=1e-6, seed=1, sketch_dtype=sk,
+                                  A_lo=At.to(torch.bfloat16) if sk == "bf16" else None)
+    assert info.status == 0, (info.kkt_rel, info.iters)
+    meas = problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))
+    assert meas["kkt"] <= 1e-6
+    xs = inst.x_star.numpy()                 # planted optimum = oracle optimum (pinned)
+    assert np.linalg.norm(_np(x) - xs) <= 1e-5 * np.linalg.norm(xs)
 
 
 def test_ipm_solve_rejects_bad_data(nys):

@@ -1,0 +1,265 @@
+"""Benchmark: time to relative KKT residual <= 1e-6 of Nys-IP-PMM on one
+MI355X, mixed precision (FP32-defined A with FP64-accumulated products, BF16
+matrix-core sketch) against the FP64 GPU form, plus the normal-equation
+matvec bandwidth against the HBM roofline.
+
+Workload (default): lowrank_20000x100000 -- m = 20000, n = 100000,
+A = U diag(i^-1.5) V^T (rank 400) + 1e-3 N(0,1) stored FP32 (8 GB) and BF16
+(4 GB), Q = diag(U[0,1]) with 30% exact zeros, planted optimum, sketch 200,
+instance seed 0, generated on the GPU.
+
+One JSON line on stdout.  `value` = seconds per mixed-precision solve (one
+step = one full solve from the initial point to KKT <= 1e-6), inputs resident
+in HBM.  The roofline object is for the dominant kernel (the pass of the
+normal-equation operator with the larger total time), timed with HIP events
+on the library's stream during the timed steps.  cpu_baseline times the FP64
+oracle's per-iteration work on a bounded sample of the same instance.
+
+Modes:
+  python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-fp64] [--no-cpu-baseline]
+  python bench.py --kernel-loop R   # only R normal-equation applies + a plain
+                                    # copy of known size (for counter runs)
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+TOL = 1e-6
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def gemv_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("gemv.hip", "common.hpp"):
+        with open(os.path.join(ROOT, "paper_2404_14524_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload: str):
+    """HBM bytes per launch of the two GEMV passes from the committed counter
+    summary, valid only if the kernel source is unchanged since."""
+    path = os.path.join(ROOT, "profiles", f"gemv_traffic_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("gemv_source_hash") != gemv_source_hash():
+        return None
+    return rec
+
+
+def cpu_baseline(inst, D, delta, gpu_iters, budget_cols: int):
+    """The FP64 oracle's per-iteration work on a bounded sample of the same
+    instance: the normal matrix from a column sample (the oracle's
+    normal_matrix on A[:, J], |J| = budget_cols), extrapolated by n/|J|, plus
+    the oracle's dense Cholesky of the m x m result; times the GPU run's
+    iteration count (extrapolated)."""
+    import numpy as np
+    import scipy.linalg as sla
+    from threadpoolctl import threadpool_limits
+
+    from oracle import normal_eq
+
+    cores = len(os.sched_getaffinity(0))
+    m, n = inst.m, inst.n
+    with threadpool_limits(limits=cores):
+        A = inst.A.cpu().double().numpy()
+        d = D.cpu().numpy()
+        J = np.arange(0, n, max(1, n // budget_cols))[:budget_cols]
+        t0 = time.perf_counter()
+        M = normal_eq.normal_matrix(A[:, J], d[J], delta)
+        t_form = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        sla.cho_factor(M)
+        t_chol = time.perf_counter() - t0
+        v = np.random.default_rng(0).standard_normal(m)
+        t0 = time.perf_counter()
+        normal_eq.normal_apply(A, d, delta, v)
+        t_apply = time.perf_counter() - t0
+    t_iter = t_form * (n / len(J)) + t_chol
+    model = open("/proc/cpuinfo").read().split("model name")[1].split("\n")[0].strip(": \t") \
+        if os.path.exists("/proc/cpuinfo") else "unknown"
+    return {
+        "value": t_iter * gpu_iters,
+        "unit": "s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": (f"one oracle IP-PMM iteration on this instance: normal_matrix on {len(J)} of {n} "
+                   f"columns ({t_form:.2f} s, scaled x{n / len(J):.0f}) + dense Cholesky of the "
+                   f"{m}x{m} matrix ({t_chol:.2f} s); x {gpu_iters} iterations (the GPU run's count); "
+                   f"extrapolated"),
+        "cpu_model": model,
+        "oracle_matvec_GBps": 2.0 * m * n * 8 / t_apply / 1e9,
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="lowrank_20000x100000")
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--kernel-loop", type=int, default=0)
+    ap.add_argument("--verbose", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
+              "(the column-sharded design is described in DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import paper_2404_14524_amd as nys
+    from instances import make_instance
+
+    dev = "cuda"
+    t0 = time.perf_counter()
+    inst = make_instance(args.workload, seed=args.seed, device=dev)
+    A = inst.A
+    A_lo = A.to(torch.bfloat16) if A.dtype == torch.float32 else None
+    torch.cuda.synchronize()
+    log(f"instance {args.workload} m={inst.m} n={inst.n} ell={inst.ell} A={A.dtype} "
+        f"generated in {time.perf_counter() - t0:.1f}s")
+    b_A = A.element_size()
+    bytes_pass = inst.m * inst.n * b_A
+
+    if args.kernel_loop:
+        d = torch.rand(inst.n, dtype=torch.float64, device=dev)
+        v = torch.randn(inst.m, dtype=torch.float64, device=dev)
+        out = torch.empty_like(v)
+        for _ in range(args.kernel_loop):
+            nys.nys_normal_apply(A, d, 1e-3, v, out)
+        src = torch.empty(1 << 29, dtype=torch.float32, device=dev)   # 2 GiB
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"kernel loop done: {args.kernel_loop} normal applies ({bytes_pass} B per pass), "
+            f"5 copies of {src.numel() * 4} B")
+        return
+
+    mixed = dict(ell=inst.ell, tol=TOL, seed=args.seed, sketch_dtype="bf16" if A_lo is not None else "f64",
+                 A_lo=A_lo, verbose=args.verbose)
+    for w in range(args.warmup):
+        x, y, z, info = nys.ipm_solve(A, inst.b, inst.c, inst.q, **mixed)
+        torch.cuda.synchronize()
+        log(f"warmup {w}: iters={info.iters} pcg={info.pcg_iters_total} kkt={info.kkt_rel:.2e}")
+
+    nys.nys_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        x, y, z, info = nys.ipm_solve(A, inst.b, inst.c, inst.q, **mixed)
+    torch.cuda.synchronize()
+    t_total = time.perf_counter() - t0
+    prof = nys.nys_profile_read()
+    nys.nys_profile_enable(False)
+    ms_per_step = 1000.0 * t_total / args.steps
+    t_sketch, t_pcg, t_other = info.t_sketch_ms, info.t_pcg_ms, info.t_other_ms
+    xs = inst.x_star
+    x_err = float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs))
+    log(f"timed: {ms_per_step:.1f} ms/solve iters={info.iters} pcg={info.pcg_iters_total} "
+        f"kkt={info.kkt_rel:.2e} |x-x*|/|x*|={x_err:.2e} sketch={t_sketch:.0f}ms pcg={t_pcg:.0f}ms "
+        f"other={t_other:.0f}ms")
+
+    # dominant kernel and its roofline
+    passes = {k: prof[k] for k in ("normal_pass1", "normal_pass2")}
+    dom = max(passes, key=lambda k: passes[k][1])
+    launches, tot_ms = passes[dom]
+    avg_ms = tot_ms / max(launches, 1)
+    achieved = bytes_pass / (avg_ms * 1e-3) / 1e9
+    pair_gbs = 2 * bytes_pass * min(passes["normal_pass1"][0], passes["normal_pass2"][0]) / \
+        ((passes["normal_pass1"][1] + passes["normal_pass2"][1]) * 1e-3) / 1e9
+    trec = load_traffic(args.workload)
+    traffic = None
+    if trec is not None:
+        traffic = trec["hbm_bytes_per_launch"].get(dom)
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
+                "kernel": f"k_gemv_{'t' if dom == 'normal_pass1' else 'n'} ({dom})",
+                "algorithmic_bytes_per_launch": bytes_pass, "launches": launches,
+                "avg_launch_ms": round(avg_ms, 4)}
+    sk = {k: prof[k] for k in ("sketch_w", "sketch_y")}
+    sketch_flops = 2.0 * inst.m * inst.n * inst.ell
+    mfma = {}
+    for k, (nl, ms) in sk.items():
+        if nl:
+            tf = sketch_flops / (ms / nl * 1e-3) / 1e12
+            mfma[k] = {"launches": nl, "avg_ms": round(ms / nl, 3), "TFLOPs": round(tf, 1),
+                       "mfma_util_bf16": round(tf / 2500.0, 4)}
+
+    fp64 = None
+    if not args.no_fp64:
+        A64 = A.double()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        x6, y6, z6, info6 = nys.ipm_solve(A64, inst.b, inst.c, inst.q, ell=inst.ell, tol=TOL, seed=args.seed,
+                                          sketch_dtype="f64")
+        torch.cuda.synchronize()
+        t64 = time.perf_counter() - t0
+        fp64 = {"seconds": round(t64, 3), "iters": info6.iters, "pcg_iters": info6.pcg_iters_total,
+                "kkt_rel": info6.kkt_rel,
+                "x_rel_err_vs_planted": float(torch.linalg.norm(x6 - xs) / torch.linalg.norm(xs)),
+                "x_rel_diff_vs_mixed": float(torch.linalg.norm(x6 - x) / torch.linalg.norm(x6)),
+                "speedup_mixed_over_fp64": round(t64 / (ms_per_step / 1000.0), 3)}
+        log(f"fp64: {t64:.2f}s iters={info6.iters} pcg={info6.pcg_iters_total} kkt={info6.kkt_rel:.2e}")
+        del A64
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        D = 1.0 / (inst.q + z / x + info.rho)
+        cpu = cpu_baseline(inst, D, info.delta, info.iters, budget_cols=max(1, inst.n // 100))
+        log(f"cpu baseline: {cpu['value']:.1f}s ({cpu['sample']})")
+
+    rec = {
+        "metric": "time to 1e-6 KKT residual (mixed precision, 1 GPU)",
+        "value": round(ms_per_step / 1000.0, 4),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": False,
+        "scaling": "strong",
+        "vs_baseline": None,
+        "dtype": "f64+f32+bf16",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "m": inst.m, "n": inst.n, "ell": inst.ell,
+                   "A_storage": str(A.dtype).replace("torch.", ""), "sketch": mixed["sketch_dtype"],
+                   "tol": TOL, "instance_seed": args.seed},
+        "accuracy": {"kkt_rel": info.kkt_rel, "rp_rel": info.rp_rel, "rd_rel": info.rd_rel, "mu": info.mu,
+                     "x_rel_err_vs_planted": x_err, "ipm_iters": info.iters,
+                     "pcg_iters": info.pcg_iters_total},
+        "time_split_ms": {"sketch": round(t_sketch, 1), "pcg": round(t_pcg, 1), "other": round(t_other, 1)},
+        "normal_matvec_GBps": {"pass1": round(bytes_pass / (passes["normal_pass1"][1] /
+                                                           max(passes["normal_pass1"][0], 1) * 1e-3) / 1e9, 1),
+                               "pass2": round(bytes_pass / (passes["normal_pass2"][1] /
+                                                           max(passes["normal_pass2"][0], 1) * 1e-3) / 1e9, 1),
+                               "pair": round(pair_gbs, 1)},
+        "roofline": roofline,
+        "sketch_mfma": mfma,
+        "fp64_gpu": fp64,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -84,6 +84,22 @@ const char* nys_last_error(nys_handle h);
    Valid after ipm_solve / ipm_adjoint; otherwise zeros. */
 int nys_last_timing(nys_handle h, double* t_sketch_ms, double* t_pcg_ms, double* t_other_ms);
 
+/* Optional kernel timing with HIP events recorded on the handle's stream
+   around every launch of the kernel classes below (for roofline reports).
+   nys_profile_enable(h, 1) resets the counters and starts recording;
+   nys_profile_read returns launches and summed milliseconds for one class
+   (it waits for the recorded events).  Classes: */
+enum {
+  NYS_K_NORMAL_PASS1 = 0,  /* w = d .* (A^T v): one full read of A            */
+  NYS_K_NORMAL_PASS2 = 1,  /* out = A w + ...: one full read of A             */
+  NYS_K_SKETCH_W = 2,      /* BF16 matrix-core W = d .* (A^T Omega)           */
+  NYS_K_SKETCH_Y = 3,      /* BF16 matrix-core Y = A W                        */
+  NYS_K_GEMM_F64 = 4,      /* FP64 tiles (FP64 sketch, Gram, Cholesky-QR)     */
+  NYS_K_NCLASSES = 5
+};
+int nys_profile_enable(nys_handle h, int enable);
+int nys_profile_read(nys_handle h, int kernel_class, int64_t* launches, double* total_ms);
+
 /* ---------------------------------------------------------------- operators */
 
 /* out = (A diag(d) A^T + delta I) v : the regularised normal-equation operator

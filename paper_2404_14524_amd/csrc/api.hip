@@ -61,6 +61,34 @@ int sync(nys_handle h) {
   return NYS_OK;
 }
 
+int prof_drain(nys_handle h) {
+  nys_prof& p = h->prof;
+  if (p.used == 0) return NYS_OK;
+  NYS_HIP(h, hipEventSynchronize(p.stop[p.used - 1]));
+  for (int i = 0; i < p.used; ++i) {
+    float ms = 0.f;
+    NYS_HIP(h, hipEventElapsedTime(&ms, p.start[i], p.stop[i]));
+    p.total_ms[p.cls[i]] += ms;
+    p.count[p.cls[i]] += 1;
+  }
+  p.used = 0;
+  return NYS_OK;
+}
+
+int prof_begin(nys_handle h, int kclass) {
+  nys_prof& p = h->prof;
+  if (!p.on) return -1;
+  if (p.used == (int)p.start.size() && prof_drain(h) < 0) return -1;
+  const int s = p.used++;
+  p.cls[s] = kclass;
+  if (hipEventRecord(p.start[s], h->stream) != hipSuccess) return -1;
+  return s;
+}
+
+void prof_end(nys_handle h, int slot) {
+  if (slot >= 0) (void)hipEventRecord(h->prof.stop[slot], h->stream);
+}
+
 namespace {
 
 // ---------------------------------------------------------------- small kernels
@@ -287,6 +315,12 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
   }
   NYS_CHECK(read_scalars(h, 0, SC_RED0));
   out.iters = (int)h->hscal[SC_ITERS];
+  if (h->prof.on && it > out.iters) {
+    // launches after convergence returned at once: not reads of A
+    NYS_CHECK(prof_drain(h));
+    h->prof.count[NYS_K_NORMAL_PASS1] -= it - out.iters;
+    h->prof.count[NYS_K_NORMAL_PASS2] -= it - out.iters;
+  }
   if (!final_res_known) {
     NYS_CHECK(true_residual(tmp));
     NYS_CHECK(read_scalars(h, SC_RED0 + 1, 1));
@@ -489,10 +523,46 @@ extern "C" int nys_create(nys_handle* out, int device, void* stream) {
   return NYS_OK;
 }
 
+extern "C" int nys_profile_enable(nys_handle h, int enable) {
+  if (!h) return NYS_EINVAL;
+  NYS_HIP(h, hipSetDevice(h->device));
+  nys_prof& p = h->prof;
+  if (enable && p.start.empty()) {
+    const int cap = 2048;
+    p.start.resize(cap);
+    p.stop.resize(cap);
+    p.cls.resize(cap);
+    for (int i = 0; i < cap; ++i) {
+      NYS_HIP(h, hipEventCreate(&p.start[i]));
+      NYS_HIP(h, hipEventCreate(&p.stop[i]));
+    }
+  }
+  NYS_CHECK(prof_drain(h));
+  for (int k = 0; k < NYS_K_NCLASSES; ++k) {
+    p.total_ms[k] = 0.0;
+    p.count[k] = 0;
+  }
+  p.on = enable != 0;
+  return NYS_OK;
+}
+
+extern "C" int nys_profile_read(nys_handle h, int kclass, int64_t* launches, double* total_ms) {
+  if (!h || kclass < 0 || kclass >= NYS_K_NCLASSES) return NYS_EINVAL;
+  NYS_HIP(h, hipSetDevice(h->device));
+  NYS_CHECK(prof_drain(h));
+  if (launches) *launches = h->prof.count[kclass];
+  if (total_ms) *total_ms = h->prof.total_ms[kclass];
+  return NYS_OK;
+}
+
 extern "C" int nys_destroy(nys_handle h) {
   if (!h) return NYS_OK;
   (void)hipSetDevice(h->device);
   (void)hipStreamSynchronize(h->stream);
+  for (size_t i = 0; i < h->prof.start.size(); ++i) {
+    (void)hipEventDestroy(h->prof.start[i]);
+    (void)hipEventDestroy(h->prof.stop[i]);
+  }
   for (int s = 0; s < WS_NSLOTS; ++s)
     if (h->slot_ptr[s]) (void)hipFree(h->slot_ptr[s]);
   if (h->counters) (void)hipFree(h->counters);

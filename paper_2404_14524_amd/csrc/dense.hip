@@ -373,11 +373,13 @@ int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64
     NYS_CHECK(gemm_dispatch<F64>(h, transA, transB, g1, M, N, K, A, lda, B, ldb, C, ldc, nullptr, GBK));
     return NYS_OK;
   }
+  const int ps = prof_begin(h, NYS_K_GEMM_F64);
   switch (adt) {
     case NYS_F64: NYS_CHECK(gemm_dispatch<F64>(h, transA, transB, g, M, N, K, A, lda, B, ldb, out, ldo, rs, klen)); break;
     case NYS_F32: NYS_CHECK(gemm_dispatch<F32>(h, transA, transB, g, M, N, K, A, lda, B, ldb, out, ldo, rs, klen)); break;
     default: NYS_CHECK(gemm_dispatch<BF16>(h, transA, transB, g, M, N, K, A, lda, B, ldb, out, ldo, rs, klen)); break;
   }
+  prof_end(h, ps);
   if (nsplit > 1) {
     hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(M * N)), dim3(NYS_BLOCK), 0, h->stream, M, N,
                        (int)nsplit, out, C, ldc, row_scale);

@@ -301,12 +301,14 @@ int gemv_t(nys_handle h, const GemvT& a) {
   }
   dim3 g((unsigned)ncol, (unsigned)nch);
   const bool vl = vec_ok(A);
+  const int ps = prof_begin(h, NYS_K_NORMAL_PASS1);
   switch (A->dtype) {
     case NYS_F64: dispatch_t<F64>(g, k, fused, vl, h->stream); break;
     case NYS_F32: dispatch_t<F32>(g, k, fused, vl, h->stream); break;
     case NYS_BF16: dispatch_t<BF16>(g, k, fused, vl, h->stream); break;
     default: return set_error(h, NYS_EINVAL, "gemv_t: bad dtype");
   }
+  prof_end(h, ps);
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }
@@ -333,12 +335,14 @@ int gemv_n(nys_handle h, const GemvN& a) {
     k.cnt = h->counters;
   }
   const bool vl = vec_ok(A) && ((uintptr_t)a.w % 16 == 0);
+  const int ps = prof_begin(h, NYS_K_NORMAL_PASS2);
   switch (A->dtype) {
     case NYS_F64: dispatch_n<F64>(k, vl, h->stream); break;
     case NYS_F32: dispatch_n<F32>(k, vl, h->stream); break;
     case NYS_BF16: dispatch_n<BF16>(k, vl, h->stream); break;
     default: return set_error(h, NYS_EINVAL, "gemv_n: bad dtype");
   }
+  prof_end(h, ps);
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }

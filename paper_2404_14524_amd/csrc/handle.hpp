@@ -50,8 +50,19 @@ enum nys_scal {
   SC_NSCAL = SC_RED0 + 16
 };
 
+// Event pairs recorded around profiled launches; drained into per-class sums.
+struct nys_prof {
+  bool on = false;
+  std::vector<hipEvent_t> start, stop;
+  std::vector<int> cls;
+  int used = 0;
+  double total_ms[NYS_K_NCLASSES] = {};
+  int64_t count[NYS_K_NCLASSES] = {};
+};
+
 struct nys_handle_s {
   int device = 0;
+  nys_prof prof;
   hipStream_t stream = nullptr;
   std::string err;
   void* slot_ptr[WS_NSLOTS] = {};
@@ -76,6 +87,10 @@ inline int ws(nys_handle h, int slot, size_t count, T** out) {
 // Copy `count` device scalars starting at index `first` to h->hscal and wait.
 int read_scalars(nys_handle h, int first, int count);
 int sync(nys_handle h);
+// Profiling: prof_begin returns a slot (or -1 when off); prof_end closes it.
+int prof_begin(nys_handle h, int kclass);
+void prof_end(nys_handle h, int slot);
+int prof_drain(nys_handle h);
 
 }  // namespace nys
 

@@ -204,8 +204,10 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
   {
     dim3 g((unsigned)((n + TBN - 1) / TBN), (unsigned)((ell + TBM - 1) / TBM), 1);
     EpiWt epi{Wt, ldw, d};
+    const int ps = prof_begin(h, NYS_K_SKETCH_W);
     hipLaunchKernelGGL((k_mfma_gemm<false, EpiWt>), g, dim3(NYS_BLOCK), 0, h->stream, (int64_t)ell, n, m,
                        (const uint16_t*)Ot, ldo, Ad, A->ld, m, true, vecA, epi);
+    prof_end(h, ps);
     NYS_LAUNCH_CHECK(h);
   }
   // Y (m x ell) = A (m x n) * Wt^T ("NT"), split over n
@@ -219,8 +221,10 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
     NYS_CHECK(ws_get(h, WS_SK_SPLIT, (size_t)nsplit * m * ell * sizeof(float), (void**)&part));
     dim3 g((unsigned)((ell + TBN - 1) / TBN), (unsigned)((m + TBM - 1) / TBM), (unsigned)nsplit);
     EpiPart epi{part, m, ell};
+    const int ps = prof_begin(h, NYS_K_SKETCH_Y);
     hipLaunchKernelGGL((k_mfma_gemm<true, EpiPart>), g, dim3(NYS_BLOCK), 0, h->stream, m, (int64_t)ell, n,
                        Ad, A->ld, (const uint16_t*)Wt, ldw, klen, vecA, true, epi);
+    prof_end(h, ps);
     NYS_LAUNCH_CHECK(h);
     hipLaunchKernelGGL(k_split_sum, dim3(grid1d(m * ell)), dim3(NYS_BLOCK), 0, h->stream, part, (int)nsplit,
                        m * ell, Y);

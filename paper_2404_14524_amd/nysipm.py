@@ -70,6 +70,7 @@ class nys_ipm_info(C.Structure):
 
 
 EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
+           "nys_profile_enable", "nys_profile_read",
            "nys_normal_apply", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint"]
 
@@ -95,6 +96,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
             "nys_destroy": [vp],
             "nys_set_stream": [vp, vp],
             "nys_last_timing": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)],
+            "nys_profile_enable": [vp, C.c_int],
+            "nys_profile_read": [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)],
             "nys_normal_apply": [vp, pm, vp, dbl, vp, vp],
             "nys_test_matrix": [vp, i64, i32, u64, u64, vp],
             "nys_sketch_product": [vp, pm, vp, vp, i32, C.c_int, vp],
@@ -346,3 +349,23 @@ def nys_last_timing(device="cuda"):
     a, b, c = C.c_double(), C.c_double(), C.c_double()
     lib.nys_last_timing(h, C.byref(a), C.byref(b), C.byref(c))
     return a.value, b.value, c.value
+
+
+KERNEL_CLASSES = {"normal_pass1": 0, "normal_pass2": 1, "sketch_w": 2, "sketch_y": 3, "gemm_f64": 4}
+
+
+def nys_profile_enable(enable: bool = True, device="cuda"):
+    """Start (and reset) or stop HIP-event timing of the library's kernel classes."""
+    lib, h = _handle(torch.device(device))
+    _check(lib, h, lib.nys_profile_enable(h, int(bool(enable))))
+
+
+def nys_profile_read(device="cuda") -> dict:
+    """{class name: (launches, total milliseconds)} since nys_profile_enable."""
+    lib, h = _handle(torch.device(device))
+    out = {}
+    for name, k in KERNEL_CLASSES.items():
+        n, ms = C.c_int64(), C.c_double()
+        _check(lib, h, lib.nys_profile_read(h, k, C.byref(n), C.byref(ms)))
+        out[name] = (int(n.value), float(ms.value))
+    return out

@@ -10,8 +10,10 @@
 // * parameter update: zeta <- x, lambda <- y every iteration and
 //   rho = delta = max(5e-10, min(rho, mu)).
 // * stopping test: max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
-// * inner tolerance: ||xi - M dy|| <= max(1e-12 ||xi||, min(1e-2 ||xi||, 0.1 mu))
-//   on the true residual (the theory asks for a residual of order mu).
+// * inner tolerance: ||xi - M dy|| <= max(1e-12 ||xi||, min(1e-2 ||xi||, tau)) with
+//   tau = max(0.1 mu, 0.01 tol (1 + ||b||)), judged on the true residual (the
+//   theory asks for a residual of order mu; the floor keeps solves from being
+//   asked for accuracy that the primal-feasibility target cannot use).
 // * a fresh test matrix per iteration (Philox key = seed, counter = k), shared
 //   by predictor and corrector.
 
@@ -427,11 +429,14 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     // predictor
     NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, m, PredM{Rp, rp, y, lam, delta}, nullptr));
-    // inner tolerance: max(1e-12 ||xi||, min(cap ||xi||, 0.1 mu)), cap = pcg.rtol or 1e-2
+    // inner tolerance: max(1e-12 ||xi||, min(cap ||xi||, tau)), cap = pcg.rtol or 1e-2,
+    // tau = max(0.1 mu, 0.01 tol (1 + ||b||)): the normal-equation residual enters
+    // only the primal block of the Newton system (Proposition 3.1), so no solve is
+    // asked for a residual far below what the primal-feasibility target needs.
+    const double tau = std::max(0.1 * mu, 0.01 * o.tol * (1.0 + bnorm));
     nys_pcg_info pi{};
     auto t0 = clk::now();
-    int rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, Rd, Rp, Rxz, &o.pcg, 0.1 * mu, dxp, dyp,
-                        dzp, &pi);
+    int rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp, &pi);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;
@@ -450,8 +455,8 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     // corrector
     NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut}, nullptr));
     t0 = clk::now();
-    rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, nullptr, nullptr, Rxz, &o.pcg, 0.1 * mu, dxc,
-                    dyc, dzc, &pi);
+    rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, nullptr, nullptr, Rxz, &o.pcg, tau, dxc, dyc,
+                    dzc, &pi);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;

@@ -508,10 +508,7 @@ extern "C" int nys_create(nys_handle* out, int device, void* stream) {
     delete h;
     return NYS_EHIP;
   }
-  h->ncounters = 1 << 16;
-  if (hipMalloc(&h->counters, h->ncounters * sizeof(unsigned)) != hipSuccess ||
-      hipMemset(h->counters, 0, h->ncounters * sizeof(unsigned)) != hipSuccess ||
-      hipMalloc(&h->dscal, SC_NSCAL * sizeof(double)) != hipSuccess ||
+  if (hipMalloc(&h->dscal, SC_NSCAL * sizeof(double)) != hipSuccess ||
       hipMemset(h->dscal, 0, SC_NSCAL * sizeof(double)) != hipSuccess ||
       hipHostMalloc(&h->hscal, SC_NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
@@ -565,7 +562,6 @@ extern "C" int nys_destroy(nys_handle h) {
   }
   for (int s = 0; s < WS_NSLOTS; ++s)
     if (h->slot_ptr[s]) (void)hipFree(h->slot_ptr[s]);
-  if (h->counters) (void)hipFree(h->counters);
   if (h->dscal) (void)hipFree(h->dscal);
   if (h->hscal) (void)hipHostFree(h->hscal);
   delete h;

@@ -118,22 +118,4 @@ __device__ __forceinline__ void block_min(double* v, double* smem) {
   __syncthreads();
 }
 
-// "Last block done" election for two-stage reductions without a second launch.
-// Every block calls this once after writing its partial results; it returns
-// true in exactly one block (the last to arrive), after which that block may
-// read every other block's partials.  The counter is reset for the next launch.
-__device__ __forceinline__ bool last_block_arrives(unsigned* counter, unsigned nblocks) {
-  __shared__ bool is_last;
-  __threadfence();
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    unsigned prev = __hip_atomic_fetch_add(counter, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == nblocks - 1);
-    if (is_last) __hip_atomic_store(counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-  }
-  __syncthreads();
-  if (is_last) __threadfence();
-  return is_last;
-}
-
 }  // namespace nys

@@ -5,13 +5,14 @@
 // Pass 1 (w = d .* A^T v): a 2-D grid of (column tile) x (row chunk) blocks.
 //   Thread t of a block owns VEC consecutive columns (16 bytes of a row) and
 //   walks the rows of its chunk, four rows in flight; v_i is a wave-uniform
-//   value.  Partial column sums go to a workspace array; the last block of a
-//   column tile to finish (arrival counter) sums the chunks in a fixed order,
-//   so the result is deterministic and no second launch is needed.
+//   value.  Partial column sums go to a workspace array and a small second
+//   launch sums the chunks in a fixed order (deterministic).  No device-wide
+//   fence is used anywhere: on gfx950 an agent-scope fence writes back and
+//   invalidates the L2, which would evict w and v for every block.
 // Pass 2 (out = A w + delta v): each block owns RB consecutive rows; every
 //   16-byte piece of w it loads is reused for RB rows.  Row sums are finished
-//   by wave shuffles and LDS.  An optional p^T (M p) dot product is fused in
-//   the same way as pass 1's second stage.
+//   by wave shuffles and LDS.  An optional p^T (M p) dot product is fused as
+//   per-block partials summed by a one-block launch.
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -33,7 +34,6 @@ struct T1Args {
   double sA;
   double* w;
   double* part;
-  unsigned* cnt;
   int rows_per_chunk;
   int nchunks;
 };
@@ -102,33 +102,48 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_t(T1Args a) {
       for (int64_t i = r0 + threadIdx.x; i < r1; i += NYS_BLOCK) a.pnew[i] = a.s[i] + beta * a.pold[i];
   }
 
-  auto finish = [&](int64_t j, double sum) {
-    double val = a.sA * sum + (a.x0 ? a.x0[j] : 0.0);
-    if (a.d) val *= a.d[j];
-    a.w[j] = val;
-  };
-
   if (a.nchunks == 1) {
 #pragma unroll
-    for (int e = 0; e < VEC; ++e)
-      if (col0 + e < a.n) finish(col0 + e, acc[e]);
+    for (int e = 0; e < VEC; ++e) {
+      const int64_t j = col0 + e;
+      if (j < a.n) {
+        double val = a.sA * acc[e] + (a.x0 ? a.x0[j] : 0.0);
+        if (a.d) val *= a.d[j];
+        a.w[j] = val;
+      }
+    }
     return;
   }
   double* mypart = a.part + (int64_t)blockIdx.y * a.n;
 #pragma unroll
   for (int e = 0; e < VEC; ++e)
     if (col0 + e < a.n) mypart[col0 + e] = acc[e];
-  if (last_block_arrives(a.cnt + blockIdx.x, a.nchunks)) {
-#pragma unroll
-    for (int e = 0; e < VEC; ++e) {
-      const int64_t j = col0 + e;
-      if (j < a.n) {
-        double s = 0.0;
-        for (int c = 0; c < a.nchunks; ++c) s += __builtin_nontemporal_load(a.part + (int64_t)c * a.n + j);
-        finish(j, s);
-      }
-    }
+}
+
+// Second stage of pass 1: w[j] = d[j] * (sA * sum_c part[c][j] + x0[j]), chunks
+// summed in a fixed order (deterministic).  A separate launch: the kernel
+// boundary orders the partial sums, so no device-wide fence is needed.
+__global__ __launch_bounds__(NYS_BLOCK) void k_gemv_t_finish(T1Args a) {
+  if (a.skip && *a.skip != 0.0) return;
+  for (int64_t j = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; j < a.n;
+       j += (int64_t)gridDim.x * NYS_BLOCK) {
+    double s = 0.0;
+    for (int c = 0; c < a.nchunks; ++c) s += a.part[(int64_t)c * a.n + j];
+    double val = a.sA * s + (a.x0 ? a.x0[j] : 0.0);
+    if (a.d) val *= a.d[j];
+    a.w[j] = val;
   }
+}
+
+// Sum of per-block partials into one device word (one block, fixed order).
+__global__ __launch_bounds__(NYS_BLOCK) void k_sum_partials(const double* skip, const double* part,
+                                                            int nb, double* out) {
+  __shared__ double smem[NYS_BLOCK / NYS_WAVE];
+  if (skip && *skip != 0.0) return;
+  double s[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += NYS_BLOCK) s[0] += part[b];
+  block_sum<1>(s, smem);
+  if (threadIdx.x == 0) *out = s[0];
 }
 
 struct T2Args {
@@ -142,7 +157,6 @@ struct T2Args {
   double* out;
   double* dot_out;
   double* dpart;
-  unsigned* cnt;
 };
 
 template <class T, int RB, bool VECLOAD>
@@ -206,14 +220,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
       }
     }
   }
-  if (!a.dot_out) return;
-  if (threadIdx.x == 0) a.dpart[blockIdx.x] = dotc;
-  if (last_block_arrives(a.cnt, gridDim.x)) {
-    double s[1] = {0.0};
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += NYS_BLOCK) s[0] += a.dpart[b];
-    block_sum<1>(s, smem);
-    if (threadIdx.x == 0) *a.dot_out = s[0];
-  }
+  if (a.dot_out && threadIdx.x == 0) a.dpart[blockIdx.x] = dotc;
 }
 
 int elem_size(nys_dtype dt) { return dt == NYS_F64 ? 8 : dt == NYS_F32 ? 4 : 2; }
@@ -293,12 +300,7 @@ int gemv_t(nys_handle h, const GemvT& a) {
   k.w = a.w;
   k.rows_per_chunk = (int)rpc;
   k.nchunks = (int)nch;
-  if (nch > 1) {
-    NYS_CHECK(ws(h, WS_PART, (size_t)nch * A->n, &k.part));
-    if ((size_t)ncol > h->ncounters)
-      return set_error(h, NYS_EINVAL, "gemv_t: %lld column tiles exceed the counter array", (long long)ncol);
-    k.cnt = h->counters;
-  }
+  if (nch > 1) NYS_CHECK(ws(h, WS_PART, (size_t)nch * A->n, &k.part));
   dim3 g((unsigned)ncol, (unsigned)nch);
   const bool vl = vec_ok(A);
   const int ps = prof_begin(h, NYS_K_NORMAL_PASS1);
@@ -310,6 +312,11 @@ int gemv_t(nys_handle h, const GemvT& a) {
   }
   prof_end(h, ps);
   NYS_LAUNCH_CHECK(h);
+  if (nch > 1 && A->n > 0) {
+    const int64_t nb = std::min<int64_t>((A->n + NYS_BLOCK - 1) / NYS_BLOCK, 4096);
+    hipLaunchKernelGGL(k_gemv_t_finish, dim3((unsigned)nb), dim3(NYS_BLOCK), 0, h->stream, k);
+    NYS_LAUNCH_CHECK(h);
+  }
   return NYS_OK;
 }
 
@@ -330,10 +337,8 @@ int gemv_n(nys_handle h, const GemvN& a) {
   k.sV = a.sV;
   k.out = a.out;
   k.dot_out = a.dot_out;
-  if (a.dot_out) {
-    NYS_CHECK(ws(h, WS_PART2, (size_t)n_blocks_pass2(A->m), &k.dpart));
-    k.cnt = h->counters;
-  }
+  const int nbp = n_blocks_pass2(A->m);
+  if (a.dot_out) NYS_CHECK(ws(h, WS_PART2, (size_t)nbp, &k.dpart));
   const bool vl = vec_ok(A) && ((uintptr_t)a.w % 16 == 0);
   const int ps = prof_begin(h, NYS_K_NORMAL_PASS2);
   switch (A->dtype) {
@@ -344,6 +349,11 @@ int gemv_n(nys_handle h, const GemvN& a) {
   }
   prof_end(h, ps);
   NYS_LAUNCH_CHECK(h);
+  if (a.dot_out) {
+    hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(NYS_BLOCK), 0, h->stream, a.skip,
+                       (const double*)k.dpart, nbp, a.dot_out);
+    NYS_LAUNCH_CHECK(h);
+  }
   return NYS_OK;
 }
 

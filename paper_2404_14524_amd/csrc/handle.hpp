@@ -67,8 +67,6 @@ struct nys_handle_s {
   std::string err;
   void* slot_ptr[WS_NSLOTS] = {};
   size_t slot_bytes[WS_NSLOTS] = {};
-  unsigned* counters = nullptr;   // zero-initialised arrival counters
-  size_t ncounters = 0;
   double* dscal = nullptr;        // device scalars
   double* hscal = nullptr;        // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr;

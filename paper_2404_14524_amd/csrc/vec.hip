@@ -49,8 +49,7 @@ struct BadF {
 
 template <class T>
 __global__ __launch_bounds__(NYS_BLOCK) void k_nonfinite(const char* A, int64_t m, int64_t n,
-                                                         int64_t row_bytes, double* part,
-                                                         unsigned* cnt, double* out) {
+                                                         int64_t row_bytes, double* part) {
   using raw = typename T::raw;
   __shared__ double smem[NYS_BLOCK / NYS_WAVE];
   double c[1] = {0.0};
@@ -61,15 +60,12 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_nonfinite(const char* A, int64_t 
   }
   block_sum<1>(c, smem);
   if (threadIdx.x == 0) part[blockIdx.x] = c[0];
-  if (last_block_arrives(cnt, gridDim.x)) {
-    double s[1] = {0.0};
-    for (unsigned b = threadIdx.x; b < gridDim.x; b += NYS_BLOCK) s[0] += part[b];
-    block_sum<1>(s, smem);
-    if (threadIdx.x == 0) *out = s[0];
-  }
 }
 
 // ---------------------------------------------------------------- PCG / P^{-1}
+// Every reduction below is two launches: per-block partials, then a one-block
+// kernel that combines them in block order (deterministic) and advances the
+// scalar recurrences held in device words.
 // Rows per block of the update/reduce kernel (one row per thread in phase 1).
 constexpr int RBU = NYS_BLOCK;
 
@@ -85,15 +81,26 @@ struct UpdArgs {
   double delta;
   double* t;            // PRECOND: ell-vector result
   double* scal;         // device scalar block
-  double* part;
-  unsigned* cnt;
+  double* part;         // per block: ell partial sums of U^T r, then ||r||^2
 };
 
-// UPDATE:  alpha = rs/pq (0 once done; breakdown if pq <= 0 or not finite);
-//          y += alpha p; r -= alpha q.
-// PRECOND: t = f .* (U^T r), f_k = (lam_l + delta)/(lam_k + delta) - 1.
-// !PRECOND (plain CG, UPDATE only): rs_new = ||r||^2, beta = rs_new/rs.
-// Always: ||r||^2 -> scal[SC_RR]; done when ||r||^2 <= tol2.
+// alpha = rs/pq, zero once done; breakdown when pq <= 0 or alpha not finite.
+__device__ __forceinline__ double pcg_alpha(const double* scal, bool* done0, bool* brk) {
+  *done0 = scal[SC_DONE] != 0.0;
+  *brk = false;
+  if (*done0) return 0.0;
+  const double pq = scal[SC_PQ], rs = scal[SC_RS];
+  const double al = rs / pq;
+  if (!(pq > 0.0) || !isfinite(al)) {
+    *brk = true;
+    return 0.0;
+  }
+  return al;
+}
+
+// UPDATE:  y += alpha p; r -= alpha q.
+// PRECOND: partial sums of U^T r over this block's rows.
+// Always:  partial ||r||^2.
 template <bool UPDATE, bool PRECOND>
 __global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update(UpdArgs a) {
   __shared__ double rl[RBU];
@@ -101,15 +108,9 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update(UpdArgs a) {
   const int64_t r0 = (int64_t)blockIdx.x * RBU;
   const int nr = (int)min((int64_t)RBU, a.m - r0);
   double alpha = 0.0;
-  bool done0 = false, brk = false;
   if constexpr (UPDATE) {
-    done0 = a.scal[SC_DONE] != 0.0;
-    const double pq = a.scal[SC_PQ], rs = a.scal[SC_RS];
-    if (!done0) {
-      const double al = rs / pq;
-      if (!(pq > 0.0) || !isfinite(al)) brk = true;
-      else alpha = al;
-    }
+    bool done0, brk;
+    alpha = pcg_alpha(a.scal, &done0, &brk);
   }
   double rr[1] = {0.0};
   if (threadIdx.x < nr) {
@@ -137,11 +138,18 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update(UpdArgs a) {
     }
   }
   if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * (ell + 1) + ell] = rr[0];
-  if (!last_block_arrives(a.cnt, gridDim.x)) return;
-  // ---- last block: finish the reductions and the scalar recurrences
-  const int nb = gridDim.x;
+}
+
+// One block.  PRECOND: t = f .* sum(partials), f_k = (lam_l + delta)/(lam_k + delta) - 1
+// with lam_l = min lam.  ||r||^2 -> SC_RR.  UPDATE: iteration count, done when
+// ||r||^2 <= tol2, breakdown flag; without a preconditioner also rs = ||r||^2
+// and beta = rs_new/rs (zero once done).
+template <bool UPDATE, bool PRECOND>
+__global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update_finish(UpdArgs a, int nb) {
+  __shared__ double smem[NYS_BLOCK / NYS_WAVE];
+  __shared__ double laml;
+  const int ell = PRECOND ? a.ell : 0;
   if constexpr (PRECOND) {
-    __shared__ double laml;
     if (threadIdx.x == 0) {
       double mn = a.lam[0];
       for (int k = 1; k < ell; ++k) mn = fmin(mn, a.lam[k]);
@@ -162,6 +170,8 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update(UpdArgs a) {
     const double rrt = s1[0];
     a.scal[SC_RR] = rrt;
     if constexpr (UPDATE) {
+      bool done0, brk;
+      (void)pcg_alpha(a.scal, &done0, &brk);
       if (!done0) a.scal[SC_ITERS] += 1.0;
       if (brk) {
         a.scal[SC_BREAK] = 1.0;
@@ -189,10 +199,9 @@ struct ExpArgs {
   double* scal;         // PCG: rs_new, beta (else NULL)
   double* dot_out;      // standalone dot (may be NULL)
   double* part;
-  unsigned* cnt;
 };
 
-// out_i = r_i + sum_k U[i,k] t_k (one wave per row); fused r^T out.
+// out_i = r_i + sum_k U[i,k] t_k (one wave per row); per-block partial r^T out.
 __global__ __launch_bounds__(NYS_BLOCK) void k_precond_expand(ExpArgs a) {
   extern __shared__ double tl[];
   __shared__ double smem[NYS_BLOCK / NYS_WAVE];
@@ -217,9 +226,13 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_precond_expand(ExpArgs a) {
   if (!a.scal && !a.dot_out) return;
   block_sum<1>(dotc, smem);
   if (threadIdx.x == 0) a.part[blockIdx.x] = dotc[0];
-  if (!last_block_arrives(a.cnt, gridDim.x)) return;
+}
+
+// One block: r^T s -> dot_out and/or (PCG) beta = rs_new/rs (zero once done), rs = rs_new.
+__global__ __launch_bounds__(NYS_BLOCK) void k_precond_expand_finish(ExpArgs a, int nb) {
+  __shared__ double smem[NYS_BLOCK / NYS_WAVE];
   double s[1] = {0.0};
-  for (unsigned b = threadIdx.x; b < gridDim.x; b += NYS_BLOCK) s[0] += a.part[b];
+  for (int b = threadIdx.x; b < nb; b += NYS_BLOCK) s[0] += a.part[b];
   block_sum<1>(s, smem);
   if (threadIdx.x == 0) {
     if (a.dot_out) *a.dot_out = s[0];
@@ -242,23 +255,32 @@ unsigned expand_blocks(int64_t m) {
 int launch_update(nys_handle h, bool update, bool precond, UpdArgs& k) {
   const unsigned nb = (unsigned)std::max<int64_t>(1, (k.m + RBU - 1) / RBU);
   NYS_CHECK(ws(h, WS_PART, (size_t)nb * ((precond ? k.ell : 0) + 1), &k.part));
-  k.cnt = h->counters;
   k.scal = h->dscal;
-  dim3 g(nb), b(NYS_BLOCK);
-  if (update && precond) hipLaunchKernelGGL((k_pcg_update<true, true>), g, b, 0, h->stream, k);
-  else if (update) hipLaunchKernelGGL((k_pcg_update<true, false>), g, b, 0, h->stream, k);
-  else if (precond) hipLaunchKernelGGL((k_pcg_update<false, true>), g, b, 0, h->stream, k);
-  else hipLaunchKernelGGL((k_pcg_update<false, false>), g, b, 0, h->stream, k);
+  dim3 g(nb), b(NYS_BLOCK), one(1);
+  if (update && precond) {
+    hipLaunchKernelGGL((k_pcg_update<true, true>), g, b, 0, h->stream, k);
+    hipLaunchKernelGGL((k_pcg_update_finish<true, true>), one, b, 0, h->stream, k, (int)nb);
+  } else if (update) {
+    hipLaunchKernelGGL((k_pcg_update<true, false>), g, b, 0, h->stream, k);
+    hipLaunchKernelGGL((k_pcg_update_finish<true, false>), one, b, 0, h->stream, k, (int)nb);
+  } else if (precond) {
+    hipLaunchKernelGGL((k_pcg_update<false, true>), g, b, 0, h->stream, k);
+    hipLaunchKernelGGL((k_pcg_update_finish<false, true>), one, b, 0, h->stream, k, (int)nb);
+  } else {
+    hipLaunchKernelGGL((k_pcg_update<false, false>), g, b, 0, h->stream, k);
+    hipLaunchKernelGGL((k_pcg_update_finish<false, false>), one, b, 0, h->stream, k, (int)nb);
+  }
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }
 
 int launch_expand(nys_handle h, ExpArgs& k) {
   const unsigned nb = expand_blocks(k.m);
-  NYS_CHECK(ws(h, WS_PART, (size_t)nb, &k.part));
-  k.cnt = h->counters;
+  NYS_CHECK(ws(h, WS_PART2, (size_t)nb, &k.part));
   hipLaunchKernelGGL(k_precond_expand, dim3(nb), dim3(NYS_BLOCK), (size_t)k.ell * sizeof(double),
                      h->stream, k);
+  if (k.scal || k.dot_out)
+    hipLaunchKernelGGL(k_precond_expand_finish, dim3(1), dim3(NYS_BLOCK), 0, h->stream, k, (int)nb);
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }
@@ -292,10 +314,12 @@ int count_nonfinite_matrix(nys_handle h, const nys_matrix* A, double* out) {
   const char* p = (const char*)A->data;
   const int64_t rb = A->ld * es;
   switch (A->dtype) {
-    case NYS_F64: hipLaunchKernelGGL(k_nonfinite<F64>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part, h->counters, out); break;
-    case NYS_F32: hipLaunchKernelGGL(k_nonfinite<F32>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part, h->counters, out); break;
-    default: hipLaunchKernelGGL(k_nonfinite<BF16>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part, h->counters, out); break;
+    case NYS_F64: hipLaunchKernelGGL(k_nonfinite<F64>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part); break;
+    case NYS_F32: hipLaunchKernelGGL(k_nonfinite<F32>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part); break;
+    default: hipLaunchKernelGGL(k_nonfinite<BF16>, dim3(nb), dim3(NYS_BLOCK), 0, h->stream, p, A->m, A->n, rb, part); break;
   }
+  hipLaunchKernelGGL((k_map_reduce_finish<1, 0>), dim3(1), dim3(NYS_BLOCK), 0, h->stream, (int)nb,
+                     (const double*)part, out);
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }

@@ -443,6 +443,9 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
       break;
     }
     pcg_total += pi.iters;
+    if (o.verbose)
+      std::fprintf(stderr, "[nysipm]   predictor pcg: iters=%d status=%d |res|=%.2e tau=%.2e\n", pi.iters,
+                   pi.status, pi.true_res, tau);
     NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp}, sc + SC_RED0)));
     NYS_CHECK(read_scalars(h, SC_RED0, 2));
     double ap = STEP * std::min(1.0, h->hscal[SC_RED0]);
@@ -463,6 +466,9 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
       break;
     }
     pcg_total += pi.iters;
+    if (o.verbose)
+      std::fprintf(stderr, "[nysipm]   corrector pcg: iters=%d status=%d |res|=%.2e alpha=(%.3f,%.3f) mu_aff=%.2e\n",
+                   pi.iters, pi.status, pi.true_res, ap, ad, mu_aff);
     NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dxp, dxc}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dzp, dzc}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, m, AddTo{dyp, dyc}, nullptr));

@@ -62,6 +62,66 @@ def load_traffic(workload: str):
     return rec
 
 
+def _db(path):
+    import glob
+    import sqlite3
+    dbs = sorted(glob.glob(os.path.join(path, "**", "*.db"), recursive=True)) if os.path.isdir(path) else [path]
+    if not dbs:
+        raise FileNotFoundError(f"no rocprofv3 database under {path}")
+    return sqlite3.connect(dbs[0])
+
+
+def summarize_trace(db_path: str, out_md: str, command: str, workload: str, m: int, n: int, b_A: int):
+    """Markdown summary of a `rocprofv3 --kernel-trace --stats` database."""
+    con = _db(db_path)
+    rows = con.execute("select name, count(*), avg(duration), min(duration), max(duration), sum(duration) "
+                       "from kernels group by name order by sum(duration) desc limit 15").fetchall()
+    bytes_pass = m * n * b_A
+    lines = [f"# Kernel trace: {workload}", "", f"Command: `{command}`", "",
+             "| kernel | calls | avg µs | min µs | max µs | total ms | GB/s (A once) |",
+             "|---|---|---|---|---|---|---|"]
+    for name, cnt, avg, mn, mx, tot in rows:
+        short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")[:80]
+        gbs = f"{bytes_pass / (avg * 1e-9) / 1e9:.0f}" if ("k_gemv_t<" in name or "k_gemv_n<" in name) else ""
+        lines.append(f"| `{short}` | {cnt} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
+                     f"{tot / 1e6:.2f} | {gbs} |")
+    os.makedirs(os.path.dirname(out_md), exist_ok=True)
+    with open(out_md, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
+def summarize_pmc(fetch_db: str, write_db: str, workload: str, m: int, n: int, b_A: int, command: str):
+    """HBM bytes per launch of the two GEMV passes from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
+    for the plain 2 GiB copy of the same run."""
+    copy_bytes = float(1 << 31)
+    rec = {"workload": workload, "gemv_source_hash": gemv_source_hash(), "command": command,
+           "algorithmic_bytes_per_launch": m * n * b_A, "hbm_bytes_per_launch": {}, "raw_kib": {}}
+    per = {}
+    for counter, path in (("FETCH_SIZE", fetch_db), ("WRITE_SIZE", write_db)):
+        con = _db(path)
+        rows = con.execute("select kernel_name, value from counters_collection where counter_name = ?",
+                           (counter,)).fetchall()
+        copies = [v for k, v in rows if "copy" in k.lower()]
+        ref = max(copies) if copies else None
+        factor = copy_bytes / (ref * 1024.0) if ref else None
+        rec[f"{counter}_copy_kib"] = ref
+        rec[f"{counter}_scale"] = factor
+        for key, tag in (("normal_pass1", "k_gemv_t<"), ("normal_pass2", "k_gemv_n<")):
+            vals = [v for k, v in rows if tag in k]
+            if vals and factor:
+                kib = sum(vals) / len(vals)
+                rec["raw_kib"][f"{key}_{counter}"] = kib
+                per.setdefault(key, 0.0)
+                per[key] += kib * 1024.0 * factor
+    rec["hbm_bytes_per_launch"] = {k: round(v) for k, v in per.items()}
+    out = os.path.join(ROOT, "profiles", f"gemv_traffic_{workload}.json")
+    with open(out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(rec, indent=1))
+
+
 def cpu_baseline(inst, D, delta, gpu_iters, budget_cols: int):
     """The FP64 oracle's per-iteration work on a bounded sample of the same
     instance: the normal matrix from a column sample (the oracle's
@@ -120,7 +180,21 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-loop", type=int, default=0)
     ap.add_argument("--verbose", action="store_true")
+    ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"))
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
+    ap.add_argument("--command", default="")
     args = ap.parse_args()
+    if args.summarize_trace or args.summarize_pmc:
+        from instances import CONFIGS
+        cfg = CONFIGS[args.workload]
+        b_A = 4 if cfg["a_dtype"] == "f32" else 8
+        if args.summarize_trace:
+            summarize_trace(args.summarize_trace[0], args.summarize_trace[1], args.command, args.workload,
+                            cfg["m"], cfg["n"], b_A)
+        if args.summarize_pmc:
+            summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, cfg["m"], cfg["n"], b_A,
+                          args.command)
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
               "(the column-sharded design is described in DESIGN.md)", file=sys.stderr)

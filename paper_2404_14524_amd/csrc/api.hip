@@ -187,7 +187,10 @@ PcgCfg pcg_cfg(const nys_pcg_opts* o, int64_t m) {
     c.replace_every = o->replace_every;
     c.poll_every = o->poll_every;
   }
-  if (c.maxit <= 0) c.maxit = (int)std::min<int64_t>(std::max<int64_t>(m, 1), 2000);
+  // default cap: the dimension (CG's exact-arithmetic bound), at least 2000;
+  // late interior-point systems need thousands of iterations, and a capped,
+  // unconverged direction costs more outer iterations than it saves
+  if (c.maxit <= 0) c.maxit = (int)std::min<int64_t>(std::max<int64_t>(m, 2000), 1 << 30);
   if (c.replace_every <= 0) c.replace_every = 50;
   if (c.poll_every <= 0) c.poll_every = 8;
   if (!(c.rtol >= 0)) c.rtol = 0;

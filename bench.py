@@ -91,7 +91,8 @@ def summarize_trace(db_path: str, out_md: str, command: str, workload: str, m: i
     print("\n".join(lines))
 
 
-def summarize_pmc(fetch_db: str, write_db: str, workload: str, m: int, n: int, b_A: int, command: str):
+def summarize_pmc(fetch_db: str, write_db: str, workload: str, m: int, n: int, b_A: int, command: str,
+                  out: str = ""):
     """HBM bytes per launch of the two GEMV passes from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
     for the plain 2 GiB copy of the same run."""
@@ -116,7 +117,7 @@ def summarize_pmc(fetch_db: str, write_db: str, workload: str, m: int, n: int, b
                 per.setdefault(key, 0.0)
                 per[key] += kib * 1024.0 * factor
     rec["hbm_bytes_per_launch"] = {k: round(v) for k, v in per.items()}
-    out = os.path.join(ROOT, "profiles", f"gemv_traffic_{workload}.json")
+    out = out or os.path.join(ROOT, "profiles", f"gemv_traffic_{workload}.json")
     with open(out, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(rec, indent=1))
@@ -183,6 +184,7 @@ def main():
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"))
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
     ap.add_argument("--command", default="")
+    ap.add_argument("--out", default="")
     args = ap.parse_args()
     if args.summarize_trace or args.summarize_pmc:
         from instances import CONFIGS
@@ -193,7 +195,7 @@ def main():
                             cfg["m"], cfg["n"], b_A)
         if args.summarize_pmc:
             summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.workload, cfg["m"], cfg["n"], b_A,
-                          args.command)
+                          args.command, args.out)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "

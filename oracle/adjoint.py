@@ -67,6 +67,46 @@ def loss(x, x_tgt):
     return 0.5 * float(d @ d), d
 
 
+def fd_gradient_rhs(A, b, c, q, S, x_tgt, block, coords, h_rel=1e-6):
+    """Central differences for the blocks that enter only the right-hand side
+    of the equality-constrained system on S ('c' or 'b'): the same central
+    differences as fd_gradient, with one LU factorisation reused for every
+    perturbed right-hand side (exact re-solves, affordable at m, n in the
+    thousands).  A perturbed c_j with j outside S leaves x unchanged."""
+    m, n = A.shape
+    k = int(S.sum())
+    AS = A[:, S]
+    K = np.zeros((k + m, k + m))
+    K[:k, :k] = np.diag(q[S])
+    K[:k, k:] = -AS.T
+    K[k:, :k] = AS
+    lu = sla.lu_factor(K)
+    base = np.concatenate([-c[S], b])
+    pos = np.full(n, -1)
+    pos[np.flatnonzero(S)] = np.arange(k)
+
+    def loss_of(rhs):
+        sol = sla.lu_solve(lu, rhs)
+        x = np.zeros(n)
+        x[S] = sol[:k]
+        return loss(x, x_tgt)[0]
+
+    out = np.zeros(len(coords))
+    for t, idx in enumerate(coords):
+        theta = float((c if block == "c" else b)[idx])
+        h = h_rel * max(1.0, abs(theta))
+        if block == "c":
+            if pos[idx] < 0:
+                continue
+            e = np.zeros(k + m)
+            e[pos[idx]] = -1.0            # rhs entry is -c_j
+        else:
+            e = np.zeros(k + m)
+            e[k + idx] = 1.0
+        out[t] = (loss_of(base + h * e) - loss_of(base - h * e)) / (2 * h)
+    return out
+
+
 def fd_gradient(A, b, c, q, S, x_tgt, block, coords, h_rel=1e-6):
     """Central differences of L(x*(data)) in the given coordinates of one data
     block ('c', 'b', 'q' or 'A'; coords are flat indices).  Step

@@ -17,6 +17,15 @@
 #include "common.hpp"
 #include "kernels.hpp"
 
+// Pass-1 launch shape: rows in flight per thread, and the block count the
+// row chunking aims for (a few blocks per CU).
+#ifndef NYS_T_UNROLL
+#define NYS_T_UNROLL 4
+#endif
+#ifndef NYS_T_TARGET_BLOCKS
+#define NYS_T_TARGET_BLOCKS 2048
+#endif
+
 namespace nys {
 namespace {
 
@@ -58,25 +67,22 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_t(T1Args a) {
   if (VECLOAD && col0 + VEC <= a.n) {
     const char* p = a.A + r0 * a.row_bytes + col0 * (int64_t)sizeof(raw);
     int64_t i = r0;
-    for (; i + 4 <= r1; i += 4) {
-      const u32x4 u0 = ld_stream16(p);
-      const u32x4 u1 = ld_stream16(p + a.row_bytes);
-      const u32x4 u2 = ld_stream16(p + 2 * a.row_bytes);
-      const u32x4 u3 = ld_stream16(p + 3 * a.row_bytes);
-      const double v0 = rowv(i), v1 = rowv(i + 1), v2 = rowv(i + 2), v3 = rowv(i + 3);
-      double e0[VEC], e1[VEC], e2[VEC], e3[VEC];
-      Unpack<T>::run(u0, e0);
-      Unpack<T>::run(u1, e1);
-      Unpack<T>::run(u2, e2);
-      Unpack<T>::run(u3, e3);
+    constexpr int U = NYS_T_UNROLL;     // rows in flight per thread
+    for (; i + U <= r1; i += U) {
+      u32x4 uu[U];
 #pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        acc[e] = fma(e0[e], v0, acc[e]);
-        acc[e] = fma(e1[e], v1, acc[e]);
-        acc[e] = fma(e2[e], v2, acc[e]);
-        acc[e] = fma(e3[e], v3, acc[e]);
+      for (int t = 0; t < U; ++t) uu[t] = ld_stream16(p + t * a.row_bytes);
+      double vv[U];
+#pragma unroll
+      for (int t = 0; t < U; ++t) vv[t] = rowv(i + t);
+#pragma unroll
+      for (int t = 0; t < U; ++t) {
+        double e0[VEC];
+        Unpack<T>::run(uu[t], e0);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) acc[e] = fma(e0[e], vv[t], acc[e]);
       }
-      p += 4 * a.row_bytes;
+      p += U * a.row_bytes;
     }
     for (; i < r1; ++i) {
       const u32x4 u0 = ld_stream16(p);
@@ -279,9 +285,10 @@ int gemv_t(nys_handle h, const GemvT& a) {
   const int64_t ncol =
       std::max<int64_t>(1, (A->n + (int64_t)NYS_BLOCK * vec - 1) / ((int64_t)NYS_BLOCK * vec));
   // enough blocks to cover the chip several times, rows per chunk >= 32
-  int64_t nch = std::max<int64_t>(1, std::min<int64_t>((A->m + 31) / 32, (2048 + ncol - 1) / ncol));
+  int64_t nch = std::max<int64_t>(
+      1, std::min<int64_t>((A->m + 31) / 32, (NYS_T_TARGET_BLOCKS + ncol - 1) / ncol));
   int64_t rpc = (A->m + nch - 1) / nch;
-  rpc = std::max<int64_t>(4, (rpc + 3) / 4 * 4);
+  rpc = std::max<int64_t>(NYS_T_UNROLL, (rpc + NYS_T_UNROLL - 1) / NYS_T_UNROLL * NYS_T_UNROLL);
   nch = std::max<int64_t>(1, (A->m + rpc - 1) / rpc);
   T1Args k{};
   k.skip = a.skip;

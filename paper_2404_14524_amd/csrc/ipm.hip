@@ -11,7 +11,7 @@
 //   rho = delta = max(5e-10, min(rho, mu)).
 // * stopping test: max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
 // * inner tolerance: ||xi - M dy|| <= max(1e-12 ||xi||, min(1e-2 ||xi||, tau)) with
-//   tau = max(0.1 mu, 0.01 tol (1 + ||b||)), judged on the true residual (the
+//   tau = max(0.1 mu, 0.1 tol (1 + ||b||)), judged on the true residual (the
 //   theory asks for a residual of order mu; the floor keeps solves from being
 //   asked for accuracy that the primal-feasibility target cannot use).
 // * a fresh test matrix per iteration (Philox key = seed, counter = k), shared
@@ -430,10 +430,10 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, m, PredM{Rp, rp, y, lam, delta}, nullptr));
     // inner tolerance: max(1e-12 ||xi||, min(cap ||xi||, tau)), cap = pcg.rtol or 1e-2,
-    // tau = max(0.1 mu, 0.01 tol (1 + ||b||)): the normal-equation residual enters
+    // tau = max(0.1 mu, 0.1 tol (1 + ||b||)): the normal-equation residual enters
     // only the primal block of the Newton system (Proposition 3.1), so no solve is
-    // asked for a residual far below what the primal-feasibility target needs.
-    const double tau = std::max(0.1 * mu, 0.01 * o.tol * (1.0 + bnorm));
+    // asked for a residual below a tenth of the primal-feasibility target.
+    const double tau = std::max(0.1 * mu, 0.1 * o.tol * (1.0 + bnorm));
     nys_pcg_info pi{};
     auto t0 = clk::now();
     int rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp, &pi);

@@ -1,0 +1,145 @@
+"""GPU parity at the workloads' full sizes, in the launch configuration that
+bench.py times (same instance generator, same storage, same entry points).
+
+The oracle cannot run the full IP-PMM at these sizes, so the checks are:
+* the normal-equation operator on every output entry, the oracle computing
+  A (d .* (A^T v)) + delta v in FP64 from the same matrix, panel by panel;
+* the BF16 matrix-core sketch on sampled columns of Y (column c of Y depends
+  only on column c of Omega, and the BF16 rounding of W is element-wise, so
+  the emulated oracle reproduces sampled columns exactly up to accumulation);
+* the full solve through properties that hold at any size: KKT <= 1e-6 and
+  the planted optimum (which is the oracle's optimum, pinned on the CPU).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from instances import make_instance
+from oracle import lowprec
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module")
+def nys():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_14524_amd as pkg
+    return pkg
+
+
+def _oracle_normal_apply(A_dev, d, delta, v, panel=1000):
+    """FP64 A (d .* (A^T v)) + delta v from a host copy of the device matrix,
+    promoted to FP64 one row panel at a time."""
+    Ah = A_dev.cpu().numpy()
+    m, n = Ah.shape
+    w = np.zeros(n)
+    for i0 in range(0, m, panel):
+        P = Ah[i0:i0 + panel].astype(np.float64)
+        w += P.T @ v[i0:i0 + panel]
+    w *= d
+    out = np.empty(m)
+    bound = np.empty(m)
+    aw = np.abs(w)
+    for i0 in range(0, m, panel):
+        P = Ah[i0:i0 + panel].astype(np.float64)
+        out[i0:i0 + panel] = P @ w + delta * v[i0:i0 + panel]
+        bound[i0:i0 + panel] = np.abs(P) @ aw + abs(delta) * np.abs(v[i0:i0 + panel])
+    return out, bound
+
+
+@pytest.mark.parametrize("name", ["lowrank_5000x20000", "lowrank_20000x100000"])
+def test_normal_apply_full_size(nys, name):
+    print(f"full-size normal_apply {name}", flush=True)
+    inst = make_instance(name, seed=0, device=DEV)
+    m, n = inst.m, inst.n
+    g = torch.Generator(device=DEV)
+    g.manual_seed(7)
+    d = torch.rand(n, generator=g, dtype=torch.float64, device=DEV) * 3.0
+    v = torch.randn(m, generator=g, dtype=torch.float64, device=DEV)
+    out = nys.nys_normal_apply(inst.A, d, 1e-3, v).cpu().numpy()
+    ref, bound = _oracle_normal_apply(inst.A, d.cpu().numpy(), 1e-3, v.cpu().numpy())
+    # |A| (|d| |A^T v|) bounds the rounding of the second product; the first
+    # product's rounding is bounded through |A^T v| <= |A|^T |v| below
+    assert np.all(np.abs(out - ref) <= 1e-11 * bound + 1e-300)
+    del inst
+    torch.cuda.empty_cache()
+
+
+def test_sketch_bf16_full_size_sampled_columns(nys):
+    name = "lowrank_20000x100000"
+    print(f"full-size BF16 sketch {name}", flush=True)
+    inst = make_instance(name, seed=0, device=DEV)
+    m, n, ell = inst.m, inst.n, inst.ell
+    Abf = inst.A.to(torch.bfloat16)
+    g = torch.Generator(device=DEV)
+    g.manual_seed(3)
+    d = torch.rand(n, generator=g, dtype=torch.float64, device=DEV) * 2.0
+    Om = torch.randn((m, ell), generator=g, dtype=torch.float64, device=DEV) / np.sqrt(m)
+    Y = nys.nys_sketch_product(Abf, d, Om, "bf16")
+    cols = [0, 57, 123, ell - 1]
+    Ab = Abf.double()                      # exact promotion of the BF16 values
+    Omb = torch.from_numpy(lowprec.round_bf16(Om[:, cols].cpu().numpy())).to(DEV)
+    dn = d.cpu().numpy()
+    for t, c in enumerate(cols):
+        wc = (Ab.T @ Omb[:, t]).cpu().numpy() * dn          # FP64 products on the exact values
+        wb = torch.from_numpy(lowprec.round_bf16(wc)).to(DEV)
+        ref = (Ab @ wb).cpu().numpy()
+        got = Y[:, c].cpu().numpy()
+        assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref), c
+    del Ab, Abf, inst
+    torch.cuda.empty_cache()
+
+
+def test_adjoint_full_size_differentiation_workload(nys):
+    """gauss_2000x8000 (FP32 A, FP32-stored products accumulated in FP64, FP64
+    scalars): loss 1/2 ||x* - x_tgt||^2 with x_tgt = x* + 0.01 N(0,1).  The GPU
+    adjoint after a 1e-6 solve against (i) the oracle's dense reduced-KKT
+    gradient for every entry of dL/dc, dL/db, dL/dq and 4096 entries of dL/dA,
+    and (ii) FP64 central differences through exact re-solves on 64 random
+    coordinates of c and of b."""
+    from oracle import adjoint as oadj
+    print("full-size adjoint gauss_2000x8000", flush=True)
+    inst = make_instance("gauss_2000x8000", seed=0, device="cpu")
+    A = inst.A.double().numpy()
+    b, c, q = inst.b.numpy(), inst.c.numpy(), inst.q.numpy()
+    xs, ys, zs = inst.x_star.numpy(), inst.y_star.numpy(), inst.z_star.numpy()
+    At = inst.A.to(DEV)
+    tb, tc, tq = (torch.from_numpy(v).to(DEV) for v in (b, c, q))
+    x, y, z, info = nys.ipm_solve(At, tb, tc, tq, ell=inst.ell, tol=1e-6, seed=0)
+    assert info.status == 0
+    x_tgt = xs + 0.01 * np.random.default_rng(0).standard_normal(xs.shape)
+    g = x.cpu().numpy() - x_tgt
+    grads, pinfo = nys.ipm_adjoint(At, tb, tc, tq, x, y, z, info.rho, info.delta,
+                                   torch.from_numpy(g).to(DEV), ell=inst.ell)
+    ref = oadj.kkt_gradient(A, b, c, q, xs, ys, zs, xs - x_tgt)
+    for k in ("c", "b", "q"):
+        e, gk = ref[k], grads[k].cpu().numpy()
+        assert np.linalg.norm(gk - e) <= 1e-4 * np.linalg.norm(e), k
+    rng = np.random.default_rng(1)
+    idx = rng.choice(A.size, 4096, replace=False)
+    gA = grads["A"].cpu().numpy().reshape(-1)[idx]
+    eA = ref["A"].reshape(-1)[idx]
+    assert np.linalg.norm(gA - eA) <= 1e-4 * np.linalg.norm(eA)
+    S = xs > 0
+    for block, size in (("c", A.shape[1]), ("b", A.shape[0])):
+        coords = rng.choice(size, 64, replace=False)
+        fd = oadj.fd_gradient_rhs(A, b, c, q, S, x_tgt, block, coords)
+        gk = grads[block].cpu().numpy()[coords]
+        assert np.linalg.norm(gk - fd) <= 1e-4 * np.linalg.norm(fd), block
+
+
+@pytest.mark.parametrize("name,sk", [("lowrank_5000x20000", "f64"), ("gauss_2000x8000", "bf16")])
+def test_ipm_solve_full_size(nys, name, sk):
+    print(f"full-size ipm_solve {name} {sk}", flush=True)
+    inst = make_instance(name, seed=0, device=DEV)
+    A = inst.A
+    A_lo = A.to(torch.bfloat16) if sk == "bf16" else None
+    x, y, z, info = nys.ipm_solve(A, inst.b, inst.c, inst.q, ell=inst.ell, tol=1e-6, seed=0, sketch_dtype=sk,
+                                  A_lo=A_lo)
+    assert info.status == 0 and info.kkt_rel <= 1e-6
+    err = float(torch.linalg.norm(x - inst.x_star) / torch.linalg.norm(inst.x_star))
+    assert err <= 1e-5, err
+    assert bool((x > 0).all()) and bool((z > 0).all())

@@ -282,6 +282,19 @@ def test_adjoint_matches_finite_differences():
         assert np.linalg.norm(an - fd) <= 1e-7 * max(np.linalg.norm(fd), 1e-12), block
 
 
+def test_fd_with_reused_factorisation_matches_full_resolves():
+    inst = make_instance("gauss_2000x8000", seed=4, m=25, n=60)
+    A, b, c, q = _np(inst)
+    x = inst.x_star.numpy()
+    S = x > 0
+    x_tgt = x + 0.01 * np.random.default_rng(16).standard_normal(x.shape)
+    for block, size in (("c", 60), ("b", 25)):
+        coords = np.arange(size)
+        full = adjoint.fd_gradient(A, b, c, q, S, x_tgt, block, coords)
+        fast = adjoint.fd_gradient_rhs(A, b, c, q, S, x_tgt, block, coords)
+        np.testing.assert_allclose(fast, full, rtol=1e-6, atol=1e-10)
+
+
 # ---------------------------------------------------------------- low precision, RNG
 
 def test_bf16_rounding_matches_torch_and_ties_to_even():

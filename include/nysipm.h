@@ -235,11 +235,17 @@ int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* 
 /* Adjoint of the converged KKT system (not in the paper; derived from the
    optimality conditions of (P)/(D)).  With g = dL/dx at the solution (x, y, z)
    returned by ipm_solve with final parameters (rho, delta):
-   D_j = 0 where x_j <= z_j, else (q_j + z_j/x_j + rho)^{-1};
-   (A D A^T + delta I) u2 = A (D g) by Nystrom-PCG; u1 = D (g - A^T u2);
+   D_j = 0 where x_j <= z_j (inactive), else (q_j + rho)^{-1} (the iterate's
+   barrier term z_j/x_j, which vanishes at the optimum, is left out; rho keeps
+   zero-curvature columns finite);
+   (A D A^T + delta I) u2 = A (D g) by Nystrom-PCG (rtol from opts->pcg, 1e-10
+   when <= 0; iteration cap max(m, 20000) when opts->pcg.maxit <= 0);
+   u1 = D (g - A^T u2);
    grad_c = -u1, grad_b = u2, grad_q = -u1 .* x, grad_A = y u1^T - u2 x^T.
    Any output pointer may be NULL (skipped); grad_A is m x n row-major FP64
-   with leading dimension n.  Synchronises. */
+   with leading dimension n.  Returns the PCG status (NYS_MAXIT = the adjoint
+   solve did not reach its tolerance; gradients from the last iterate).
+   Synchronises. */
 int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, const double* x,
                 const double* y, const double* z, double rho, double delta, const double* g,
                 double* grad_c, double* grad_b, double* grad_q, double* grad_A,

@@ -169,12 +169,14 @@ struct InitShift {
     zeta[j] = xn;
   }
 };
-struct AdjD {         // D_adj = 0 where x <= z, else (q + z/x + rho)^{-1}; tn = D g
+struct AdjD {         // D_adj = 0 where x <= z, else (q + rho)^{-1}; tn = D g
   double *D, *tn;
   const double *q, *x, *z, *g;
   double rho;
   __device__ void operator()(int64_t j, double*, double*) const {
-    const double d = x[j] > z[j] ? 1.0 / (q[j] + z[j] / x[j] + rho) : 0.0;
+    // at the optimum z_S = 0: the barrier term z/x of the iterate is an O(mu)
+    // bias and is left out; rho keeps zero-curvature columns finite
+    const double d = x[j] > z[j] ? 1.0 / (q[j] + rho) : 0.0;
     D[j] = d;
     tn[j] = d * g[j];
   }
@@ -548,6 +550,7 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   h->t_sketch += ms_since(t0);
   nys_pcg_opts po = o.pcg;
   if (!(po.rtol > 0)) po.rtol = 1e-10;
+  if (po.maxit <= 0) po.maxit = (int)std::max<int64_t>(m, 20000);
   t0 = clk::now();
   int rc = ipm_pcg(h, A, D, delta, U, lamh, o.ell, rhs, u2, &po, info);
   h->t_pcg += ms_since(t0);

@@ -114,6 +114,8 @@ def test_adjoint_full_size_differentiation_workload(nys):
     g = x.cpu().numpy() - x_tgt
     grads, pinfo = nys.ipm_adjoint(At, tb, tc, tq, x, y, z, info.rho, info.delta,
                                    torch.from_numpy(g).to(DEV), ell=inst.ell)
+    print(f"adjoint pcg: iters={pinfo.iters} status={pinfo.status} rel_res={pinfo.rel_res:.2e}", flush=True)
+    assert pinfo.status == 0
     ref = oadj.kkt_gradient(A, b, c, q, xs, ys, zs, xs - x_tgt)
     for k in ("c", "b", "q"):
         e, gk = ref[k], grads[k].cpu().numpy()

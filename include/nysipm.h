@@ -235,9 +235,10 @@ int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* 
 /* Adjoint of the converged KKT system (not in the paper; derived from the
    optimality conditions of (P)/(D)).  With g = dL/dx at the solution (x, y, z)
    returned by ipm_solve with final parameters (rho, delta):
-   D_j = 0 where x_j <= z_j (inactive), else (q_j + rho)^{-1} (the iterate's
-   barrier term z_j/x_j, which vanishes at the optimum, is left out; rho keeps
-   zero-curvature columns finite);
+   D_j = 0 where x_j <= z_j (inactive), else max(q_j, rho)^{-1} (the exact
+   Q_S^{-1} of the converged system: the iterate's barrier term z_j/x_j, zero at
+   the optimum, is left out, and only curvature below rho -- zero-curvature
+   columns included -- is floored at rho);
    (A D A^T + delta I) u2 = A (D g) by Nystrom-PCG (rtol from opts->pcg, 1e-10
    when <= 0; iteration cap max(m, 20000) when opts->pcg.maxit <= 0);
    u1 = D (g - A^T u2);

@@ -169,14 +169,15 @@ struct InitShift {
     zeta[j] = xn;
   }
 };
-struct AdjD {         // D_adj = 0 where x <= z, else (q + rho)^{-1}; tn = D g
+struct AdjD {         // D_adj = 0 where x <= z, else max(q, rho)^{-1}; tn = D g
   double *D, *tn;
   const double *q, *x, *z, *g;
   double rho;
   __device__ void operator()(int64_t j, double*, double*) const {
-    // at the optimum z_S = 0: the barrier term z/x of the iterate is an O(mu)
-    // bias and is left out; rho keeps zero-curvature columns finite
-    const double d = x[j] > z[j] ? 1.0 / (q[j] + rho) : 0.0;
+    // The adjoint of the converged KKT system needs Q_S^{-1} exactly: the
+    // iterate's barrier term z/x (zero at the optimum) is left out, and only
+    // curvature below rho (zero-curvature columns included) is floored at rho.
+    const double d = x[j] > z[j] ? 1.0 / fmax(q[j], rho) : 0.0;
     D[j] = d;
     tn[j] = d * g[j];
   }

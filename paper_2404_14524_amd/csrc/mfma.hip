@@ -27,8 +27,11 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-constexpr int TBM = 128, TBN = 128, TBK = 32;
-constexpr int LDK = TBK + 8;   // padded LDS row (bf16 elements): 80 bytes
+constexpr int TBM = 128, TBN = 128, TBK = 64;
+constexpr int LDK = TBK + 8;   // padded LDS row (bf16 elements): 144 bytes
+constexpr int KCH = TBK / 8;   // 16-byte chunks along k per tile row
+constexpr int APT = TBM * KCH / NYS_BLOCK;   // A chunks per thread (4)
+constexpr int BPT = TBN * KCH / NYS_BLOCK;   // B chunks per thread (4)
 
 __device__ __forceinline__ uint16_t bf16_rne(float f) {
   uint32_t u = __float_as_uint(f);
@@ -87,30 +90,27 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_mfma_gemm(int64_t M, int64_t N, i
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-  for (int64_t k0 = kb; k0 < ke; k0 += TBK) {
-    // ---- A tile: 128 rows x 32 k, two 16-byte pieces per thread
+  // Register-prefetch pipeline: the next k-tile's global loads are issued
+  // before the current tile's MFMAs, so their latency hides behind the math.
+  u16x8 ra[APT], rb[BPT];
+  auto load_tiles = [&](int64_t k0) {
 #pragma unroll
-    for (int p = 0; p < 2; ++p) {
-      const int row = (tid >> 2) + 64 * p;
-      const int kc = (tid & 3) * 8;
-      const u16x8 v = load_k8(A, lda, m0 + row, M, k0 + kc, ke, veca);
-      *(u16x8*)(As + row * LDK + kc) = v;
+    for (int p = 0; p < APT; ++p) {
+      const int idx = tid + p * NYS_BLOCK;
+      ra[p] = load_k8(A, lda, m0 + idx / KCH, M, k0 + (idx % KCH) * 8, ke, veca);
     }
-    // ---- B tile: 128 columns x 32 k
     if constexpr (B_NK) {
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const int col = (tid >> 2) + 64 * p;
-        const int kc = (tid & 3) * 8;
-        const u16x8 v = load_k8(B, ldb, n0 + col, N, k0 + kc, ke, vecb);
-        *(u16x8*)(Bs + col * LDK + kc) = v;
+      for (int p = 0; p < BPT; ++p) {
+        const int idx = tid + p * NYS_BLOCK;
+        rb[p] = load_k8(B, ldb, n0 + idx / KCH, N, k0 + (idx % KCH) * 8, ke, vecb);
       }
     } else {
-      // B stored K x N (N contiguous): read 8 columns of one k-row, write transposed
+      // B stored K x N (N contiguous): 8 consecutive columns of one k-row
 #pragma unroll
-      for (int p = 0; p < 2; ++p) {
-        const int kr = (tid >> 4) + 16 * p;
-        const int nc = (tid & 15) * 8;
+      for (int p = 0; p < BPT; ++p) {
+        const int idx = tid + p * NYS_BLOCK;
+        const int kr = idx / (TBN / 8), nc = (idx % (TBN / 8)) * 8;
         const int64_t gk = k0 + kr;
         u16x8 v = {0, 0, 0, 0, 0, 0, 0, 0};
         if (gk < ke) {
@@ -123,11 +123,38 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_mfma_gemm(int64_t M, int64_t N, i
               if (n0 + nc + e < N) v[e] = src[e];
           }
         }
-#pragma unroll
-        for (int e = 0; e < 8; ++e) Bs[(nc + e) * LDK + kr] = v[e];
+        rb[p] = v;
       }
     }
+  };
+  auto store_tiles = [&]() {
+#pragma unroll
+    for (int p = 0; p < APT; ++p) {
+      const int idx = tid + p * NYS_BLOCK;
+      *(u16x8*)(As + (idx / KCH) * LDK + (idx % KCH) * 8) = ra[p];
+    }
+    if constexpr (B_NK) {
+#pragma unroll
+      for (int p = 0; p < BPT; ++p) {
+        const int idx = tid + p * NYS_BLOCK;
+        *(u16x8*)(Bs + (idx / KCH) * LDK + (idx % KCH) * 8) = rb[p];
+      }
+    } else {
+#pragma unroll
+      for (int p = 0; p < BPT; ++p) {
+        const int idx = tid + p * NYS_BLOCK;
+        const int kr = idx / (TBN / 8), nc = (idx % (TBN / 8)) * 8;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) Bs[(nc + e) * LDK + kr] = rb[p][e];   // transpose into [n][k]
+      }
+    }
+  };
+
+  if (kb < ke) load_tiles(kb);
+  for (int64_t k0 = kb; k0 < ke; k0 += TBK) {
+    store_tiles();
     __syncthreads();
+    if (k0 + TBK < ke) load_tiles(k0 + TBK);
 #pragma unroll
     for (int ks = 0; ks < TBK; ks += 16) {
       const int kk = ks + 8 * (lane >> 5);

@@ -224,10 +224,21 @@ def main():
         out = torch.empty_like(v)
         for _ in range(args.kernel_loop):
             nys.nys_normal_apply(A, d, 1e-3, v, out)
-        src = torch.empty(1 << 29, dtype=torch.float32, device=dev)   # 2 GiB
+        src = torch.ones(1 << 29, dtype=torch.float32, device=dev)    # 2 GiB
         dst = torch.empty_like(src)
         for _ in range(5):
             dst.copy_(src)
+        # plain read stream of known size: a sum over 8 GiB (reference read bandwidth)
+        big = torch.ones(1 << 31, dtype=torch.float32, device=dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(2)]
+        best = float("inf")
+        for _ in range(5):
+            ev[0].record()
+            big.sum()
+            ev[1].record()
+            torch.cuda.synchronize()
+            best = min(best, ev[0].elapsed_time(ev[1]))
+        log(f"read-stream reference: {big.numel() * 4 / (best * 1e-3) / 1e9:.0f} GB/s (torch sum over 8 GiB)")
         torch.cuda.synchronize()
         log(f"kernel loop done: {args.kernel_loop} normal applies ({bytes_pass} B per pass), "
             f"5 copies of {src.numel() * 4} B")

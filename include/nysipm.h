@@ -100,6 +100,13 @@ enum {
 int nys_profile_enable(nys_handle h, int enable);
 int nys_profile_read(nys_handle h, int kernel_class, int64_t* launches, double* total_ms);
 
+/* Read-stream reference for roofline reports (not a step of the method):
+   reads `bytes` (a multiple of 16; data 16-byte aligned) once with the same
+   16-byte non-temporal loads as the normal-equation passes and returns the
+   device time of the read in *ms (the call synchronises).  NYS_EINVAL on a
+   bad size or alignment. */
+int nys_stream_read(nys_handle h, const void* data, int64_t bytes, double* ms);
+
 /* ---------------------------------------------------------------- operators */
 
 /* out = (A diag(d) A^T + delta I) v : the regularised normal-equation operator

@@ -555,6 +555,29 @@ extern "C" int nys_profile_read(nys_handle h, int kclass, int64_t* launches, dou
   return NYS_OK;
 }
 
+extern "C" int nys_stream_read(nys_handle h, const void* data, int64_t bytes, double* ms) {
+  if (!h) return NYS_EINVAL;
+  if (!data || bytes <= 0 || bytes % 16 != 0 || (uintptr_t)data % 16 != 0 || !ms)
+    return set_error(h, NYS_EINVAL, "nys_stream_read: need 16-byte aligned data and a size multiple of 16");
+  NYS_HIP(h, hipSetDevice(h->device));
+  const int nb = 4096;
+  unsigned* part;
+  NYS_CHECK(ws_get(h, WS_PART2, (size_t)nb * 4 * sizeof(unsigned), (void**)&part));
+  hipEvent_t e0, e1;
+  NYS_HIP(h, hipEventCreate(&e0));
+  NYS_HIP(h, hipEventCreate(&e1));
+  NYS_HIP(h, hipEventRecord(e0, h->stream));
+  int rc = stream_read(h, data, bytes, part, nb);
+  NYS_HIP(h, hipEventRecord(e1, h->stream));
+  NYS_HIP(h, hipEventSynchronize(e1));
+  float t = 0.f;
+  NYS_HIP(h, hipEventElapsedTime(&t, e0, e1));
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  *ms = t;
+  return rc;
+}
+
 extern "C" int nys_destroy(nys_handle h) {
   if (!h) return NYS_OK;
   (void)hipSetDevice(h->device);

@@ -48,6 +48,10 @@ int gemv_n(nys_handle h, const GemvN& a);
 int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
                  const double* v, double* out, double* dot_out);
 
+// Read-stream reference (16-byte non-temporal loads over `bytes`, a multiple of
+// 16); part receives nblocks * 4 words.
+int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int nblocks);
+
 // ---------------------------------------------------------------- vectors
 int fill(nys_handle h, double* x, int64_t n, double value);
 int copy(nys_handle h, double* dst, const double* src, int64_t n);

@@ -62,12 +62,35 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_nonfinite(const char* A, int64_t 
   if (threadIdx.x == 0) part[blockIdx.x] = c[0];
 }
 
+// Read-stream reference: every 16-byte piece read once with the GEMV passes'
+// non-temporal loads, XOR-folded so the reads cannot be elided.
+__global__ __launch_bounds__(NYS_BLOCK) void k_stream_read(const char* p, int64_t n16, unsigned* part) {
+  const int64_t stride = (int64_t)gridDim.x * NYS_BLOCK;
+  unsigned acc = 0u;
+  int64_t i = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x;
+  for (; i + 3 * stride < n16; i += 4 * stride) {
+    const u32x4 v0 = ld_stream16(p + 16 * i);
+    const u32x4 v1 = ld_stream16(p + 16 * (i + stride));
+    const u32x4 v2 = ld_stream16(p + 16 * (i + 2 * stride));
+    const u32x4 v3 = ld_stream16(p + 16 * (i + 3 * stride));
+    acc ^= v0.x ^ v0.y ^ v0.z ^ v0.w ^ v1.x ^ v1.y ^ v1.z ^ v1.w ^ v2.x ^ v2.y ^ v2.z ^ v2.w ^ v3.x ^ v3.y ^
+           v3.z ^ v3.w;
+  }
+  for (; i < n16; i += stride) {
+    const u32x4 v = ld_stream16(p + 16 * i);
+    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, NYS_WAVE);
+  if ((threadIdx.x & (NYS_WAVE - 1)) == 0) part[blockIdx.x * (NYS_BLOCK / NYS_WAVE) + threadIdx.x / NYS_WAVE] = acc;
+}
+
 // ---------------------------------------------------------------- PCG / P^{-1}
 // Every reduction below is two launches: per-block partials, then a one-block
 // kernel that combines them in block order (deterministic) and advances the
 // scalar recurrences held in device words.
 // Rows per block of the update/reduce kernel (one row per thread in phase 1).
-constexpr int RBU = NYS_BLOCK;
+constexpr int RBU = 64;
 
 struct UpdArgs {
   int64_t m;
@@ -140,32 +163,29 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update(UpdArgs a) {
   if (threadIdx.x == 0) a.part[(int64_t)blockIdx.x * (ell + 1) + ell] = rr[0];
 }
 
-// One block.  PRECOND: t = f .* sum(partials), f_k = (lam_l + delta)/(lam_k + delta) - 1
-// with lam_l = min lam.  ||r||^2 -> SC_RR.  UPDATE: iteration count, done when
-// ||r||^2 <= tol2, breakdown flag; without a preconditioner also rs = ||r||^2
-// and beta = rs_new/rs (zero once done).
+// One block per column of the partials (ell + 1 blocks).  Block k < ell:
+// t_k = f_k * sum_b part[b][k], f_k = (lam_ell + delta)/(lam_k + delta) - 1 with
+// lam_ell the last (smallest) entry of the descending lambda.  Block ell:
+// ||r||^2 -> SC_RR; UPDATE: iteration count, done when ||r||^2 <= tol2,
+// breakdown flag; without a preconditioner also rs = ||r||^2 and
+// beta = rs_new/rs (zero once done).
 template <bool UPDATE, bool PRECOND>
 __global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update_finish(UpdArgs a, int nb) {
   __shared__ double smem[NYS_BLOCK / NYS_WAVE];
-  __shared__ double laml;
   const int ell = PRECOND ? a.ell : 0;
+  const int col = blockIdx.x;
+  double s1[1] = {0.0};
+  for (int b = threadIdx.x; b < nb; b += NYS_BLOCK) s1[0] += a.part[(int64_t)b * (ell + 1) + col];
+  block_sum<1>(s1, smem);
   if constexpr (PRECOND) {
-    if (threadIdx.x == 0) {
-      double mn = a.lam[0];
-      for (int k = 1; k < ell; ++k) mn = fmin(mn, a.lam[k]);
-      laml = mn;
-    }
-    __syncthreads();
-    for (int k = threadIdx.x; k < ell; k += NYS_BLOCK) {
-      double s = 0.0;
-      for (int b = 0; b < nb; ++b) s += a.part[(int64_t)b * (ell + 1) + k];
-      const double f = (laml + a.delta) / (a.lam[k] + a.delta) - 1.0;
-      a.t[k] = f * s;
+    if (col < ell) {
+      if (threadIdx.x == 0) {
+        const double laml = a.lam[ell - 1];
+        a.t[col] = ((laml + a.delta) / (a.lam[col] + a.delta) - 1.0) * s1[0];
+      }
+      return;
     }
   }
-  double s1[1] = {0.0};
-  for (int b = threadIdx.x; b < nb; b += NYS_BLOCK) s1[0] += a.part[(int64_t)b * (ell + 1) + ell];
-  block_sum<1>(s1, smem);
   if (threadIdx.x == 0) {
     const double rrt = s1[0];
     a.scal[SC_RR] = rrt;
@@ -256,19 +276,20 @@ int launch_update(nys_handle h, bool update, bool precond, UpdArgs& k) {
   const unsigned nb = (unsigned)std::max<int64_t>(1, (k.m + RBU - 1) / RBU);
   NYS_CHECK(ws(h, WS_PART, (size_t)nb * ((precond ? k.ell : 0) + 1), &k.part));
   k.scal = h->dscal;
-  dim3 g(nb), b(NYS_BLOCK), one(1);
+  // finish: one block per column of the partials (ell entries of t, then ||r||^2)
+  dim3 g(nb), b(NYS_BLOCK), fin((unsigned)((precond ? k.ell : 0) + 1));
   if (update && precond) {
     hipLaunchKernelGGL((k_pcg_update<true, true>), g, b, 0, h->stream, k);
-    hipLaunchKernelGGL((k_pcg_update_finish<true, true>), one, b, 0, h->stream, k, (int)nb);
+    hipLaunchKernelGGL((k_pcg_update_finish<true, true>), fin, b, 0, h->stream, k, (int)nb);
   } else if (update) {
     hipLaunchKernelGGL((k_pcg_update<true, false>), g, b, 0, h->stream, k);
-    hipLaunchKernelGGL((k_pcg_update_finish<true, false>), one, b, 0, h->stream, k, (int)nb);
+    hipLaunchKernelGGL((k_pcg_update_finish<true, false>), fin, b, 0, h->stream, k, (int)nb);
   } else if (precond) {
     hipLaunchKernelGGL((k_pcg_update<false, true>), g, b, 0, h->stream, k);
-    hipLaunchKernelGGL((k_pcg_update_finish<false, true>), one, b, 0, h->stream, k, (int)nb);
+    hipLaunchKernelGGL((k_pcg_update_finish<false, true>), fin, b, 0, h->stream, k, (int)nb);
   } else {
     hipLaunchKernelGGL((k_pcg_update<false, false>), g, b, 0, h->stream, k);
-    hipLaunchKernelGGL((k_pcg_update_finish<false, false>), one, b, 0, h->stream, k, (int)nb);
+    hipLaunchKernelGGL((k_pcg_update_finish<false, false>), fin, b, 0, h->stream, k, (int)nb);
   }
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
@@ -286,6 +307,13 @@ int launch_expand(nys_handle h, ExpArgs& k) {
 }
 
 }  // namespace
+
+int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int nblocks) {
+  hipLaunchKernelGGL(k_stream_read, dim3((unsigned)nblocks), dim3(NYS_BLOCK), 0, h->stream,
+                     (const char*)data, bytes / 16, part);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
 
 int fill(nys_handle h, double* x, int64_t n, double value) {
   return map_reduce<0, 0>(h, n, FillF{x, value}, nullptr);

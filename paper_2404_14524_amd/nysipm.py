@@ -70,7 +70,7 @@ class nys_ipm_info(C.Structure):
 
 
 EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
-           "nys_profile_enable", "nys_profile_read",
+           "nys_profile_enable", "nys_profile_read", "nys_stream_read",
            "nys_normal_apply", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint"]
 
@@ -98,6 +98,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
             "nys_last_timing": [vp, C.POINTER(dbl), C.POINTER(dbl), C.POINTER(dbl)],
             "nys_profile_enable": [vp, C.c_int],
             "nys_profile_read": [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)],
+            "nys_stream_read": [vp, vp, i64, C.POINTER(dbl)],
             "nys_normal_apply": [vp, pm, vp, dbl, vp, vp],
             "nys_test_matrix": [vp, i64, i32, u64, u64, vp],
             "nys_sketch_product": [vp, pm, vp, vp, i32, C.c_int, vp],
@@ -369,3 +370,13 @@ def nys_profile_read(device="cuda") -> dict:
         _check(lib, h, lib.nys_profile_read(h, k, C.byref(n), C.byref(ms)))
         out[name] = (int(n.value), float(ms.value))
     return out
+
+
+def nys_stream_read(t: torch.Tensor) -> float:
+    """Milliseconds for one 16-byte non-temporal read of the tensor's bytes
+    (read-stream reference for roofline reports)."""
+    lib, h = _handle(t.device)
+    nbytes = t.numel() * t.element_size()
+    ms = C.c_double()
+    _check(lib, h, lib.nys_stream_read(h, C.c_void_p(t.data_ptr()), nbytes - nbytes % 16, C.byref(ms)))
+    return ms.value

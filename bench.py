@@ -95,8 +95,11 @@ def summarize_pmc(fetch_db: str, write_db: str, workload: str, m: int, n: int, b
                   out: str = ""):
     """HBM bytes per launch of the two GEMV passes from FETCH_SIZE and
     WRITE_SIZE (KiB per dispatch), each scaled by what the same counter reads
-    for the plain 2 GiB copy of the same run."""
+    for a reference kernel of known size in the same run: FETCH_SIZE by the
+    read-stream kernel over A (the same 16-byte non-temporal loads, m*n*b_A
+    bytes), WRITE_SIZE by the plain 2 GiB copy."""
     copy_bytes = float(1 << 31)
+    read_bytes = float((m * n * b_A) // 16 * 16)
     rec = {"workload": workload, "gemv_source_hash": gemv_source_hash(), "command": command,
            "algorithmic_bytes_per_launch": m * n * b_A, "hbm_bytes_per_launch": {}, "raw_kib": {}}
     per = {}
@@ -104,10 +107,16 @@ def summarize_pmc(fetch_db: str, write_db: str, workload: str, m: int, n: int, b
         con = _db(path)
         rows = con.execute("select kernel_name, value from counters_collection where counter_name = ?",
                            (counter,)).fetchall()
-        copies = [v for k, v in rows if "copy" in k.lower()]
-        ref = max(copies) if copies else None
-        factor = copy_bytes / (ref * 1024.0) if ref else None
-        rec[f"{counter}_copy_kib"] = ref
+        if counter == "FETCH_SIZE":
+            refs = [v for k, v in rows if "k_stream_read" in k]
+            known = read_bytes
+        else:
+            refs = [v for k, v in rows if "copy" in k.lower()]
+            known = copy_bytes
+        ref = (sum(refs) / len(refs) if counter == "FETCH_SIZE" else max(refs)) if refs else None
+        factor = known / (ref * 1024.0) if ref else None
+        rec[f"{counter}_reference_kib"] = ref
+        rec[f"{counter}_reference_bytes"] = known
         rec[f"{counter}_scale"] = factor
         for key, tag in (("normal_pass1", "k_gemv_t<"), ("normal_pass2", "k_gemv_n<")):
             vals = [v for k, v in rows if tag in k]

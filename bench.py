@@ -17,8 +17,10 @@ oracle's per-iteration work on a bounded sample of the same instance.
 
 Modes:
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-fp64] [--no-cpu-baseline]
-  python bench.py --kernel-loop R   # only R normal-equation applies + a plain
-                                    # copy of known size (for counter runs)
+  python bench.py --kernel-loop R   # only R normal-equation applies (pass 1 on a
+                                    # transposed copy, as in the solver), a plain
+                                    # copy and read-stream kernels of known size
+                                    # (for counter runs)
 """
 
 from __future__ import annotations
@@ -39,6 +41,13 @@ TOL = 1e-6
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+# kernel-name prefixes of the two passes (pass 1 over A^T rows, or over
+# column stripes of A when there is no transposed copy)
+PASS1_TAGS = ("k_gemv_tt<", "k_gemv_t<")
+PASS2_TAGS = ("k_gemv_n<",)
+PASS_TAGS = PASS1_TAGS + PASS2_TAGS
 
 
 def gemv_source_hash() -> str:
@@ -82,7 +91,7 @@ def summarize_trace(db_path: str, out_md: str, command: str, workload: str, m: i
              "|---|---|---|---|---|---|---|"]
     for name, cnt, avg, mn, mx, tot in rows:
         short = name.replace("(anonymous namespace)::", "").split("(")[0].replace("void ", "")[:80]
-        gbs = f"{bytes_pass / (avg * 1e-9) / 1e9:.0f}" if ("k_gemv_t<" in name or "k_gemv_n<" in name) else ""
+        gbs = f"{bytes_pass / (avg * 1e-9) / 1e9:.0f}" if any(t in name for t in PASS_TAGS) else ""
         lines.append(f"| `{short}` | {cnt} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
                      f"{tot / 1e6:.2f} | {gbs} |")
     os.makedirs(os.path.dirname(out_md), exist_ok=True)
@@ -118,8 +127,8 @@ def summarize_pmc(fetch_db: str, write_db: str, workload: str, m: int, n: int, b
         rec[f"{counter}_reference_kib"] = ref
         rec[f"{counter}_reference_bytes"] = known
         rec[f"{counter}_scale"] = factor
-        for key, tag in (("normal_pass1", "k_gemv_t<"), ("normal_pass2", "k_gemv_n<")):
-            vals = [v for k, v in rows if tag in k]
+        for key, tags in (("normal_pass1", PASS1_TAGS), ("normal_pass2", PASS2_TAGS)):
+            vals = [v for k, v in rows if any(t in k for t in tags)]
             if vals and factor:
                 kib = sum(vals) / len(vals)
                 rec["raw_kib"][f"{key}_{counter}"] = kib
@@ -231,8 +240,10 @@ def main():
         d = torch.rand(inst.n, dtype=torch.float64, device=dev)
         v = torch.randn(inst.m, dtype=torch.float64, device=dev)
         out = torch.empty_like(v)
+        A_t = nys.nys_transpose(A)      # the layout ipm_solve gives pass 1
         for _ in range(args.kernel_loop):
-            nys.nys_normal_apply(A, d, 1e-3, v, out)
+            nys.nys_normal_apply(A, d, 1e-3, v, out, A_t=A_t)
+        del A_t
         src = torch.ones(1 << 29, dtype=torch.float32, device=dev)    # 2 GiB
         dst = torch.empty_like(src)
         for _ in range(5):
@@ -287,7 +298,7 @@ def main():
         traffic = trec["hbm_bytes_per_launch"].get(dom)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": traffic,
-                "kernel": f"k_gemv_{'t' if dom == 'normal_pass1' else 'n'} ({dom})",
+                "kernel": f"k_gemv_{'tt' if dom == 'normal_pass1' else 'n'} ({dom})",
                 "algorithmic_bytes_per_launch": bytes_pass, "launches": launches,
                 "avg_launch_ms": round(avg_ms, 4), "read_stream_GBps": round(read_stream_gbs, 1),
                 "frac_of_read_stream": round(achieved / read_stream_gbs, 4)}
@@ -338,6 +349,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": args.workload, "m": inst.m, "n": inst.n, "ell": inst.ell,
                    "A_storage": str(A.dtype).replace("torch.", ""), "sketch": mixed["sketch_dtype"],
+                   "pass1_layout": "transposed copy of A made inside the timed solve",
                    "tol": TOL, "instance_seed": args.seed},
         "accuracy": {"kkt_rel": info.kkt_rel, "rp_rel": info.rp_rel, "rd_rel": info.rd_rel, "mu": info.mu,
                      "x_rel_err_vs_planted": x_err, "ipm_iters": info.iters,

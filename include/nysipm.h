@@ -54,11 +54,19 @@ typedef enum { NYS_F64 = 0, NYS_F32 = 1, NYS_BF16 = 2 } nys_dtype;
 
 typedef struct nys_handle_s* nys_handle;
 
-/* A: m x n, row-major, leading dimension ld (elements), storage dtype. */
+/* A: m x n, row-major, leading dimension ld (elements), storage dtype.
+   data_t (optional, may be NULL): the same matrix transposed, n x m row-major
+   with leading dimension ld_t >= m, same dtype, caller-owned and not modified.
+   When present, the products that reduce over the m rows (A^T v) stream whole
+   rows of it instead of column stripes of A (same results up to the order of
+   the FP64 additions).  ipm_solve and ipm_adjoint make such a copy in their
+   workspace when none is given (see nys_ipm_opts.no_transposed_copy). */
 typedef struct {
   int64_t m, n, ld;
   nys_dtype dtype;
   const void* data;
+  const void* data_t;
+  int64_t ld_t;
 } nys_matrix;
 
 /* Nystrom preconditioner {U_hat, Lambda_hat} (Algorithm 2; eq. Nys_precond).
@@ -116,6 +124,13 @@ int nys_stream_read(nys_handle h, const void* data, int64_t bytes, double* ms);
    FP64, out must not alias v.  Enqueue only. */
 int nys_normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
                      const double* v, double* out);
+
+/* Storage layout helper for nys_matrix.data_t (not a step of the method):
+   out (n x m row-major, leading dimension ld_out >= m elements, A's dtype,
+   caller-owned, must not overlap A) = A^T, so that A^T v products stream
+   whole rows.  Elements m .. ld_out-1 of each row are left untouched.
+   NYS_EINVAL on bad arguments or m > 4194240.  Enqueue only. */
+int nys_transpose(nys_handle h, const nys_matrix* A, void* out, int64_t ld_out);
 
 /* Gaussian test matrix (Algorithm 1, first step): out (m x ell FP64,
    row-major) = standard normals from Philox4x32-10 keyed by `seed`, with the
@@ -219,6 +234,7 @@ typedef struct {
   double c_nu;              /* shift constant of the sketch; <= 0: 1             */
   nys_pcg_opts pcg;
   int32_t verbose;          /* 1: one line per iteration on stderr              */
+  int32_t no_transposed_copy; /* 1: never copy A^T into the workspace         */
 } nys_ipm_opts;
 
 typedef struct {

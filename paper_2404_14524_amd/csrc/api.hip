@@ -159,6 +159,8 @@ int check_matrix(nys_handle h, const nys_matrix* A, const char* who) {
   if (A->dtype != NYS_F64 && A->dtype != NYS_F32 && A->dtype != NYS_BF16)
     return set_error(h, NYS_EINVAL, "%s: bad dtype %d", who, (int)A->dtype);
   if (A->m > 0 && A->n > 0 && !A->data) return set_error(h, NYS_EINVAL, "%s: data is NULL", who);
+  if (A->data_t && A->ld_t < std::max<int64_t>(A->m, 1))
+    return set_error(h, NYS_EINVAL, "%s: ld_t=%lld < m=%lld", who, (long long)A->ld_t, (long long)A->m);
   return NYS_OK;
 }
 
@@ -622,6 +624,16 @@ extern "C" int nys_normal_apply(nys_handle h, const nys_matrix* A, const double*
   NYS_HIP(h, hipSetDevice(h->device));
   if (A->m == 0) return NYS_OK;
   return normal_apply(h, A, d, delta, v, out, nullptr);
+}
+
+extern "C" int nys_transpose(nys_handle h, const nys_matrix* A, void* out, int64_t ld_out) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_transpose"));
+  if (A->m > 0 && A->n > 0 && (!out || ld_out < A->m))
+    return set_error(h, NYS_EINVAL, "nys_transpose: need out != NULL and ld_out >= m");
+  if (out == A->data && A->m * A->n > 0) return set_error(h, NYS_EINVAL, "nys_transpose: out aliases A");
+  NYS_HIP(h, hipSetDevice(h->device));
+  return transpose(h, A, out, ld_out);
 }
 
 extern "C" int nys_test_matrix(nys_handle h, int64_t m, int32_t ell, uint64_t seed, uint64_t counter,

@@ -60,6 +60,17 @@ __device__ __forceinline__ u32x4 ld_stream16(const void* p) {
 }
 __device__ __forceinline__ u32x4 ld16(const void* p) { return *(const u32x4*)p; }
 
+// VEC consecutive doubles (VEC even, p 16-byte aligned) through 16-byte loads.
+template <int VEC>
+__device__ __forceinline__ void ld_f64s(const double* p, double* o) {
+#pragma unroll
+  for (int e = 0; e < VEC; e += 2) {
+    const u32x4 u = ld16(p + e);
+    o[e] = __hiloint2double((int)u.y, (int)u.x);
+    o[e + 1] = __hiloint2double((int)u.w, (int)u.z);
+  }
+}
+
 // ------------------------------------------------------------------ reductions
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll

@@ -13,6 +13,12 @@
 //   16-byte piece of w it loads is reused for RB rows.  Row sums are finished
 //   by wave shuffles and LDS.  An optional p^T (M p) dot product is fused as
 //   per-block partials summed by a one-block launch.
+// Pass 1 over a transposed copy (A^T stored n x m row-major): the same
+//   row-streaming shape as pass 2, with rows of A^T in place of rows of A, so
+//   each block reads RB whole rows (contiguous runs of m elements) instead of
+//   16-byte pieces of ~m rows that lie a full row of A apart.  With 288 GB of
+//   HBM the second copy of A is cheap, and the copy itself costs about one
+//   pass.
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -184,12 +190,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
     for (int64_t jv = threadIdx.x; jv < nv; jv += NYS_BLOCK) {
       const int64_t j = jv * VEC;
       double wv[VEC];
-#pragma unroll
-      for (int e = 0; e < VEC; e += 2) {
-        const u32x4 u = ld16(a.w + j + e);
-        wv[e] = __hiloint2double((int)u.y, (int)u.x);
-        wv[e + 1] = __hiloint2double((int)u.w, (int)u.z);
-      }
+      ld_f64s<VEC>(a.w + j, wv);
       u32x4 u[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
@@ -227,6 +228,114 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
     }
   }
   if (a.dot_out && threadIdx.x == 0) a.dpart[blockIdx.x] = dotc;
+}
+
+// Pass 1 on A^T (rows = n rows of A^T, cols = m):
+//   w[j] = d[j] * (sA * sum_i At[j,i] v_i + x0[j]),
+// v_i = v[i] or, fused, s[i] + beta * pold[i] (each block also stores its
+// share of that new direction to pnew).
+struct TTArgs {
+  const double* skip;
+  const char* At;
+  int64_t rows, cols, row_bytes;
+  const double* v;
+  const double* s;
+  const double* pold;
+  double* pnew;
+  const double* beta;
+  const double* d;
+  const double* x0;
+  double sA;
+  double* w;
+};
+
+template <class T, int RB, bool VECLOAD, bool FUSEDP>
+__global__ __launch_bounds__(NYS_BLOCK) void k_gemv_tt(TTArgs a) {
+  using raw = typename T::raw;
+  constexpr int VEC = T::vec;
+  __shared__ double smem[RB * (NYS_BLOCK / NYS_WAVE)];
+  if (a.skip && *a.skip != 0.0) return;
+  const double beta = FUSEDP ? *a.beta : 0.0;
+  if constexpr (FUSEDP) {
+    const int64_t per = (a.cols + gridDim.x - 1) / gridDim.x;
+    const int64_t lo = (int64_t)blockIdx.x * per;
+    const int64_t hi = min(a.cols, lo + per);
+    for (int64_t i = lo + threadIdx.x; i < hi; i += NYS_BLOCK) a.pnew[i] = a.s[i] + beta * a.pold[i];
+  }
+  const int64_t j0 = (int64_t)blockIdx.x * RB;
+  const int nr = (int)max((int64_t)0, min((int64_t)RB, a.rows - j0));
+  double acc[RB];
+#pragma unroll
+  for (int r = 0; r < RB; ++r) acc[r] = 0.0;
+
+  int64_t itail = 0;
+  if (VECLOAD) {
+    const int64_t nv = a.cols / VEC;
+    const char* base = a.At + j0 * a.row_bytes;
+    for (int64_t iv = threadIdx.x; iv < nv; iv += NYS_BLOCK) {
+      const int64_t i = iv * VEC;
+      u32x4 u[RB];
+#pragma unroll
+      for (int r = 0; r < RB; ++r)
+        if (r < nr) u[r] = ld_stream16(base + r * a.row_bytes + i * (int64_t)sizeof(raw));
+      double vv[VEC];
+      if constexpr (FUSEDP) {
+        double sv[VEC], pv[VEC];
+        ld_f64s<VEC>(a.s + i, sv);
+        ld_f64s<VEC>(a.pold + i, pv);
+#pragma unroll
+        for (int e = 0; e < VEC; ++e) vv[e] = sv[e] + beta * pv[e];
+      } else {
+        ld_f64s<VEC>(a.v + i, vv);
+      }
+#pragma unroll
+      for (int r = 0; r < RB; ++r) {
+        if (r < nr) {
+          double e[VEC];
+          Unpack<T>::run(u[r], e);
+#pragma unroll
+          for (int k = 0; k < VEC; ++k) acc[r] = fma(e[k], vv[k], acc[r]);
+        }
+      }
+    }
+    itail = nv * VEC;
+  }
+  for (int64_t i = itail + threadIdx.x; i < a.cols; i += NYS_BLOCK) {
+    const double vi = FUSEDP ? a.s[i] + beta * a.pold[i] : a.v[i];
+#pragma unroll
+    for (int r = 0; r < RB; ++r)
+      if (r < nr) acc[r] = fma(to_f64(((const raw*)(a.At + (j0 + r) * a.row_bytes))[i]), vi, acc[r]);
+  }
+  block_sum<RB>(acc, smem);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int r = 0; r < RB; ++r) {
+      if (r < nr) {
+        const int64_t j = j0 + r;
+        double val = a.sA * acc[r] + (a.x0 ? a.x0[j] : 0.0);
+        if (a.d) val *= a.d[j];
+        a.w[j] = val;
+      }
+    }
+  }
+}
+
+// At (n x m, row pitch ldt_bytes) = A^T through a 64 x 64 LDS tile.
+template <class raw>
+__global__ __launch_bounds__(NYS_BLOCK) void k_transpose(const char* A, int64_t m, int64_t n,
+                                                         int64_t lda_bytes, char* At, int64_t ldt_bytes) {
+  __shared__ raw tile[64][65];
+  const int64_t j0 = (int64_t)blockIdx.x * 64, i0 = (int64_t)blockIdx.y * 64;
+  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
+  for (int r = ty; r < 64; r += NYS_BLOCK / 64) {
+    const int64_t i = i0 + r, j = j0 + tx;
+    if (i < m && j < n) tile[r][tx] = ((const raw*)(A + i * lda_bytes))[j];
+  }
+  __syncthreads();
+  for (int r = ty; r < 64; r += NYS_BLOCK / 64) {
+    const int64_t j = j0 + r, i = i0 + tx;
+    if (j < n && i < m) ((raw*)(At + j * ldt_bytes))[i] = tile[tx][r];
+  }
 }
 
 int elem_size(nys_dtype dt) { return dt == NYS_F64 ? 8 : dt == NYS_F32 ? 4 : 2; }
@@ -268,6 +377,63 @@ void dispatch_n(T2Args& k, bool vecload, hipStream_t st) {
   else launch_n_rb<T, 1>(k, vecload, st);
 }
 
+template <class T, int RB>
+void launch_tt_rb(TTArgs& k, bool vecload, bool fused, hipStream_t st) {
+  dim3 g((unsigned)std::max<int64_t>(1, (k.rows + RB - 1) / RB));
+  if (fused) {
+    if (vecload) hipLaunchKernelGGL((k_gemv_tt<T, RB, true, true>), g, dim3(NYS_BLOCK), 0, st, k);
+    else hipLaunchKernelGGL((k_gemv_tt<T, RB, false, true>), g, dim3(NYS_BLOCK), 0, st, k);
+  } else {
+    if (vecload) hipLaunchKernelGGL((k_gemv_tt<T, RB, true, false>), g, dim3(NYS_BLOCK), 0, st, k);
+    else hipLaunchKernelGGL((k_gemv_tt<T, RB, false, false>), g, dim3(NYS_BLOCK), 0, st, k);
+  }
+}
+
+template <class T>
+void dispatch_tt(TTArgs& k, bool vecload, bool fused, hipStream_t st) {
+  const int64_t r = k.rows;
+  if (r >= 8 * 1536) launch_tt_rb<T, 8>(k, vecload, fused, st);
+  else if (r >= 4 * 1024) launch_tt_rb<T, 4>(k, vecload, fused, st);
+  else if (r >= 2 * 1024) launch_tt_rb<T, 2>(k, vecload, fused, st);
+  else launch_tt_rb<T, 1>(k, vecload, fused, st);
+}
+
+bool al16(const void* p) { return ((uintptr_t)p % 16) == 0; }
+
+// Pass 1 over the caller's (or the workspace's) transposed copy of A.
+int gemv_t_rows(nys_handle h, const GemvT& a) {
+  const nys_matrix* A = a.A;
+  const int es = elem_size(A->dtype);
+  const bool fused = a.s != nullptr;
+  TTArgs k{};
+  k.skip = a.skip;
+  k.At = (const char*)A->data_t;
+  k.rows = A->n;
+  k.cols = A->m;
+  k.row_bytes = A->ld_t * es;
+  k.v = a.v;
+  k.s = a.s;
+  k.pold = a.pold;
+  k.pnew = a.pnew;
+  k.beta = a.beta;
+  k.d = a.d;
+  k.x0 = a.x0;
+  k.sA = a.sA;
+  k.w = a.w;
+  const bool vl = al16(A->data_t) && (k.row_bytes % 16 == 0) &&
+                  (fused ? al16(a.s) && al16(a.pold) : al16(a.v));
+  const int ps = prof_begin(h, NYS_K_NORMAL_PASS1);
+  switch (A->dtype) {
+    case NYS_F64: dispatch_tt<F64>(k, vl, fused, h->stream); break;
+    case NYS_F32: dispatch_tt<F32>(k, vl, fused, h->stream); break;
+    case NYS_BF16: dispatch_tt<BF16>(k, vl, fused, h->stream); break;
+    default: return set_error(h, NYS_EINVAL, "gemv_t: bad dtype");
+  }
+  prof_end(h, ps);
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
 int n_blocks_pass2(int64_t m) {
   const int rb = m >= 8 * 1536 ? 8 : m >= 4 * 1024 ? 4 : m >= 2 * 1024 ? 2 : 1;
   return (int)((m + rb - 1) / rb);
@@ -282,6 +448,8 @@ int gemv_t(nys_handle h, const GemvT& a) {
   const bool fused = a.s != nullptr;
   // n == 0: nothing to reduce; the fused direction update still has to run
   if (A->n == 0 && !fused) return NYS_OK;
+  if (A->m == 0) return NYS_OK;
+  if (A->data_t) return gemv_t_rows(h, a);
   const int64_t ncol =
       std::max<int64_t>(1, (A->n + (int64_t)NYS_BLOCK * vec - 1) / ((int64_t)NYS_BLOCK * vec));
   // enough blocks to cover the chip several times, rows per chunk >= 32
@@ -361,6 +529,43 @@ int gemv_n(nys_handle h, const GemvN& a) {
                        (const double*)k.dpart, nbp, a.dot_out);
     NYS_LAUNCH_CHECK(h);
   }
+  return NYS_OK;
+}
+
+int transpose(nys_handle h, const nys_matrix* A, void* At, int64_t ld_t) {
+  if (A->m == 0 || A->n == 0) return NYS_OK;
+  const int es = elem_size(A->dtype);
+  const int64_t gy = (A->m + 63) / 64;
+  if (gy > 65535) return set_error(h, NYS_EINVAL, "transpose: m=%lld too large", (long long)A->m);
+  dim3 g((unsigned)((A->n + 63) / 64), (unsigned)gy);
+  const char* src = (const char*)A->data;
+  char* dst = (char*)At;
+  switch (A->dtype) {
+    case NYS_F64: hipLaunchKernelGGL(k_transpose<double>, g, dim3(NYS_BLOCK), 0, h->stream, src, A->m, A->n, A->ld * es, dst, ld_t * es); break;
+    case NYS_F32: hipLaunchKernelGGL(k_transpose<float>, g, dim3(NYS_BLOCK), 0, h->stream, src, A->m, A->n, A->ld * es, dst, ld_t * es); break;
+    case NYS_BF16: hipLaunchKernelGGL(k_transpose<uint16_t>, g, dim3(NYS_BLOCK), 0, h->stream, src, A->m, A->n, A->ld * es, dst, ld_t * es); break;
+    default: return set_error(h, NYS_EINVAL, "transpose: bad dtype");
+  }
+  NYS_LAUNCH_CHECK(h);
+  return NYS_OK;
+}
+
+int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, nys_matrix* out) {
+  *out = *A;
+  if (A->data_t || !allowed || A->m == 0 || A->n == 0) return NYS_OK;
+  const int es = elem_size(A->dtype);
+  const int64_t per16 = 16 / es;
+  const int64_t ld_t = (A->m + per16 - 1) / per16 * per16;
+  void* p = nullptr;
+  const int rc = ws_get(h, WS_AT, (size_t)A->n * ld_t * es, &p);
+  if (rc == NYS_ENOMEM) {
+    h->err.clear();   // not enough memory for the copy: pass 1 reads column stripes of A
+    return NYS_OK;
+  }
+  NYS_CHECK(rc);
+  NYS_CHECK(transpose(h, A, p, ld_t));
+  out->data_t = p;
+  out->ld_t = ld_t;
   return NYS_OK;
 }
 

@@ -30,6 +30,7 @@ enum nys_slot {
   WS_ALO,         // BF16 copy of A made by the library when none is given
   WS_PCU,         // preconditioner U (ipm_solve / ipm_adjoint internal)
   WS_PCL,         // preconditioner lambda (ipm_solve / ipm_adjoint internal)
+  WS_AT,          // transposed copy of A made by ipm_solve / ipm_adjoint
   WS_NSLOTS
 };
 

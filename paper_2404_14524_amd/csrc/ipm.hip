@@ -198,6 +198,8 @@ int check_qp(nys_handle h, const nys_qp* qp, const char* who) {
     return set_error(h, NYS_EINVAL, "%s: bad A (m=%lld n=%lld)", who, (long long)A->m, (long long)A->n);
   if (A->dtype != NYS_F64 && A->dtype != NYS_F32)
     return set_error(h, NYS_EINVAL, "%s: A must be FP64 or FP32 storage", who);
+  if (A->data_t && A->ld_t < A->m)
+    return set_error(h, NYS_EINVAL, "%s: ld_t=%lld < m=%lld", who, (long long)A->ld_t, (long long)A->m);
   if (qp->A_lo) {
     const nys_matrix* L = qp->A_lo;
     if (L->m != A->m || L->n != A->n || L->ld < L->n || L->dtype != NYS_BF16 || !L->data)
@@ -234,6 +236,7 @@ struct Opts {
   double c_nu = 1.0;
   nys_pcg_opts pcg{};
   int verbose = 0;
+  bool transpose = true;
 };
 
 Opts read_opts(const nys_ipm_opts* o) {
@@ -247,6 +250,7 @@ Opts read_opts(const nys_ipm_opts* o) {
   if (o->c_nu > 0) r.c_nu = o->c_nu;
   r.pcg = o->pcg;
   r.verbose = o->verbose;
+  r.transpose = o->no_transposed_copy == 0;
   return r;
 }
 
@@ -283,6 +287,9 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     if (hs[0] + hs[1] + hs[3] + hs[5] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: non-finite problem data");
     if (hs[6] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: q has negative entries");
   }
+  nys_matrix At{};
+  NYS_CHECK(with_transpose(h, A, o.transpose, &At));
+  A = &At;
 
   // ---- workspace
   double* base;
@@ -522,6 +529,9 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   NYS_HIP(h, hipSetDevice(h->device));
   const auto t_start = clk::now();
   h->t_sketch = h->t_pcg = h->t_other = 0.0;
+  nys_matrix At{};
+  NYS_CHECK(with_transpose(h, A, o.transpose, &At));
+  A = &At;
   double* base;
   NYS_CHECK(ws(h, WS_IPM, (size_t)12 * n + 8 * m + 64, &base));
   double* D = base;

@@ -7,7 +7,7 @@
 namespace nys {
 
 // ---------------------------------------------------------------- GEMV pair
-// Pass 1 (reduction over the m rows of A):
+// Pass 1 (reduction over the m rows of A; over the rows of A->data_t when set):
 //   w[j] = d[j] * (sA * sum_i A[i,j] v_i + x0[j])     (d, x0 may be NULL)
 // where v_i = v[i], or, when `s` is non-NULL, the fused CG direction update
 //   v_i = s[i] + beta * pold[i]   (beta read from the device word *beta),
@@ -43,6 +43,13 @@ struct GemvN {
   double* dot_out = nullptr;
 };
 int gemv_n(nys_handle h, const GemvN& a);
+
+// At (n x m, leading dimension ld_t >= m elements, A's dtype) = A^T.
+int transpose(nys_handle h, const nys_matrix* A, void* At, int64_t ld_t);
+// *out = *A with data_t pointing at a transposed copy in the WS_AT slot (made
+// here unless A already has one or `allowed` is false; without memory for it,
+// *out = *A and the column-stripe pass 1 is used).
+int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, nys_matrix* out);
 
 // out = (A diag(d) A^T + delta I) v, with optional *dot_out = v^T out.
 int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,

@@ -34,7 +34,7 @@ class NysError(RuntimeError):
 
 class nys_matrix(C.Structure):
     _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("ld", C.c_int64), ("dtype", C.c_int),
-                ("data", C.c_void_p)]
+                ("data", C.c_void_p), ("data_t", C.c_void_p), ("ld_t", C.c_int64)]
 
 
 class nys_precond(C.Structure):
@@ -59,7 +59,7 @@ class nys_qp(C.Structure):
 class nys_ipm_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ell", C.c_int32),
                 ("seed", C.c_uint64), ("sketch_dtype", C.c_int), ("c_nu", C.c_double),
-                ("pcg", nys_pcg_opts), ("verbose", C.c_int32)]
+                ("pcg", nys_pcg_opts), ("verbose", C.c_int32), ("no_transposed_copy", C.c_int32)]
 
 
 class nys_ipm_info(C.Structure):
@@ -71,7 +71,7 @@ class nys_ipm_info(C.Structure):
 
 EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
            "nys_profile_enable", "nys_profile_read", "nys_stream_read",
-           "nys_normal_apply", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
+           "nys_normal_apply", "nys_transpose", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint"]
 
 _lib = None
@@ -100,6 +100,7 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
             "nys_profile_read": [vp, C.c_int, C.POINTER(i64), C.POINTER(dbl)],
             "nys_stream_read": [vp, vp, i64, C.POINTER(dbl)],
             "nys_normal_apply": [vp, pm, vp, dbl, vp, vp],
+            "nys_transpose": [vp, pm, vp, i64],
             "nys_test_matrix": [vp, i64, i32, u64, u64, vp],
             "nys_sketch_product": [vp, pm, vp, vp, i32, C.c_int, vp],
             "nys_sketch": [vp, pm, vp, i32, u64, u64, C.c_int, vp, C.POINTER(nys_precond), C.POINTER(dbl)],
@@ -156,11 +157,19 @@ def _vec(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
     return t
 
 
-def _mat(A: torch.Tensor) -> nys_matrix:
+def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None) -> nys_matrix:
+    """nys_matrix view of a row-major CUDA tensor; A_t (optional) is the same
+    matrix transposed, n x m row-major (see nys_transpose)."""
     if A.dim() != 2 or A.dtype not in _DT or not A.is_cuda or A.stride(1) != 1:
         raise ValueError("A: need a 2-D row-major float64/float32/bfloat16 CUDA tensor")
+    tp, tld = None, 0
+    if A_t is not None:
+        if (A_t.dim() != 2 or tuple(A_t.shape) != (A.shape[1], A.shape[0]) or A_t.dtype != A.dtype
+                or A_t.device != A.device or A_t.stride(1) != 1):
+            raise ValueError("A_t: need an n x m row-major tensor of A's dtype on A's device")
+        tp, tld = A_t.data_ptr(), max(A_t.stride(0), A.shape[0], 1)
     return nys_matrix(A.shape[0], A.shape[1], max(A.stride(0), A.shape[1], 1), _DT[A.dtype],
-                      A.data_ptr())
+                      A.data_ptr(), tp, tld)
 
 
 @dataclass
@@ -177,14 +186,25 @@ def _pcg_opts(rtol=1e-10, atol=0.0, maxit=0, replace_every=0, poll_every=0) -> n
     return nys_pcg_opts(rtol, atol, maxit, replace_every, poll_every)
 
 
+def nys_transpose(A: torch.Tensor) -> torch.Tensor:
+    """A^T as a new n x m row-major tensor (the layout nys_matrix.data_t takes),
+    written by the library's transpose kernel."""
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    out = torch.empty((n, m), dtype=A.dtype, device=A.device)
+    Am = _mat(A)
+    _check(lib, h, lib.nys_transpose(h, C.byref(Am), _ptr(out), max(m, 1)))
+    return out
+
+
 def nys_normal_apply(A: torch.Tensor, d: torch.Tensor, delta: float, v: torch.Tensor,
-                     out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                     out: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None) -> torch.Tensor:
     lib, h = _handle(A.device)
     m, n = A.shape
     _vec(d, n, "d", A.device)
     _vec(v, m, "v", A.device)
     out = torch.empty(m, dtype=torch.float64, device=A.device) if out is None else _vec(out, m, "out", A.device)
-    Am = _mat(A)
+    Am = _mat(A, A_t)
     _check(lib, h, lib.nys_normal_apply(h, C.byref(Am), _ptr(d), float(delta), _ptr(v), _ptr(out)))
     return out
 
@@ -241,13 +261,14 @@ def nys_precond_apply(P: Precond, delta: float, r: torch.Tensor,
 
 
 def nys_pcg_solve(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Tensor,
-                  P: Optional[Precond] = None, y0: Optional[torch.Tensor] = None, **opts):
+                  P: Optional[Precond] = None, y0: Optional[torch.Tensor] = None,
+                  A_t: Optional[torch.Tensor] = None, **opts):
     lib, h = _handle(A.device)
     m, n = A.shape
     _vec(d, n, "d", A.device)
     _vec(rhs, m, "rhs", A.device)
     y = torch.zeros(m, dtype=torch.float64, device=A.device) if y0 is None else _vec(y0, m, "y0", A.device).clone()
-    Am = _mat(A)
+    Am = _mat(A, A_t)
     o = _pcg_opts(**opts)
     info = nys_pcg_info()
     Pc = P.c() if P is not None else None
@@ -257,7 +278,8 @@ def nys_pcg_solve(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Ten
     return y, info
 
 
-def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond] = None, **opts):
+def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond] = None,
+                     A_t: Optional[torch.Tensor] = None, **opts):
     lib, h = _handle(A.device)
     m, n = A.shape
     dev = A.device
@@ -267,7 +289,7 @@ def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond
     dx = torch.empty(n, dtype=torch.float64, device=dev)
     dz = torch.empty(n, dtype=torch.float64, device=dev)
     dy = torch.empty(m, dtype=torch.float64, device=dev)
-    Am = _mat(A)
+    Am = _mat(A, A_t)
     o = _pcg_opts(**opts)
     info = nys_pcg_info()
     Pc = P.c() if P is not None else None
@@ -279,13 +301,15 @@ def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond
 
 
 def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0, verbose=False,
-              pcg_rtol=0.0, pcg_maxit=0, replace_every=0, poll_every=0) -> nys_ipm_opts:
+              pcg_rtol=0.0, pcg_maxit=0, replace_every=0, poll_every=0,
+              transposed_copy=True) -> nys_ipm_opts:
     return nys_ipm_opts(tol, max_iter, ell, seed, _SK[sketch_dtype], c_nu,
-                        _pcg_opts(pcg_rtol, 0.0, pcg_maxit, replace_every, poll_every), int(verbose))
+                        _pcg_opts(pcg_rtol, 0.0, pcg_maxit, replace_every, poll_every), int(verbose),
+                        0 if transposed_copy else 1)
 
 
-def _qp(A, b, c, q, A_lo):
-    Am = _mat(A)
+def _qp(A, b, c, q, A_lo, A_t=None):
+    Am = _mat(A, A_t)
     Alo = _mat(A_lo) if A_lo is not None else None
     keep = (Am, Alo)
     qp = nys_qp(C.pointer(Am), C.pointer(Alo) if Alo is not None else None, b.data_ptr(),
@@ -294,8 +318,9 @@ def _qp(A, b, c, q, A_lo):
 
 
 def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor, ell: int,
-              A_lo: Optional[torch.Tensor] = None, **kw):
-    """Nys-IP-PMM.  Returns (x, y, z, info: nys_ipm_info)."""
+              A_lo: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None, **kw):
+    """Nys-IP-PMM.  Returns (x, y, z, info: nys_ipm_info).  Without A_t the
+    library makes its own transposed copy of A unless transposed_copy=False."""
     lib, h = _handle(A.device)
     m, n = A.shape
     dev = A.device
@@ -305,7 +330,7 @@ def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor
     x = torch.empty(n, dtype=torch.float64, device=dev)
     z = torch.empty(n, dtype=torch.float64, device=dev)
     y = torch.empty(m, dtype=torch.float64, device=dev)
-    qp, keep = _qp(A, b, c, q, A_lo)
+    qp, keep = _qp(A, b, c, q, A_lo, A_t)
     o = _ipm_opts(ell, **kw)
     info = nys_ipm_info()
     rc = lib.ipm_solve(h, C.byref(qp), C.byref(o), _ptr(x), _ptr(y), _ptr(z), C.byref(info))
@@ -315,7 +340,7 @@ def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor
 
 
 def ipm_adjoint(A, b, c, q, x, y, z, rho, delta, g, ell, A_lo=None, want=("c", "b", "q", "A"),
-                **kw):
+                A_t=None, **kw):
     """Gradients of L with dL/dx = g through the KKT conditions.  Returns
     (dict of requested gradients, nys_pcg_info)."""
     lib, h = _handle(A.device)
@@ -333,7 +358,7 @@ def ipm_adjoint(A, b, c, q, x, y, z, rho, delta, g, ell, A_lo=None, want=("c", "
         out["q"] = torch.empty(n, dtype=torch.float64, device=dev)
     if "A" in want:
         out["A"] = torch.empty((m, n), dtype=torch.float64, device=dev)
-    qp, keep = _qp(A, b, c, q, A_lo)
+    qp, keep = _qp(A, b, c, q, A_lo, A_t)
     kw.pop("tol", None)
     o = _ipm_opts(ell, **kw)
     info = nys_pcg_info()

@@ -64,7 +64,11 @@ def test_normal_apply_full_size(nys, name):
     # |A| (|d| |A^T v|) bounds the rounding of the second product; the first
     # product's rounding is bounded through |A^T v| <= |A|^T |v| below
     assert np.all(np.abs(out - ref) <= 1e-11 * bound + 1e-300)
-    del inst
+    # the pass-1 layout the solver uses: a transposed copy of A
+    A_t = nys.nys_transpose(inst.A)
+    out_t = nys.nys_normal_apply(inst.A, d, 1e-3, v, A_t=A_t).cpu().numpy()
+    assert np.all(np.abs(out_t - ref) <= 1e-11 * bound + 1e-300)
+    del inst, A_t
     torch.cuda.empty_cache()
 
 

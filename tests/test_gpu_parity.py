@@ -53,17 +53,22 @@ def _case(m, n, seed, scale=1.0):
 SHAPES = [(1, 1), (7, 5), (200, 500), (257, 1031), (1000, 3 * 1024 + 37), (3000, 2048), (5, 20000)]
 
 
+@pytest.mark.parametrize("layout", ["rows", "transposed"])
 @pytest.mark.parametrize("dtype", [torch.float64, torch.float32, torch.bfloat16])
 @pytest.mark.parametrize("m,n", SHAPES)
-def test_normal_apply_parity(nys, dtype, m, n):
-    print(f"normal_apply {dtype} {m}x{n}", flush=True)
+def test_normal_apply_parity(nys, dtype, m, n, layout):
+    print(f"normal_apply {dtype} {m}x{n} {layout}", flush=True)
     A, d, v = _case(m, n, seed=m * 7 + n)
     At = _t(A).to(dtype)
     Aq = _np(At)          # the values the GPU sees (exact FP64 promotion)
     if dtype == torch.bfloat16:
         np.testing.assert_array_equal(Aq, lowprec.round_bf16(A.astype(np.float32).astype(np.float64)))
     delta = 0.37
-    out = nys.nys_normal_apply(At, _t(d), delta, _t(v))
+    A_t = None
+    if layout == "transposed":
+        A_t = nys.nys_transpose(At)
+        np.testing.assert_array_equal(_np(A_t), Aq.T)     # a transpose moves values only
+    out = nys.nys_normal_apply(At, _t(d), delta, _t(v), A_t=A_t)
     ref = normal_eq.normal_apply(Aq, d, delta, v)
     bound = np.abs(Aq) @ (np.abs(d) * (np.abs(Aq).T @ np.abs(v))) + delta * np.abs(v)
     err = np.abs(_np(out) - ref)
@@ -81,6 +86,15 @@ def test_normal_apply_strided_and_empty(nys):
     out = nys.nys_normal_apply(A32, _t(d), 0.5, _t(v))
     ref = normal_eq.normal_apply(_np(A32), d, 0.5, v)
     np.testing.assert_allclose(_np(out), ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
+    # transposed copies with a padded leading dimension (16-byte rows broken
+    # for FP64/BF16: the scalar path)
+    for dt, pad in ((torch.float64, 1), (torch.float32, 4), (torch.bfloat16, 3)):
+        Aw = _t(A).to(dt)
+        wide = torch.zeros((777, 300 + pad), dtype=dt, device=DEV)
+        wide[:, :300] = nys.nys_transpose(Aw)
+        out = nys.nys_normal_apply(Aw, _t(d), 0.25, _t(v), A_t=wide[:, :300])
+        ref = normal_eq.normal_apply(_np(Aw), d, 0.25, v)
+        np.testing.assert_allclose(_np(out), ref, rtol=1e-11, atol=1e-11 * np.abs(ref).max())
     # n = 0: out = delta v
     out = nys.nys_normal_apply(torch.zeros((4, 0), dtype=torch.float64, device=DEV),
                                torch.zeros(0, dtype=torch.float64, device=DEV), 2.0, _t(np.arange(4.0)))
@@ -91,6 +105,8 @@ def test_normal_apply_rejects_bad_arguments(nys):
     A, d, v = _case(10, 12, seed=4)
     with pytest.raises(nys.NysError):
         nys.nys_normal_apply(_t(A), _t(d), float("nan"), _t(v))
+    with pytest.raises(ValueError):      # A_t of the wrong shape never reaches the library
+        nys.nys_normal_apply(_t(A), _t(d), 1.0, _t(v), A_t=_t(A))
 
 
 # ------------------------------------------------------------------ test matrix (Philox)
@@ -215,8 +231,9 @@ def test_sketch_rejects_bad_sizes(nys):
 
 # ------------------------------------------------------------------ PCG
 
+@pytest.mark.parametrize("layout", ["rows", "transposed"])
 @pytest.mark.parametrize("use_p", [False, True])
-def test_pcg_parity_with_dense_solve(nys, use_p):
+def test_pcg_parity_with_dense_solve(nys, use_p, layout):
     inst = make_instance("lowrank_5000x20000", seed=12, m=800, n=3000, rank=40)
     A = inst.A.double().numpy()
     rng = np.random.default_rng(1)
@@ -224,7 +241,8 @@ def test_pcg_parity_with_dense_solve(nys, use_p):
     delta = 1e-3
     xi = rng.standard_normal(800)
     P = nys.nys_sketch(_t(A), _t(d), 60, seed=1) if use_p else None
-    y, info = nys.nys_pcg_solve(_t(A), _t(d), delta, _t(xi), P=P, rtol=1e-11, maxit=3000)
+    A_t = _t(A.T) if layout == "transposed" else None
+    y, info = nys.nys_pcg_solve(_t(A), _t(d), delta, _t(xi), P=P, rtol=1e-11, maxit=3000, A_t=A_t)
     M = normal_eq.normal_matrix(A, d, delta)
     ref = np.linalg.solve(M, xi)
     assert info.status == 0
@@ -278,16 +296,18 @@ def test_ipm_solve_gauss_small(nys):
     assert np.all(_np(x) > 0) and np.all(_np(z) > 0)
 
 
-@pytest.mark.parametrize("sk", ["f64", "bf16"])
-def test_ipm_solve_mixed_precision_fp32_matrix(nys, sk):
-    """FP32-defined matrix, FP64-accumulated products, FP64 or BF16 sketch:
-    KKT <= 1e-6 and x within 1e-5 of the oracle's (polished) optimum."""
+@pytest.mark.parametrize("sk,tcopy", [("f64", True), ("bf16", True), ("bf16", False)])
+def test_ipm_solve_mixed_precision_fp32_matrix(nys, sk, tcopy):
+    """FP32-defined matrix, FP64-accumulated products, FP64 or BF16 sketch,
+    with and without the library's transposed copy of A: KKT <= 1e-6 and x
+    within 1e-5 of the oracle's (polished) optimum."""
     inst = make_instance("gauss_2000x8000", seed=5, m=400, n=1600)
     A = inst.A.double().numpy()
     b, c, q = inst.b.numpy(), inst.c.numpy(), inst.q.numpy()
     At = inst.A.to(DEV)
     x, y, z, info = nys.ipm_solve(At, _t(b), _t(c), _t(q), ell=50, tol=1e-6, seed=1, sketch_dtype=sk,
-                                  A_lo=At.to(torch.bfloat16) if sk == "bf16" else None)
+                                  A_lo=At.to(torch.bfloat16) if sk == "bf16" else None,
+                                  transposed_copy=tcopy)
     assert info.status == 0, (info.kkt_rel, info.iters)
     meas = problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))
     assert meas["kkt"] <= 1e-6

@@ -85,6 +85,33 @@ __device__ __forceinline__ double wave_min(double v) {
 
 // Block-wide sum of K values per thread; result valid in every thread.
 // `smem` needs K * (blockDim/64) doubles.  Fixed order: deterministic.
+// Wave sum through DPP lane moves and lane reads instead of LDS permutes (for
+// latency-bound loops).  Within each row of 16 lanes: swap neighbours, swap
+// pairs (quad permutes), then half-row and row mirrors leave every lane of the
+// row with the row sum; the four row sums are read from lanes 0/16/32/48 and
+// added in a fixed order, so all lanes return the same value.  Needs all 64
+// lanes active.
+template <int CTRL>
+__device__ __forceinline__ double dpp_mov(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double lane_read(double v, int lane) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, lane);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), lane);
+  return __longlong_as_double(((long long)hi << 32) | (unsigned)lo);
+}
+__device__ __forceinline__ double wave_sum_dpp(double v) {
+  v += dpp_mov<0xB1>(v);    // quad_perm [1,0,3,2]
+  v += dpp_mov<0x4E>(v);    // quad_perm [2,3,0,1]
+  v += dpp_mov<0x141>(v);   // row_half_mirror
+  v += dpp_mov<0x140>(v);   // row_mirror
+  return (lane_read(v, 0) + lane_read(v, 16)) + (lane_read(v, 32) + lane_read(v, 48));
+}
+
 template <int K>
 __device__ __forceinline__ void block_sum(double* v, double* smem) {
   const int lane = threadIdx.x & (NYS_WAVE - 1);

@@ -200,12 +200,161 @@ __global__ __launch_bounds__(DB) void k_tri_inv_upper(const double* C, double* X
   }
 }
 
+// Blocked form of k_chol_upper for ell >= 2*NB: panels of NB rows are factored
+// in LDS (the unblocked steps touch only the panel), and the trailing upper
+// triangle is updated once per panel from the LDS copy.  G is symmetrised and
+// shifted first, exactly as in k_chol_upper.
+__global__ __launch_bounds__(DB) void k_chol_upper_blocked(double* G, int ell, int NB, double shift_abs,
+                                                           double shift_rel, double* fail) {
+  extern __shared__ double P[];          // NB x ell panel (row pitch ell)
+  __shared__ double red[DB / NYS_WAVE];
+  __shared__ int bad;
+  const int tid = threadIdx.x;
+  double tr[1] = {0.0};
+  for (int64_t idx = tid; idx < (int64_t)ell * ell; idx += DB) {
+    const int i = (int)(idx / ell), j = (int)(idx % ell);
+    if (i < j) G[idx] = 0.5 * (G[idx] + G[(int64_t)j * ell + i]);
+    if (i == j) tr[0] += G[idx];
+  }
+  block_sum<1>(tr, red);
+  const double shift = shift_abs + shift_rel * tr[0];
+  for (int i = tid; i < ell; i += DB) G[(int64_t)i * ell + i] += shift;
+  if (tid == 0) bad = 0;
+  __syncthreads();
+  for (int k0 = 0; k0 < ell; k0 += NB) {
+    const int nb = min(NB, ell - k0);
+    const int w = ell - k0;              // panel columns k0 .. ell-1
+    for (int idx = tid; idx < nb * w; idx += DB) {
+      const int r = idx / w, c = idx % w;
+      P[r * ell + c] = G[(int64_t)(k0 + r) * ell + k0 + c];
+    }
+    __syncthreads();
+    bool badl = false;
+    for (int kk = 0; kk < nb; ++kk) {
+      const double g = P[kk * ell + kk];
+      if (!(g > 0.0) || !isfinite(g)) {  // uniform: every thread read the same g
+        badl = true;
+        break;
+      }
+      const double piv = sqrt(g);
+      __syncthreads();
+      for (int c = kk + 1 + tid; c < w; c += DB) P[kk * ell + c] /= piv;
+      if (tid == 0) P[kk * ell + kk] = piv;
+      __syncthreads();
+      // rows kk+1 .. nb-1 of the panel, columns c >= r
+      const int rows = nb - kk - 1;
+      for (int idx = tid; idx < rows * w; idx += DB) {
+        const int r = kk + 1 + idx / w, c = idx % w;
+        if (c >= r) P[r * ell + c] -= P[kk * ell + r] * P[kk * ell + c];
+      }
+      __syncthreads();
+    }
+    if (badl) {
+      if (tid == 0) bad = 1;
+      break;
+    }
+    for (int idx = tid; idx < nb * w; idx += DB) {
+      const int r = idx / w, c = idx % w;
+      G[(int64_t)(k0 + r) * ell + k0 + c] = c >= r ? P[r * ell + c] : 0.0;
+    }
+    // trailing update of the upper triangle rows/cols >= k0 + nb
+    const int t = w - nb;
+    for (int64_t idx = tid; idx < (int64_t)t * t; idx += DB) {
+      const int i = nb + (int)(idx / t), j = nb + (int)(idx % t);
+      if (j < i) continue;
+      double acc = 0.0;
+      for (int kk = 0; kk < nb; ++kk) acc = fma(P[kk * ell + i], P[kk * ell + j], acc);
+      G[(int64_t)(k0 + i) * ell + k0 + j] -= acc;
+    }
+    __syncthreads();
+  }
+  for (int64_t idx = tid; idx < (int64_t)ell * ell; idx += DB) {
+    const int i = (int)(idx / ell), j = (int)(idx % ell);
+    if (i > j) G[idx] = 0.0;
+  }
+  if (tid == 0) *fail = bad ? 1.0 : 0.0;
+}
+
+// X = C^{-1} for upper-triangular C, one wave per column: column j solves
+// C x = e_j by back substitution, x_i = -(sum_{k=i+1..j} C[i][k] x_k) / C[i][i].
+// Lane l keeps x_k for k = l, l+64, ... in registers (ell <= 64*TRI_CH); the row
+// of C for the next step is loaded while the current one is reduced.
+constexpr int TRI_CH = 16;
+constexpr int TRI_WAVES = 4;
+__global__ __launch_bounds__(TRI_WAVES * NYS_WAVE) void k_tri_inv_cols(const double* C, double* X, int ell) {
+  const int lane = threadIdx.x % NYS_WAVE;
+  const int j = blockIdx.x * TRI_WAVES + threadIdx.x / NYS_WAVE;
+  if (j >= ell) return;                  // no block-level synchronisation below
+  double x[TRI_CH];
+#pragma unroll
+  for (int t = 0; t < TRI_CH; ++t) x[t] = 0.0;
+  const double xj = 1.0 / C[(int64_t)j * ell + j];
+#pragma unroll
+  for (int t = 0; t < TRI_CH; ++t)
+    if (t * NYS_WAVE + lane == j) x[t] = xj;
+  double cn[TRI_CH];
+  auto load_row = [&](int i, double* cr) {
+#pragma unroll
+    for (int t = 0; t < TRI_CH; ++t) {
+      const int k = t * NYS_WAVE + lane;
+      cr[t] = (k > i && k <= j) ? C[(int64_t)i * ell + k] : 0.0;
+    }
+  };
+  if (j > 0) load_row(j - 1, cn);
+  for (int i = j - 1; i >= 0; --i) {
+    double cr[TRI_CH];
+#pragma unroll
+    for (int t = 0; t < TRI_CH; ++t) cr[t] = cn[t];
+    const double cii = C[(int64_t)i * ell + i];
+    if (i > 0) load_row(i - 1, cn);
+    double s = 0.0;
+#pragma unroll
+    for (int t = 0; t < TRI_CH; ++t) s = fma(cr[t], x[t], s);
+    s = wave_sum_dpp(s);
+    const double xi = -s / cii;
+#pragma unroll
+    for (int t = 0; t < TRI_CH; ++t)
+      if (t * NYS_WAVE + lane == i) x[t] = xi;
+  }
+#pragma unroll
+  for (int t = 0; t < TRI_CH; ++t) {
+    const int k = t * NYS_WAVE + lane;
+    if (k < ell) X[(int64_t)k * ell + j] = x[t];
+  }
+}
+
 // ---------------------------------------------------------------- one-sided Jacobi SVD
 // Xc holds the columns contiguously (column k at Xc + k*ell).  One launch per
 // round of the round-robin ordering; one wave per column pair.
 __device__ __forceinline__ int rr_player(int p, int round, int np) {
   // np players 0..np-1 (np even); player 0 fixed, others rotate
   return p == 0 ? 0 : 1 + (p - 1 + round) % (np - 1);
+}
+
+// Rotation of the column pair (xp, xq) (length ell) that makes them
+// orthogonal, by one wave; returns whether it rotated.
+__device__ __forceinline__ bool jacobi_pair(double* xp, double* xq, int ell, double tol, int lane) {
+  double al = 0.0, be = 0.0, ga = 0.0;
+  for (int i = lane; i < ell; i += NYS_WAVE) {
+    const double u = xp[i], v = xq[i];
+    al = fma(u, u, al);
+    be = fma(v, v, be);
+    ga = fma(u, v, ga);
+  }
+  al = wave_sum_dpp(al);
+  be = wave_sum_dpp(be);
+  ga = wave_sum_dpp(ga);
+  if (!(fabs(ga) > tol * sqrt(al * be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+  for (int i = lane; i < ell; i += NYS_WAVE) {
+    const double u = xp[i], v = xq[i];
+    xp[i] = c * u - s * v;
+    xq[i] = s * u + c * v;
+  }
+  return true;
 }
 
 __global__ __launch_bounds__(NYS_WAVE) void k_jacobi_round(double* Xc, int ell, int np, int round,
@@ -218,27 +367,42 @@ __global__ __launch_bounds__(NYS_WAVE) void k_jacobi_round(double* Xc, int ell, 
   double* xp = Xc + (int64_t)p * ell;
   double* xq = Xc + (int64_t)q * ell;
   const int lane = threadIdx.x;
-  double al = 0.0, be = 0.0, ga = 0.0;
-  for (int i = lane; i < ell; i += NYS_WAVE) {
-    const double u = xp[i], v = xq[i];
-    al = fma(u, u, al);
-    be = fma(v, v, be);
-    ga = fma(u, v, ga);
+  if (jacobi_pair(xp, xq, ell, tol, lane) && lane == 0) atomicAdd(rotations, 1u);
+}
+
+// Block variant: the columns form groups of JG (the last ones padded), and a
+// launch is one round of the round-robin over groups.  Each block takes one
+// group pair, copies its 2*JG columns to LDS, runs one full round-robin sweep
+// over them there (2*JG - 1 rounds, one wave per column pair), and writes them
+// back.  Every column pair meets at least once per sweep over the group
+// rounds, so the convergence test (a sweep without rotations) is unchanged.
+template <int JG>
+__global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc, int ell, int ngp, int round,
+                                                                      double tol, unsigned* rotations) {
+  extern __shared__ double cols[];       // 2*JG columns of length ell
+  const int ga = rr_player(blockIdx.x, round, ngp);
+  const int gb = rr_player(ngp - 1 - blockIdx.x, round, ngp);
+  auto gcol = [&](int c) { return c < JG ? ga * JG + c : gb * JG + (c - JG); };
+  for (int idx = threadIdx.x; idx < 2 * JG * ell; idx += JG * NYS_WAVE) {
+    const int c = idx / ell, i = idx % ell;
+    const int g = gcol(c);
+    cols[idx] = g < ell ? Xc[(int64_t)g * ell + i] : 0.0;
   }
-  al = wave_sum(al);
-  be = wave_sum(be);
-  ga = wave_sum(ga);
-  if (!(fabs(ga) > tol * sqrt(al * be))) return;
-  const double zeta = (be - al) / (2.0 * ga);
-  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-  const double c = 1.0 / sqrt(1.0 + t * t);
-  const double s = c * t;
-  for (int i = lane; i < ell; i += NYS_WAVE) {
-    const double u = xp[i], v = xq[i];
-    xp[i] = c * u - s * v;
-    xq[i] = s * u + c * v;
+  __syncthreads();
+  const int wid = threadIdx.x / NYS_WAVE, lane = threadIdx.x % NYS_WAVE;
+  unsigned nrot = 0;
+  for (int r = 0; r < 2 * JG - 1; ++r) {
+    const int a = rr_player(wid, r, 2 * JG), b = rr_player(2 * JG - 1 - wid, r, 2 * JG);
+    const int p = min(a, b), q = max(a, b);
+    if (gcol(p) < ell && gcol(q) < ell && jacobi_pair(cols + p * ell, cols + q * ell, ell, tol, lane)) ++nrot;
+    __syncthreads();
   }
-  if (lane == 0) atomicAdd(rotations, 1u);
+  for (int idx = threadIdx.x; idx < 2 * JG * ell; idx += JG * NYS_WAVE) {
+    const int c = idx / ell, i = idx % ell;
+    const int g = gcol(c);
+    if (g < ell) Xc[(int64_t)g * ell + i] = cols[idx];
+  }
+  if (lane == 0 && nrot) atomicAdd(rotations, nrot);
 }
 
 __global__ __launch_bounds__(DB) void k_transpose_sq(const double* X, double* Y, int ell) {
@@ -389,13 +553,27 @@ int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64
 }
 
 int chol_upper(nys_handle h, double* G, int ell, double shift_abs, double shift_rel, double* fail) {
-  hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(DB), 0, h->stream, G, ell, shift_abs, shift_rel, fail);
+  // panel height: the largest power of two <= 32 whose NB x ell panel fits in
+  // 60 KB of LDS (the kernel's static LDS and 64 KB per block stay clear)
+  int nb = 32;
+  while (nb > 1 && (size_t)nb * ell * sizeof(double) > 61440) nb /= 2;
+  if (ell >= 2 * nb && nb >= 4) {
+    hipLaunchKernelGGL(k_chol_upper_blocked, dim3(1), dim3(DB), (size_t)nb * ell * sizeof(double), h->stream,
+                       G, ell, nb, shift_abs, shift_rel, fail);
+  } else {
+    hipLaunchKernelGGL(k_chol_upper, dim3(1), dim3(DB), 0, h->stream, G, ell, shift_abs, shift_rel, fail);
+  }
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }
 
 int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell) {
-  hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(DB), 0, h->stream, C, Cinv, ell);
+  if (ell <= TRI_CH * NYS_WAVE) {
+    hipLaunchKernelGGL(k_tri_inv_cols, dim3((unsigned)((ell + TRI_WAVES - 1) / TRI_WAVES)),
+                       dim3(TRI_WAVES * NYS_WAVE), 0, h->stream, C, Cinv, ell);
+  } else {
+    hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(DB), 0, h->stream, C, Cinv, ell);
+  }
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }
@@ -411,15 +589,37 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
   hipLaunchKernelGGL(k_transpose_sq, dim3(grid_for((int64_t)ell * ell)), dim3(DB), 0, h->stream, X, Xc, ell);
   NYS_LAUNCH_CHECK(h);
   const int np = ell + (ell & 1);
-  const double tol = sqrt((double)ell) * 2.220446049250313e-16;
+  // rotation threshold ell * eps: the computed cosine of two columns of length
+  // ell carries a rounding error up to about ell * eps, so a smaller threshold
+  // keeps rotating on noise and only stops when a sweep happens to find none
+  const double tol = (double)ell * 2.220446049250313e-16;
+  // group size of the block variant: the largest of 16, 8, 4, 2 whose 2*JG
+  // columns fit in 60 KB of LDS (0: per-pair launches)
+  int jg = 16;
+  while (jg >= 2 && (size_t)2 * jg * ell * sizeof(double) > 61440) jg /= 2;
+  if (jg < 2) jg = 0;
+  const int ng = jg ? (ell + jg - 1) / jg : 0;
+  const int ngp = ng + (ng & 1);
+  const size_t lds = (size_t)2 * jg * ell * sizeof(double);
   int sweep = 0;
   const int max_sweeps = 40;
   if (np >= 2) {
     for (; sweep < max_sweeps; ++sweep) {
       NYS_CHECK(zero_u32(h, rot, 1));
-      for (int round = 0; round < np - 1; ++round) {
-        hipLaunchKernelGGL(k_jacobi_round, dim3(np / 2), dim3(NYS_WAVE), 0, h->stream, Xc, ell, np,
-                           round, tol, rot);
+      if (jg) {
+        for (int round = 0; round < ngp - 1; ++round) {
+          switch (jg) {
+            case 16: hipLaunchKernelGGL(k_jacobi_block_round<16>, dim3(ngp / 2), dim3(16 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
+            case 8: hipLaunchKernelGGL(k_jacobi_block_round<8>, dim3(ngp / 2), dim3(8 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
+            case 4: hipLaunchKernelGGL(k_jacobi_block_round<4>, dim3(ngp / 2), dim3(4 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
+            default: hipLaunchKernelGGL(k_jacobi_block_round<2>, dim3(ngp / 2), dim3(2 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
+          }
+        }
+      } else {
+        for (int round = 0; round < np - 1; ++round) {
+          hipLaunchKernelGGL(k_jacobi_round, dim3(np / 2), dim3(NYS_WAVE), 0, h->stream, Xc, ell, np,
+                             round, tol, rot);
+        }
       }
       NYS_LAUNCH_CHECK(h);
       unsigned hrot = 0;

@@ -31,6 +31,14 @@
 #ifndef NYS_T_TARGET_BLOCKS
 #define NYS_T_TARGET_BLOCKS 2048
 #endif
+// Rows per block of the row-streaming passes on large matrices (pass 2 on A,
+// pass 1 on A^T): 1, 2, 4, 8 or 16.
+#ifndef NYS_N_RB
+#define NYS_N_RB 8
+#endif
+#ifndef NYS_TT_RB
+#define NYS_TT_RB 8
+#endif
 
 namespace nys {
 namespace {
@@ -231,37 +239,27 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
 }
 
 // Pass 1 on A^T (rows = n rows of A^T, cols = m):
-//   w[j] = d[j] * (sA * sum_i At[j,i] v_i + x0[j]),
-// v_i = v[i] or, fused, s[i] + beta * pold[i] (each block also stores its
-// share of that new direction to pnew).
+//   w[j] = d[j] * (sA * sum_i At[j,i] v_i + x0[j]).
+// (The CG direction update runs before it as its own small kernel: fusing it
+// here makes every block read two vectors instead of one, which measured ~4%
+// slower than the extra launch.)
 struct TTArgs {
   const double* skip;
   const char* At;
   int64_t rows, cols, row_bytes;
   const double* v;
-  const double* s;
-  const double* pold;
-  double* pnew;
-  const double* beta;
   const double* d;
   const double* x0;
   double sA;
   double* w;
 };
 
-template <class T, int RB, bool VECLOAD, bool FUSEDP>
+template <class T, int RB, bool VECLOAD>
 __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_tt(TTArgs a) {
   using raw = typename T::raw;
   constexpr int VEC = T::vec;
   __shared__ double smem[RB * (NYS_BLOCK / NYS_WAVE)];
   if (a.skip && *a.skip != 0.0) return;
-  const double beta = FUSEDP ? *a.beta : 0.0;
-  if constexpr (FUSEDP) {
-    const int64_t per = (a.cols + gridDim.x - 1) / gridDim.x;
-    const int64_t lo = (int64_t)blockIdx.x * per;
-    const int64_t hi = min(a.cols, lo + per);
-    for (int64_t i = lo + threadIdx.x; i < hi; i += NYS_BLOCK) a.pnew[i] = a.s[i] + beta * a.pold[i];
-  }
   const int64_t j0 = (int64_t)blockIdx.x * RB;
   const int nr = (int)max((int64_t)0, min((int64_t)RB, a.rows - j0));
   double acc[RB];
@@ -279,15 +277,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_tt(TTArgs a) {
       for (int r = 0; r < RB; ++r)
         if (r < nr) u[r] = ld_stream16(base + r * a.row_bytes + i * (int64_t)sizeof(raw));
       double vv[VEC];
-      if constexpr (FUSEDP) {
-        double sv[VEC], pv[VEC];
-        ld_f64s<VEC>(a.s + i, sv);
-        ld_f64s<VEC>(a.pold + i, pv);
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) vv[e] = sv[e] + beta * pv[e];
-      } else {
-        ld_f64s<VEC>(a.v + i, vv);
-      }
+      ld_f64s<VEC>(a.v + i, vv);
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         if (r < nr) {
@@ -301,7 +291,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_tt(TTArgs a) {
     itail = nv * VEC;
   }
   for (int64_t i = itail + threadIdx.x; i < a.cols; i += NYS_BLOCK) {
-    const double vi = FUSEDP ? a.s[i] + beta * a.pold[i] : a.v[i];
+    const double vi = a.v[i];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
       if (r < nr) acc[r] = fma(to_f64(((const raw*)(a.At + (j0 + r) * a.row_bytes))[i]), vi, acc[r]);
@@ -318,6 +308,16 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_tt(TTArgs a) {
       }
     }
   }
+}
+
+// pnew = s + beta * pold (beta from a device word), skip-aware.
+__global__ __launch_bounds__(NYS_BLOCK) void k_dir_update(const double* skip, const double* s,
+                                                          const double* pold, const double* beta,
+                                                          double* pnew, int64_t m) {
+  if (skip && *skip != 0.0) return;
+  const double b = *beta;
+  for (int64_t i = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; i < m; i += (int64_t)gridDim.x * NYS_BLOCK)
+    pnew[i] = s[i] + b * pold[i];
 }
 
 // At (n x m, row pitch ldt_bytes) = A^T through a 64 x 64 LDS tile.
@@ -371,62 +371,61 @@ void launch_n_rb(T2Args& k, bool vecload, hipStream_t st) {
 template <class T>
 void dispatch_n(T2Args& k, bool vecload, hipStream_t st) {
   const int64_t m = k.m;
-  if (m >= 8 * 1536) launch_n_rb<T, 8>(k, vecload, st);
+  if (m >= 8 * 1536) launch_n_rb<T, NYS_N_RB>(k, vecload, st);
   else if (m >= 4 * 1024) launch_n_rb<T, 4>(k, vecload, st);
   else if (m >= 2 * 1024) launch_n_rb<T, 2>(k, vecload, st);
   else launch_n_rb<T, 1>(k, vecload, st);
 }
 
 template <class T, int RB>
-void launch_tt_rb(TTArgs& k, bool vecload, bool fused, hipStream_t st) {
+void launch_tt_rb(TTArgs& k, bool vecload, hipStream_t st) {
   dim3 g((unsigned)std::max<int64_t>(1, (k.rows + RB - 1) / RB));
-  if (fused) {
-    if (vecload) hipLaunchKernelGGL((k_gemv_tt<T, RB, true, true>), g, dim3(NYS_BLOCK), 0, st, k);
-    else hipLaunchKernelGGL((k_gemv_tt<T, RB, false, true>), g, dim3(NYS_BLOCK), 0, st, k);
-  } else {
-    if (vecload) hipLaunchKernelGGL((k_gemv_tt<T, RB, true, false>), g, dim3(NYS_BLOCK), 0, st, k);
-    else hipLaunchKernelGGL((k_gemv_tt<T, RB, false, false>), g, dim3(NYS_BLOCK), 0, st, k);
-  }
+  if (vecload) hipLaunchKernelGGL((k_gemv_tt<T, RB, true>), g, dim3(NYS_BLOCK), 0, st, k);
+  else hipLaunchKernelGGL((k_gemv_tt<T, RB, false>), g, dim3(NYS_BLOCK), 0, st, k);
 }
 
 template <class T>
-void dispatch_tt(TTArgs& k, bool vecload, bool fused, hipStream_t st) {
+void dispatch_tt(TTArgs& k, bool vecload, hipStream_t st) {
   const int64_t r = k.rows;
-  if (r >= 8 * 1536) launch_tt_rb<T, 8>(k, vecload, fused, st);
-  else if (r >= 4 * 1024) launch_tt_rb<T, 4>(k, vecload, fused, st);
-  else if (r >= 2 * 1024) launch_tt_rb<T, 2>(k, vecload, fused, st);
-  else launch_tt_rb<T, 1>(k, vecload, fused, st);
+  if (r >= 8 * 1536) launch_tt_rb<T, NYS_TT_RB>(k, vecload, st);
+  else if (r >= 4 * 1024) launch_tt_rb<T, 4>(k, vecload, st);
+  else if (r >= 2 * 1024) launch_tt_rb<T, 2>(k, vecload, st);
+  else launch_tt_rb<T, 1>(k, vecload, st);
 }
 
 bool al16(const void* p) { return ((uintptr_t)p % 16) == 0; }
 
-// Pass 1 over the caller's (or the workspace's) transposed copy of A.
+// Pass 1 over the caller's (or the workspace's) transposed copy of A; a
+// fused direction update runs first as k_dir_update.
 int gemv_t_rows(nys_handle h, const GemvT& a) {
   const nys_matrix* A = a.A;
   const int es = elem_size(A->dtype);
-  const bool fused = a.s != nullptr;
+  const double* v = a.v;
+  if (a.s) {
+    const int64_t nb = std::max<int64_t>(1, std::min<int64_t>((A->m + NYS_BLOCK - 1) / NYS_BLOCK, 1024));
+    hipLaunchKernelGGL(k_dir_update, dim3((unsigned)nb), dim3(NYS_BLOCK), 0, h->stream, a.skip, a.s, a.pold,
+                       a.beta, a.pnew, A->m);
+    NYS_LAUNCH_CHECK(h);
+    v = a.pnew;
+  }
+  if (A->n == 0) return NYS_OK;
   TTArgs k{};
   k.skip = a.skip;
   k.At = (const char*)A->data_t;
   k.rows = A->n;
   k.cols = A->m;
   k.row_bytes = A->ld_t * es;
-  k.v = a.v;
-  k.s = a.s;
-  k.pold = a.pold;
-  k.pnew = a.pnew;
-  k.beta = a.beta;
+  k.v = v;
   k.d = a.d;
   k.x0 = a.x0;
   k.sA = a.sA;
   k.w = a.w;
-  const bool vl = al16(A->data_t) && (k.row_bytes % 16 == 0) &&
-                  (fused ? al16(a.s) && al16(a.pold) : al16(a.v));
+  const bool vl = al16(A->data_t) && (k.row_bytes % 16 == 0) && al16(v);
   const int ps = prof_begin(h, NYS_K_NORMAL_PASS1);
   switch (A->dtype) {
-    case NYS_F64: dispatch_tt<F64>(k, vl, fused, h->stream); break;
-    case NYS_F32: dispatch_tt<F32>(k, vl, fused, h->stream); break;
-    case NYS_BF16: dispatch_tt<BF16>(k, vl, fused, h->stream); break;
+    case NYS_F64: dispatch_tt<F64>(k, vl, h->stream); break;
+    case NYS_F32: dispatch_tt<F32>(k, vl, h->stream); break;
+    case NYS_BF16: dispatch_tt<BF16>(k, vl, h->stream); break;
     default: return set_error(h, NYS_EINVAL, "gemv_t: bad dtype");
   }
   prof_end(h, ps);
@@ -435,7 +434,7 @@ int gemv_t_rows(nys_handle h, const GemvT& a) {
 }
 
 int n_blocks_pass2(int64_t m) {
-  const int rb = m >= 8 * 1536 ? 8 : m >= 4 * 1024 ? 4 : m >= 2 * 1024 ? 2 : 1;
+  const int rb = m >= 8 * 1536 ? NYS_N_RB : m >= 4 * 1024 ? 4 : m >= 2 * 1024 ? 2 : 1;
   return (int)((m + rb - 1) / rb);
 }
 

@@ -145,7 +145,9 @@ int nys_test_matrix(nys_handle h, int64_t m, int32_t ell, uint64_t seed, uint64_
    sketch_dtype NYS_F64: FP64 arithmetic, A stored FP64 or FP32.
    NYS_BF16: A stored BF16; Omega and W are rounded to BF16 (round to nearest
    even, through FP32) and both products run on matrix cores with FP32
-   accumulation; Y's split partial sums are added in FP64.  Enqueue only. */
+   accumulation; Y's split partial sums are added in FP64.  With a BF16
+   transposed copy in A->data_t both products read k-contiguous operands
+   (wider tiles; same arithmetic).  Enqueue only. */
 int nys_sketch_product(nys_handle h, const nys_matrix* A, const double* d, const double* omega,
                        int32_t ell, nys_dtype sketch_dtype, double* Y);
 

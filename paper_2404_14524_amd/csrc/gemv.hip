@@ -549,16 +549,16 @@ int transpose(nys_handle h, const nys_matrix* A, void* At, int64_t ld_t) {
   return NYS_OK;
 }
 
-int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, nys_matrix* out) {
+int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, int slot, nys_matrix* out) {
   *out = *A;
   if (A->data_t || !allowed || A->m == 0 || A->n == 0) return NYS_OK;
   const int es = elem_size(A->dtype);
   const int64_t per16 = 16 / es;
   const int64_t ld_t = (A->m + per16 - 1) / per16 * per16;
   void* p = nullptr;
-  const int rc = ws_get(h, WS_AT, (size_t)A->n * ld_t * es, &p);
+  const int rc = ws_get(h, slot, (size_t)A->n * ld_t * es, &p);
   if (rc == NYS_ENOMEM) {
-    h->err.clear();   // not enough memory for the copy: pass 1 reads column stripes of A
+    h->err.clear();   // not enough memory for the copy: the kernels read A as it is
     return NYS_OK;
   }
   NYS_CHECK(rc);

@@ -31,6 +31,7 @@ enum nys_slot {
   WS_PCU,         // preconditioner U (ipm_solve / ipm_adjoint internal)
   WS_PCL,         // preconditioner lambda (ipm_solve / ipm_adjoint internal)
   WS_AT,          // transposed copy of A made by ipm_solve / ipm_adjoint
+  WS_ALOT,        // transposed copy of the BF16 matrix of the sketch
   WS_NSLOTS
 };
 

@@ -288,7 +288,7 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     if (hs[6] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: q has negative entries");
   }
   nys_matrix At{};
-  NYS_CHECK(with_transpose(h, A, o.transpose, &At));
+  NYS_CHECK(with_transpose(h, A, o.transpose, WS_AT, &At));
   A = &At;
 
   // ---- workspace
@@ -319,9 +319,11 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
   NYS_CHECK(ws(h, WS_PCL, (size_t)o.ell + 8, &lamh));
   nys_matrix Alo{};
   const nys_matrix* Ask = A;
+  nys_matrix Alot{};
   if (o.sk == NYS_BF16) {
     NYS_CHECK(lo_matrix(h, qp, &Alo));
-    Ask = &Alo;
+    NYS_CHECK(with_transpose(h, &Alo, o.transpose, WS_ALOT, &Alot));
+    Ask = &Alot;
   }
   int pcg_total = 0;
 
@@ -530,7 +532,7 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   const auto t_start = clk::now();
   h->t_sketch = h->t_pcg = h->t_other = 0.0;
   nys_matrix At{};
-  NYS_CHECK(with_transpose(h, A, o.transpose, &At));
+  NYS_CHECK(with_transpose(h, A, o.transpose, WS_AT, &At));
   A = &At;
   double* base;
   NYS_CHECK(ws(h, WS_IPM, (size_t)12 * n + 8 * m + 64, &base));
@@ -544,9 +546,11 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   NYS_CHECK(ws(h, WS_PCL, (size_t)o.ell + 8, &lamh));
   nys_matrix Alo{};
   const nys_matrix* Ask = A;
+  nys_matrix Alot{};
   if (o.sk == NYS_BF16) {
     NYS_CHECK(lo_matrix(h, qp, &Alo));
-    Ask = &Alo;
+    NYS_CHECK(with_transpose(h, &Alo, o.transpose, WS_ALOT, &Alot));
+    Ask = &Alot;
   }
   NYS_CHECK(map_reduce<0, 0>(h, n, AdjD{D, tn, qp->q, x, z, g, rho}, nullptr));
   GemvN g2;

@@ -46,10 +46,10 @@ int gemv_n(nys_handle h, const GemvN& a);
 
 // At (n x m, leading dimension ld_t >= m elements, A's dtype) = A^T.
 int transpose(nys_handle h, const nys_matrix* A, void* At, int64_t ld_t);
-// *out = *A with data_t pointing at a transposed copy in the WS_AT slot (made
-// here unless A already has one or `allowed` is false; without memory for it,
-// *out = *A and the column-stripe pass 1 is used).
-int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, nys_matrix* out);
+// *out = *A with data_t pointing at a transposed copy in workspace slot `slot`
+// (made here unless A already has one or `allowed` is false; without memory
+// for it, *out = *A and the kernels read A as it is).
+int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, int slot, nys_matrix* out);
 
 // out = (A diag(d) A^T + delta I) v, with optional *dot_out = v^T out.
 int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,

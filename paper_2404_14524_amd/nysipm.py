@@ -218,7 +218,7 @@ def nys_test_matrix(m: int, ell: int, seed: int, counter: int, device="cuda") ->
 
 
 def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sketch_dtype="f64",
-                       out: Optional[torch.Tensor] = None) -> torch.Tensor:
+                       out: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None) -> torch.Tensor:
     lib, h = _handle(A.device)
     m, n = A.shape
     ell = omega.shape[1]
@@ -226,14 +226,15 @@ def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sk
     _vec(omega.reshape(-1), m * ell, "omega", A.device)
     Y = torch.empty((m, ell), dtype=torch.float64, device=A.device) if out is None else out
     _vec(Y.reshape(-1), m * ell, "out", A.device)
-    Am = _mat(A)
+    Am = _mat(A, A_t)
     _check(lib, h, lib.nys_sketch_product(h, C.byref(Am), _ptr(d), _ptr(omega), ell, _SK[sketch_dtype],
                                           _ptr(Y)))
     return Y
 
 
 def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,
-               sketch_dtype="f64", omega: Optional[torch.Tensor] = None) -> Precond:
+               sketch_dtype="f64", omega: Optional[torch.Tensor] = None,
+               A_t: Optional[torch.Tensor] = None) -> Precond:
     lib, h = _handle(A.device)
     m, n = A.shape
     _vec(d, n, "d", A.device)
@@ -243,7 +244,7 @@ def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counte
     lam = torch.empty(ell, dtype=torch.float64, device=A.device)
     P = nys_precond(m, ell, U.data_ptr(), lam.data_ptr())
     nu = C.c_double(0.0)
-    Am = _mat(A)
+    Am = _mat(A, A_t)
     _check(lib, h, lib.nys_sketch(h, C.byref(Am), _ptr(d), ell, seed, counter, _SK[sketch_dtype],
                                   _ptr(omega), C.byref(P), C.byref(nu)))
     return Precond(U, lam, nu.value)

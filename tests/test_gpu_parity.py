@@ -163,9 +163,10 @@ def test_sketch_fp64_parity(nys, m, n, ell):
 
 
 @pytest.mark.parametrize("m,n,ell", [(1, 9, 1), (130, 257, 7), (1000, 3000, 100), (2000, 8000, 50),
-                                     (777, 5001, 200)])
+                                     (777, 5001, 200), (300, 1000, 257), (515, 2049, 400)])
 def test_sketch_product_parity(nys, m, n, ell):
-    """Y = A diag(d) A^T Omega in FP64 and on BF16 matrix cores."""
+    """Y = A diag(d) A^T Omega in FP64 and on BF16 matrix cores (both the
+    128-wide tiles on A alone and the 256-wide tiles with a transposed copy)."""
     print(f"sketch_product {m}x{n} ell={ell}", flush=True)
     rng = np.random.default_rng(m + n + ell)
     A = rng.standard_normal((m, n)) / np.sqrt(n)
@@ -179,16 +180,17 @@ def test_sketch_product_parity(nys, m, n, ell):
     # BF16 matrix cores, FP32 accumulation, against the emulated-BF16 oracle
     A32 = A.astype(np.float32)
     Abf = _t(A32, torch.float32).to(torch.bfloat16)
-    Yb = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16"))
     refb = lowprec.sketch_bf16(A32.astype(np.float64), d, Om)
     Ab = lowprec.round_bf16(A32.astype(np.float64))
     boundb = np.abs(Ab) @ (d[:, None] * (np.abs(Ab).T @ np.abs(lowprec.round_bf16(Om))))
-    # Worst case per entry: FP32 accumulation errors (m + n terms) plus a BF16
-    # rounding of W that lands on the other side of a tie, at most 2^-8 |W|.
-    err = np.abs(Yb - refb)
-    assert np.all(err <= (2.0 ** -8 + 2.0 ** -24 * (m + n)) * boundb + 1e-300)
-    # typical: the flips are rare and the FP32 errors average out
-    assert np.linalg.norm(Yb - refb) <= 1e-4 * np.linalg.norm(refb)
+    for A_t in (None, nys.nys_transpose(Abf)):
+        Yb = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16", A_t=A_t))
+        # Worst case per entry: FP32 accumulation errors (m + n terms) plus a BF16
+        # rounding of W that lands on the other side of a tie, at most 2^-8 |W|.
+        err = np.abs(Yb - refb)
+        assert np.all(err <= (2.0 ** -8 + 2.0 ** -24 * (m + n)) * boundb + 1e-300)
+        # typical: the flips are rare and the FP32 errors average out
+        assert np.linalg.norm(Yb - refb) <= 1e-4 * np.linalg.norm(refb)
 
 
 @pytest.mark.parametrize("m,n,ell", [(600, 2000, 40), (1500, 6000, 120)])
@@ -201,7 +203,7 @@ def test_sketch_bf16_parity(nys, m, n, ell):
     d = rng.uniform(0.01, 10.0, n)
     Om = rng.standard_normal((m, ell))
     Abf = inst.A.to(DEV).to(torch.bfloat16)
-    P = nys.nys_sketch(Abf, _t(d), ell, omega=_t(Om), sketch_dtype="bf16")
+    P = nys.nys_sketch(Abf, _t(d), ell, omega=_t(Om), sketch_dtype="bf16", A_t=nys.nys_transpose(Abf))
     Omq = nystrom.orthonormalize(Om)
     Y = lowprec.sketch_bf16(A32.astype(np.float64), d, Omq)
     Uo, lo, nuo = nystrom.nystrom_from_sketch(Y, Omq, precision="bf16")

@@ -128,7 +128,9 @@ int nys_normal_apply(nys_handle h, const nys_matrix* A, const double* d, double 
 /* Storage layout helper for nys_matrix.data_t (not a step of the method):
    out (n x m row-major, leading dimension ld_out >= m elements, A's dtype,
    caller-owned, must not overlap A) = A^T, so that A^T v products stream
-   whole rows.  Elements m .. ld_out-1 of each row are left untouched.
+   whole rows.  Elements m .. ld_out-1 of each row are left untouched.  Rows
+   whose pitch is a multiple of 128 bytes stream fastest (the copies the
+   library makes use that pitch).
    NYS_EINVAL on bad arguments or m > 4194240.  Enqueue only. */
 int nys_transpose(nys_handle h, const nys_matrix* A, void* out, int64_t ld_out);
 

@@ -552,9 +552,12 @@ int transpose(nys_handle h, const nys_matrix* A, void* At, int64_t ld_t) {
 int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, int slot, nys_matrix* out) {
   *out = *A;
   if (A->data_t || !allowed || A->m == 0 || A->n == 0) return NYS_OK;
+  // rows start on 128-byte boundaries: a row pitch off by 64 bytes makes every
+  // 1 KB wave load of a row touch nine cache lines instead of eight (measured
+  // 5 % on pass 1 at m = 50000 FP32)
   const int es = elem_size(A->dtype);
-  const int64_t per16 = 16 / es;
-  const int64_t ld_t = (A->m + per16 - 1) / per16 * per16;
+  const int64_t per = 128 / es;
+  const int64_t ld_t = (A->m + per - 1) / per * per;
   void* p = nullptr;
   const int rc = ws_get(h, slot, (size_t)A->n * ld_t * es, &p);
   if (rc == NYS_ENOMEM) {

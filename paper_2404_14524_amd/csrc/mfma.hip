@@ -225,8 +225,10 @@ __global__ __launch_bounds__(WTHREADS) void k_mfma_nt_wide(int64_t M, int64_t N,
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
 
-  u16x8 ra[WAPT], rb[WBPT];
-  auto load_tiles = [&](int64_t k0) {
+  // Two register sets, loaded two k-steps ahead: one block per CU (150+
+  // VGPRs), so the loads of the step after next are what cover HBM latency.
+  u16x8 ra0[WAPT], rb0[WBPT], ra1[WAPT], rb1[WBPT];
+  auto load_tiles = [&](int64_t k0, u16x8* ra, u16x8* rb) {
 #pragma unroll
     for (int p = 0; p < WAPT; ++p) {
       const int idx = tid + p * WTHREADS;
@@ -238,7 +240,7 @@ __global__ __launch_bounds__(WTHREADS) void k_mfma_nt_wide(int64_t M, int64_t N,
       rb[p] = load_k8(B, ldb, n0 + idx / KCH, N, k0 + (idx % KCH) * 8, ke, vecb);
     }
   };
-  auto store_tiles = [&]() {
+  auto store_tiles = [&](const u16x8* ra, const u16x8* rb) {
 #pragma unroll
     for (int p = 0; p < WAPT; ++p) {
       const int idx = tid + p * WTHREADS;
@@ -250,12 +252,7 @@ __global__ __launch_bounds__(WTHREADS) void k_mfma_nt_wide(int64_t M, int64_t N,
       *(u16x8*)(Bs + (idx / KCH) * LDK + (idx % KCH) * 8) = rb[p];
     }
   };
-
-  if (kb < ke) load_tiles(kb);
-  for (int64_t k0 = kb; k0 < ke; k0 += TBK) {
-    store_tiles();
-    __syncthreads();
-    if (k0 + TBK < ke) load_tiles(k0 + TBK);
+  auto compute = [&]() {
 #pragma unroll
     for (int ks = 0; ks < TBK; ks += 16) {
       const int kk = ks + 8 * (lane >> 5);
@@ -273,6 +270,21 @@ __global__ __launch_bounds__(WTHREADS) void k_mfma_nt_wide(int64_t M, int64_t N,
         for (int tj = 0; tj < 2; ++tj)
           acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
     }
+  };
+
+  if (kb < ke) load_tiles(kb, ra0, rb0);
+  if (kb + TBK < ke) load_tiles(kb + TBK, ra1, rb1);
+  for (int64_t k0 = kb; k0 < ke; k0 += 2 * TBK) {
+    store_tiles(ra0, rb0);
+    __syncthreads();
+    if (k0 + 2 * TBK < ke) load_tiles(k0 + 2 * TBK, ra0, rb0);
+    compute();
+    __syncthreads();
+    if (k0 + TBK >= ke) break;
+    store_tiles(ra1, rb1);
+    __syncthreads();
+    if (k0 + 3 * TBK < ke) load_tiles(k0 + 3 * TBK, ra1, rb1);
+    compute();
     __syncthreads();
   }
   if constexpr (STAGE_T) {

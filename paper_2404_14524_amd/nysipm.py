@@ -191,10 +191,12 @@ def nys_transpose(A: torch.Tensor) -> torch.Tensor:
     written by the library's transpose kernel."""
     lib, h = _handle(A.device)
     m, n = A.shape
-    out = torch.empty((n, m), dtype=A.dtype, device=A.device)
+    per = 128 // A.element_size()          # 128-byte row pitch
+    ld = max((m + per - 1) // per * per, 1)
+    buf = torch.empty((n, ld), dtype=A.dtype, device=A.device)
     Am = _mat(A)
-    _check(lib, h, lib.nys_transpose(h, C.byref(Am), _ptr(out), max(m, 1)))
-    return out
+    _check(lib, h, lib.nys_transpose(h, C.byref(Am), _ptr(buf), ld))
+    return buf[:, :m]
 
 
 def nys_normal_apply(A: torch.Tensor, d: torch.Tensor, delta: float, v: torch.Tensor,

@@ -152,3 +152,53 @@ def test_ipm_solve_full_size(nys, name, sk):
     err = float(torch.linalg.norm(x - inst.x_star) / torch.linalg.norm(inst.x_star))
     assert err <= 1e-5, err
     assert bool((x > 0).all()) and bool((z > 0).all())
+
+
+def test_large_mixed_solve_and_adjoint_full_size(nys):
+    """lowrank_50000x200000 (FP32 A of 40 GB, BF16 sketch with ell = 400):
+    forward solve to KKT <= 1e-6, then the adjoint gradient with respect to c
+    and b.  The oracle's dense KKT gradient does not fit at this size, so the
+    gradient is checked through the adjoint system it must satisfy, with the
+    support S = {x > z} of the computed solution and u1 = -dL/dc, u2 = dL/db:
+      A u1 = 0 on 64 sampled rows, q_j u1_j + (A^T u2)_j = g_j on 64 sampled
+      columns of S (those with q_j above the final rho), and u1_j = 0 off S;
+    together these equations determine (u1, u2), and each sampled equation is
+    evaluated in FP64 on the CPU from the rows and columns of A."""
+    print("full-size solve + adjoint lowrank_50000x200000", flush=True)
+    inst = make_instance("lowrank_50000x200000", seed=0, device=DEV)
+    A = inst.A
+    A_lo = A.to(torch.bfloat16)
+    x, y, z, info = nys.ipm_solve(A, inst.b, inst.c, inst.q, ell=inst.ell, tol=1e-6, seed=0, sketch_dtype="bf16",
+                                  A_lo=A_lo)
+    print(f"forward: iters={info.iters} pcg={info.pcg_iters_total} kkt={info.kkt_rel:.2e}", flush=True)
+    assert info.status == 0 and info.kkt_rel <= 1e-6
+    xs = inst.x_star
+    assert float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)) <= 1e-5
+    g = torch.Generator(device=DEV)
+    g.manual_seed(11)
+    x_tgt = xs + 0.01 * torch.randn(inst.n, generator=g, dtype=torch.float64, device=DEV)
+    gvec = x - x_tgt
+    grads, pinfo = nys.ipm_adjoint(A, inst.b, inst.c, inst.q, x, y, z, info.rho, info.delta, gvec, ell=inst.ell,
+                                   A_lo=A_lo, want=("c", "b"), sketch_dtype="bf16")
+    print(f"adjoint pcg: iters={pinfo.iters} status={pinfo.status} rel_res={pinfo.rel_res:.2e}", flush=True)
+    assert pinfo.status == 0
+    u1 = -grads["c"].cpu().numpy()
+    u2 = grads["b"].cpu().numpy()
+    gh = gvec.cpu().numpy()
+    S = (x > z).cpu().numpy()
+    q = inst.q.cpu().numpy()
+    assert np.all(u1[~S] == 0.0)
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(inst.m, 64, replace=False))
+    Ar = A[torch.from_numpy(rows).to(DEV)].cpu().numpy().astype(np.float64)
+    res_rows = Ar @ u1
+    scale_rows = np.abs(Ar) @ np.abs(u1)
+    assert np.all(np.abs(res_rows) <= 1e-6 * scale_rows), np.max(np.abs(res_rows) / scale_rows)
+    # (columns with q_j below the final regularisation use D_j = 1/rho instead of 1/q_j)
+    cols = np.sort(rng.choice(np.flatnonzero(S & (q > info.rho)), 64, replace=False))
+    Ac = A[:, torch.from_numpy(cols).to(DEV)].cpu().numpy().astype(np.float64)
+    res_cols = q[cols] * u1[cols] + Ac.T @ u2 - gh[cols]
+    scale_cols = np.abs(q[cols] * u1[cols]) + np.abs(Ac).T @ np.abs(u2) + np.abs(gh[cols])
+    assert np.all(np.abs(res_cols) <= 1e-8 * scale_cols), np.max(np.abs(res_cols) / scale_cols)
+    del inst, A, A_lo
+    torch.cuda.empty_cache()

@@ -250,12 +250,30 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
     if (info) *info = out;
     return NYS_OK;
   }
-  if (y_zero) NYS_CHECK(copy(h, r, rhs, m));
-  else NYS_CHECK(true_residual(r));
+  double r0norm = bnorm;
+  if (y_zero) {
+    NYS_CHECK(copy(h, r, rhs, m));
+  } else {
+    NYS_CHECK(true_residual(r));
+    NYS_CHECK(read_scalars(h, SC_RED0 + 1, 1));
+    r0norm = std::sqrt(h->hscal[SC_RED0 + 1]);
+  }
+  if (r0norm <= tol) {
+    // the starting point already meets the tolerance (a zero right-hand side
+    // with a zero guess included): no iteration, and none could proceed, since
+    // r = 0 gives p = 0 and p^T M p = 0
+    out.true_res = r0norm;
+    out.rel_res = bnorm > 0 ? r0norm / bnorm : r0norm;
+    if (info) *info = out;
+    return NYS_OK;
+  }
   NYS_CHECK(set_scalars(h, 4, SC_DONE, 0.0, SC_BREAK, 0.0, SC_ITERS, 0.0, SC_BETA, 0.0));
   NYS_CHECK(set_scalars(h, 1, SC_TOL2, tol * tol));
   NYS_CHECK(fill(h, pa, m, 0.0));
   NYS_CHECK(refresh_s());
+  // refresh_s leaves beta = (r^T s) / (the previous solve's r^T s); the first
+  // direction is p = s, and beta * 0 would be NaN if that old value were 0
+  NYS_CHECK(set_scalars(h, 1, SC_BETA, 0.0));
   const double* sdir = pre ? s : r;
 
   int status = NYS_MAXIT;

@@ -140,7 +140,8 @@ def test_adjoint_full_size_differentiation_workload(nys):
         assert np.linalg.norm(gk - fd) <= 1e-4 * np.linalg.norm(fd), block
 
 
-@pytest.mark.parametrize("name,sk", [("lowrank_5000x20000", "f64"), ("gauss_2000x8000", "bf16")])
+@pytest.mark.parametrize("name,sk", [("lowrank_5000x20000", "f64"), ("gauss_2000x8000", "bf16"),
+                                     ("lowrank_20000x100000", "bf16")])
 def test_ipm_solve_full_size(nys, name, sk):
     print(f"full-size ipm_solve {name} {sk}", flush=True)
     inst = make_instance(name, seed=0, device=DEV)
@@ -152,6 +153,8 @@ def test_ipm_solve_full_size(nys, name, sk):
     err = float(torch.linalg.norm(x - inst.x_star) / torch.linalg.norm(inst.x_star))
     assert err <= 1e-5, err
     assert bool((x > 0).all()) and bool((z > 0).all())
+    del inst, A, A_lo
+    torch.cuda.empty_cache()
 
 
 def test_large_mixed_solve_and_adjoint_full_size(nys):

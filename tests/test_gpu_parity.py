@@ -334,6 +334,63 @@ def test_ipm_solve_rejects_bad_data(nys):
         nys.ipm_solve(A, b, c, q, ell=0)
 
 
+def _planted(m, n, nsupp, q, seed):
+    """Planted KKT point (x*, y*, z*) with |support| = nsupp and b, c from it."""
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    S = rng.permutation(n)[:nsupp]
+    xs = np.zeros(n)
+    xs[S] = rng.uniform(0.1, 1.0, nsupp)
+    zs = rng.uniform(0.1, 1.0, n)
+    zs[S] = 0.0
+    ys = rng.standard_normal(m)
+    return A, A @ xs, A.T @ ys + zs - q * xs, xs, ys, zs
+
+
+def test_ipm_solve_lp_planted_vertex(nys):
+    """Q = 0 (a linear program): the planted optimum is a vertex with m basic
+    variables, unique because A_S is square and nonsingular."""
+    m, n = 30, 80
+    q = np.zeros(n)
+    A, b, c, xs, ys, zs = _planted(m, n, m, q, seed=3)
+    ref = oipm.solve(A, b, c, q, tol=1e-10)
+    xo, _, _, polished = oipm.polish(A, b, c, q, ref["x"], ref["y"], ref["z"])
+    assert polished and np.linalg.norm(xo - xs) <= 1e-10 * np.linalg.norm(xs)
+    x, y, z, info = nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=10, tol=1e-8, seed=0)
+    assert info.status == 0
+    assert problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))["kkt"] <= 1e-8
+    assert np.linalg.norm(_np(x) - xs) <= 1e-5 * np.linalg.norm(xs)
+
+
+def test_ipm_solve_single_constraint(nys):
+    """m = 1 (ell = 1): the smallest problem the method defines."""
+    n = 7
+    q = np.random.default_rng(4).uniform(0.5, 1.0, n)
+    A, b, c, xs, ys, zs = _planted(1, n, 3, q, seed=4)
+    x, y, z, info = nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=1, tol=1e-8, seed=0)
+    assert info.status == 0
+    assert problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))["kkt"] <= 1e-8
+    assert np.linalg.norm(_np(x) - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_pcg_zero_rhs_and_full_rank_sketch(nys):
+    """rhs = 0 returns y = 0 without iterating; with ell = m the Nystrom
+    approximation is N itself, so P^{-1} M is a multiple of I and PCG takes
+    one iteration."""
+    m, n = 64, 300
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    d = rng.uniform(0.1, 2.0, n)
+    y, info = nys.nys_pcg_solve(_t(A), _t(d), 1e-2, _t(np.zeros(m)))
+    assert info.iters == 0 and info.status == 0 and not bool(y.any())
+    P = nys.nys_sketch(_t(A), _t(d), m, seed=2)
+    xi = rng.standard_normal(m)
+    y, info = nys.nys_pcg_solve(_t(A), _t(d), 1e-2, _t(xi), P=P, rtol=1e-9, poll_every=1)
+    assert info.status == 0 and info.iters <= 2, info.iters
+    M = normal_eq.normal_matrix(A, d, 1e-2)
+    np.testing.assert_allclose(_np(y), np.linalg.solve(M, xi), rtol=1e-7, atol=1e-9)
+
+
 def test_ipm_adjoint_parity(nys):
     inst = make_instance("gauss_2000x8000", seed=3, m=150, n=400)
     A32 = inst.A

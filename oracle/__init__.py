@@ -11,6 +11,7 @@ Modules
 problem    definitions of (P)/(D): objectives, KKT residuals, stopping measure
 normal_eq  the regularised normal-equation operator and the Newton step
 nystrom    randomized Nystrom approximation and the Nystrom preconditioner
+pchol      partial Cholesky preconditioner (the Chol-IP-PMM comparator)
 pcg        textbook preconditioned conjugate gradients
 ippmm      the IP-PMM outer loop with an exact (dense Cholesky) inner solve
 bruteforce active-set enumeration of the KKT conditions of tiny problems

@@ -337,3 +337,58 @@ def test_philox_gaussian_distribution():
     G2 = philox.gaussian_matrix(400, 50, seed=123, counter=8)
     assert abs(np.corrcoef(G.ravel(), G2.ravel())[0, 1]) < 0.02
     np.testing.assert_array_equal(G, philox.gaussian_matrix(400, 50, seed=123, counter=7))
+
+
+# ------------------------------------------------------------------ partial Cholesky (comparator)
+
+def _pchol_case(m=40, n=90, seed=0):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) * rng.uniform(0.2, 3.0, m)[:, None]   # uneven row scales
+    d = rng.uniform(0.05, 4.0, n)
+    return A, d, 1e-3
+
+
+def test_pchol_inverse_formula_matches_dense_preconditioner():
+    """eq. chol-precond-inv applied factor by factor equals a library solve
+    with P_Chol assembled from eq. chol-precond."""
+    from oracle import pchol
+    A, d, delta = _pchol_case()
+    P = pchol.build(A, d, delta, 12)
+    Pd = pchol.precond_dense(P)
+    r = np.random.default_rng(1).standard_normal(A.shape[0])
+    np.testing.assert_allclose(pchol.precond_inv_apply(P, r), np.linalg.solve(Pd, r), rtol=1e-10, atol=1e-12)
+
+
+def test_pchol_reproduces_pivot_block_and_diagonal():
+    """P_Chol agrees with N + delta I exactly on the pivot rows and columns
+    (L11, L21 are its exact Cholesky columns) and on the whole diagonal (diag S
+    is exact); the pivots carry the ell largest diagonal entries."""
+    from oracle import pchol
+    A, d, delta = _pchol_case(seed=2)
+    ell = 9
+    P = pchol.build(A, d, delta, ell)
+    Pd, Nd = pchol.precond_dense(P), P["Ndelta"]
+    piv = P["piv"]
+    np.testing.assert_allclose(Pd[:, piv], Nd[:, piv], rtol=1e-12, atol=1e-12 * np.abs(Nd).max())
+    np.testing.assert_allclose(np.diag(Pd), np.diag(Nd), rtol=1e-12)
+    np.testing.assert_allclose(pchol.normal_diag(A, d, delta), np.diag(Nd), rtol=1e-13)
+    rest = P["rest"]
+    assert np.diag(Nd)[piv].min() >= np.diag(Nd)[rest].max()
+    assert len(piv) == ell and np.all(np.diff(piv) > 0)
+
+
+def test_pchol_full_rank_is_exact():
+    """ell = m: no Schur complement is left, P_Chol = N + delta I and the
+    inverse formula is the exact inverse."""
+    from oracle import pchol
+    A, d, delta = _pchol_case(m=15, n=40, seed=3)
+    P = pchol.build(A, d, delta, 15)
+    np.testing.assert_allclose(pchol.precond_dense(P), P["Ndelta"], rtol=1e-12, atol=1e-12)
+    r = np.random.default_rng(4).standard_normal(15)
+    np.testing.assert_allclose(pchol.precond_inv_apply(P, r), np.linalg.solve(P["Ndelta"], r), rtol=1e-9)
+
+
+def test_pchol_pivot_ties_go_to_smaller_index():
+    from oracle import pchol
+    piv = pchol.pivots(np.array([1.0, 3.0, 2.0, 3.0, 3.0, 0.5]), 2)
+    np.testing.assert_array_equal(piv, [1, 3])

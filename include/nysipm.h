@@ -52,6 +52,11 @@ enum {
 
 typedef enum { NYS_F64 = 0, NYS_F32 = 1, NYS_BF16 = 2 } nys_dtype;
 
+/* Preconditioner of the inner solves of ipm_solve: the randomized Nystrom
+   preconditioner (Nys-IP-PMM, the method), or the paper's comparators: none
+   (CG-IP-PMM) and partial Cholesky with ell pivots (Chol-IP-PMM). */
+enum { NYS_PRECOND_NYSTROM = 0, NYS_PRECOND_NONE = 1, NYS_PRECOND_PCHOL = 2 };
+
 typedef struct nys_handle_s* nys_handle;
 
 /* A: m x n, row-major, leading dimension ld (elements), storage dtype.
@@ -206,6 +211,48 @@ int nys_pcg_solve(nys_handle h, const nys_matrix* A, const double* d, double del
                   const nys_precond* P, const double* rhs, double* y,
                   const nys_pcg_opts* opts, nys_pcg_info* info);
 
+/* ------------------------------------------------ comparator: partial Cholesky */
+
+/* Partial Cholesky preconditioner of N + delta I, N = A diag(d) A^T (section
+   "Partial Cholesky preconditioners", eq. partialCholeskyfact and
+   eq. chol-precond; the preconditioner of the paper's Chol-IP-PMM
+   comparator).  The pivots are the ell largest diagonal entries of
+   N + delta I (ties: smaller index); with E moving them first,
+   E (N + delta I) E^T = [L11 0; L21 I] [I 0; 0 S] [L11^T L21^T; 0 I] and S is
+   replaced by diag(S).  Caller-owned device buffers, sizes from m and ell
+   (1 <= ell <= m):
+     piv   ell int32: pivot rows, ascending
+     pos   m int32: pos[i] = k when i = piv[k], else -1
+     L     m x ell FP64 row-major: [L11; L21] in the original row order (row
+           piv[k] holds row k of L11, every other row its row of L21)
+     Cinv  ell x ell FP64 row-major, upper triangular: L11^{-T}
+     diagS m FP64: diag(S) on the rows that are not pivots, 1 on pivots */
+typedef struct {
+  int64_t m;
+  int32_t ell;
+  int32_t* piv;
+  int32_t* pos;
+  double* L;
+  double* Cinv;
+  double* diagS;
+} nys_pchol;
+
+/* Builds P for N + delta I (delta > 0; d >= 0, n FP64).  The diagonal is
+   sum_j A_ij^2 d_j + delta (entrywise access to A, as in the paper's
+   experiments).  NYS_ENOTPD if the pivot block's Cholesky fails.
+   Synchronises. */
+int nys_pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta, nys_pchol* P);
+
+/* out = P_Chol^{-1} r by eq. chol-precond-inv; r, out: m FP64, no aliasing.
+   Enqueue only. */
+int nys_pchol_apply(nys_handle h, const nys_pchol* P, const double* r, double* out);
+
+/* nys_pcg_solve with the partial Cholesky preconditioner (P built for the
+   same d and delta). */
+int nys_pcg_solve_pchol(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                        const nys_pchol* P, const double* rhs, double* y,
+                        const nys_pcg_opts* opts, nys_pcg_info* info);
+
 /* One Newton direction of IP-PMM for non-negative variables (Algorithm 5 with
    F = J = empty; eq. normal-eq, delta_x, delta_z):
    D = (Q + Z X^{-1} + rho I)^{-1}; xi_au = -X^{-1} r_xz;
@@ -239,6 +286,7 @@ typedef struct {
   nys_pcg_opts pcg;
   int32_t verbose;          /* 1: one line per iteration on stderr              */
   int32_t no_transposed_copy; /* 1: never copy A^T into the workspace         */
+  int32_t precond;          /* NYS_PRECOND_*: the inner solver's preconditioner */
 } nys_ipm_opts;
 
 typedef struct {

@@ -201,10 +201,12 @@ PcgCfg pcg_cfg(const nys_pcg_opts* o, int64_t m) {
 }
 
 // ---------------------------------------------------------------- PCG driver
+// Nystrom data (U, lam, ell) or a partial Cholesky preconditioner (pc); none: plain CG.
 struct Precond {
   const double* U = nullptr;
   const double* lam = nullptr;
   int ell = 0;
+  const nys_pchol* pc = nullptr;
 };
 
 // Solves (A diag(d) A^T + delta I) y = rhs.  y_zero: y is taken as 0 (and set).
@@ -212,6 +214,7 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
             const double* rhs, double* y, bool y_zero, const PcgCfg& cfg, nys_pcg_info* info) {
   const int64_t m = A->m;
   const bool pre = P.U != nullptr;
+  const bool pch = P.pc != nullptr;
   double* base;
   NYS_CHECK(ws(h, WS_PCG, (size_t)6 * m + P.ell + 8, &base));
   double* r = base;
@@ -242,6 +245,7 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
       NYS_CHECK(precond_reduce(h, P.U, P.lam, m, P.ell, delta, r, t));
       return precond_expand(h, P.U, m, P.ell, r, t, s, sc + SC_RS);
     }
+    if (pch) return pchol_apply(h, P.pc, r, s, true, nullptr);
     return dot(h, r, r, m, sc + SC_RS);
   };
 
@@ -274,7 +278,7 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
   // refresh_s leaves beta = (r^T s) / (the previous solve's r^T s); the first
   // direction is p = s, and beta * 0 would be NaN if that old value were 0
   NYS_CHECK(set_scalars(h, 1, SC_BETA, 0.0));
-  const double* sdir = pre ? s : r;
+  const double* sdir = (pre || pch) ? s : r;
 
   int status = NYS_MAXIT;
   bool final_res_known = false;
@@ -304,8 +308,9 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
     g2.out = q;
     g2.dot_out = sc + SC_PQ;
     NYS_CHECK(gemv_n(h, g2));
-    NYS_CHECK(pcg_update(h, m, y, r, pnew, q, P.U, P.lam, P.ell, delta, t));
+    NYS_CHECK(pcg_update(h, m, y, r, pnew, q, P.U, P.lam, P.ell, delta, t, pch));
     if (pre) NYS_CHECK(pcg_expand(h, m, P.U, P.ell, r, t, s));
+    if (pch) NYS_CHECK(pchol_apply(h, P.pc, r, s, true, nullptr));
     ++it;
     const bool poll = (it % cfg.poll_every == 0) || it == cfg.maxit;
     if (poll) {
@@ -735,6 +740,46 @@ extern "C" int nys_pcg_solve(nys_handle h, const nys_matrix* A, const double* d,
   return pcg_run(h, A, d, delta, pc, rhs, y, false, pcg_cfg(opts, A->m), info);
 }
 
+int check_pchol(nys_handle h, const nys_pchol* P, int64_t m, const char* who) {
+  if (!P || P->m != m || P->ell < 1 || P->ell > m || !P->piv || !P->pos || !P->L || !P->Cinv || !P->diagS)
+    return set_error(h, NYS_EINVAL, "%s: bad partial Cholesky preconditioner", who);
+  return NYS_OK;
+}
+
+extern "C" int nys_pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta, nys_pchol* P) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_pchol_build"));
+  if (A->m < 1) return set_error(h, NYS_EINVAL, "nys_pchol_build: m must be >= 1");
+  NYS_CHECK(check_pchol(h, P, A->m, "nys_pchol_build"));
+  if (!(delta > 0) || !is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_pchol_build: delta must be finite and > 0");
+  if (A->n > 0 && !d) return set_error(h, NYS_EINVAL, "nys_pchol_build: NULL d");
+  NYS_HIP(h, hipSetDevice(h->device));
+  return pchol_build(h, A, d, delta, P);
+}
+
+extern "C" int nys_pchol_apply(nys_handle h, const nys_pchol* P, const double* r, double* out) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_pchol(h, P, P ? P->m : 0, "nys_pchol_apply"));
+  if (!r || !out || r == out) return set_error(h, NYS_EINVAL, "nys_pchol_apply: bad vectors");
+  NYS_HIP(h, hipSetDevice(h->device));
+  return pchol_apply(h, P, r, out, false, nullptr);
+}
+
+extern "C" int nys_pcg_solve_pchol(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                                   const nys_pchol* P, const double* rhs, double* y,
+                                   const nys_pcg_opts* opts, nys_pcg_info* info) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_pcg_solve_pchol"));
+  if (A->m < 1) return set_error(h, NYS_EINVAL, "nys_pcg_solve_pchol: m must be >= 1");
+  NYS_CHECK(check_pchol(h, P, A->m, "nys_pcg_solve_pchol"));
+  if (!(delta > 0) || !is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_pcg_solve_pchol: delta must be finite and > 0");
+  if (!rhs || !y || (A->n > 0 && !d)) return set_error(h, NYS_EINVAL, "nys_pcg_solve_pchol: NULL vector");
+  NYS_HIP(h, hipSetDevice(h->device));
+  Precond pc;
+  pc.pc = P;
+  return pcg_run(h, A, d, delta, pc, rhs, y, false, pcg_cfg(opts, A->m), info);
+}
+
 extern "C" int nys_newton_solve(nys_handle h, const nys_matrix* A, const double* q, const double* x,
                                 const double* z, double rho, double delta, const nys_precond* P,
                                 const double* r_d, const double* r_p, const double* r_xz,
@@ -763,9 +808,9 @@ extern "C" int nys_newton_solve(nys_handle h, const nys_matrix* A, const double*
 // through these internal entry points.
 namespace nys {
 int ipm_pcg(nys_handle h, const nys_matrix* A, const double* d, double delta, const double* U,
-            const double* lam, int ell, const double* rhs, double* y, const nys_pcg_opts* o,
-            nys_pcg_info* info) {
-  Precond pc{U, lam, U ? ell : 0};
+            const double* lam, int ell, const nys_pchol* pch, const double* rhs, double* y,
+            const nys_pcg_opts* o, nys_pcg_info* info) {
+  Precond pc{U, lam, U ? ell : 0, pch};
   return pcg_run(h, A, d, delta, pc, rhs, y, true, pcg_cfg(o, A->m), info);
 }
 int ipm_sketch(nys_handle h, const nys_matrix* A, const double* d, int ell, uint64_t seed,
@@ -776,10 +821,10 @@ int ipm_sketch(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
   return NYS_OK;
 }
 int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
-               double delta, const double* U, const double* lam, int ell, const double* rd,
-               const double* rp, const double* rxz, const nys_pcg_opts* o, double mu_abs, double* dx,
-               double* dy, double* dz, nys_pcg_info* info) {
-  Precond pc{U, lam, U ? ell : 0};
+               double delta, const double* U, const double* lam, int ell, const nys_pchol* pch,
+               const double* rd, const double* rp, const double* rxz, const nys_pcg_opts* o,
+               double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info) {
+  Precond pc{U, lam, U ? ell : 0, pch};
   PcgCfg cfg = pcg_cfg(o, A->m);
   cfg.rtol = (o && o->rtol > 0) ? o->rtol : 1e-2;
   cfg.atol = 0.0;

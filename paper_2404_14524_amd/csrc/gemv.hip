@@ -177,9 +177,11 @@ struct T2Args {
   double* out;
   double* dot_out;
   double* dpart;
+  double shift;         // added to every output
 };
 
-template <class T, int RB, bool VECLOAD>
+// SQ: the entries of A are squared (sum_j A_ij^2 w_j: the diagonal of A diag(w) A^T).
+template <class T, int RB, bool VECLOAD, bool SQ>
 __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
   using raw = typename T::raw;
   constexpr int VEC = T::vec;
@@ -209,7 +211,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
           double e[VEC];
           Unpack<T>::run(u[r], e);
 #pragma unroll
-          for (int k = 0; k < VEC; ++k) acc[r] = fma(e[k], wv[k], acc[r]);
+          for (int k = 0; k < VEC; ++k) acc[r] = fma(SQ ? e[k] * e[k] : e[k], wv[k], acc[r]);
         }
       }
     }
@@ -219,7 +221,10 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
     const double wj = a.w[j];
 #pragma unroll
     for (int r = 0; r < RB; ++r)
-      if (r < nr) acc[r] = fma(to_f64(((const raw*)(a.A + (i0 + r) * a.row_bytes))[j]), wj, acc[r]);
+      if (r < nr) {
+        const double e = to_f64(((const raw*)(a.A + (i0 + r) * a.row_bytes))[j]);
+        acc[r] = fma(SQ ? e * e : e, wj, acc[r]);
+      }
   }
   block_sum<RB>(acc, smem);
   double dotc = 0.0;
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
       if (r < nr) {
         const int64_t i = i0 + r;
         const double vi = a.v ? a.v[i] : 0.0;
-        const double o = a.sA * acc[r] + a.sV * vi + (a.x0 ? a.x0[i] : 0.0);
+        const double o = a.sA * acc[r] + a.sV * vi + (a.x0 ? a.x0[i] : 0.0) + a.shift;
         a.out[i] = o;
         dotc += o * vi;
       }
@@ -361,20 +366,26 @@ void dispatch_t(dim3 g, T1Args& k, bool fused, bool vecload, hipStream_t st) {
   }
 }
 
-template <class T, int RB>
+template <class T, int RB, bool SQ>
 void launch_n_rb(T2Args& k, bool vecload, hipStream_t st) {
   dim3 g((unsigned)((k.m + RB - 1) / RB));
-  if (vecload) hipLaunchKernelGGL((k_gemv_n<T, RB, true>), g, dim3(NYS_BLOCK), 0, st, k);
-  else hipLaunchKernelGGL((k_gemv_n<T, RB, false>), g, dim3(NYS_BLOCK), 0, st, k);
+  if (vecload) hipLaunchKernelGGL((k_gemv_n<T, RB, true, SQ>), g, dim3(NYS_BLOCK), 0, st, k);
+  else hipLaunchKernelGGL((k_gemv_n<T, RB, false, SQ>), g, dim3(NYS_BLOCK), 0, st, k);
+}
+
+template <class T, bool SQ>
+void dispatch_n_sq(T2Args& k, bool vecload, hipStream_t st) {
+  const int64_t m = k.m;
+  if (m >= 8 * 1536) launch_n_rb<T, NYS_N_RB, SQ>(k, vecload, st);
+  else if (m >= 4 * 1024) launch_n_rb<T, 4, SQ>(k, vecload, st);
+  else if (m >= 2 * 1024) launch_n_rb<T, 2, SQ>(k, vecload, st);
+  else launch_n_rb<T, 1, SQ>(k, vecload, st);
 }
 
 template <class T>
-void dispatch_n(T2Args& k, bool vecload, hipStream_t st) {
-  const int64_t m = k.m;
-  if (m >= 8 * 1536) launch_n_rb<T, NYS_N_RB>(k, vecload, st);
-  else if (m >= 4 * 1024) launch_n_rb<T, 4>(k, vecload, st);
-  else if (m >= 2 * 1024) launch_n_rb<T, 2>(k, vecload, st);
-  else launch_n_rb<T, 1>(k, vecload, st);
+void dispatch_n(T2Args& k, bool vecload, bool sq, hipStream_t st) {
+  if (sq) dispatch_n_sq<T, true>(k, vecload, st);
+  else dispatch_n_sq<T, false>(k, vecload, st);
 }
 
 template <class T, int RB>
@@ -511,17 +522,18 @@ int gemv_n(nys_handle h, const GemvN& a) {
   k.sV = a.sV;
   k.out = a.out;
   k.dot_out = a.dot_out;
+  k.shift = a.shift;
   const int nbp = n_blocks_pass2(A->m);
   if (a.dot_out) NYS_CHECK(ws(h, WS_PART2, (size_t)nbp, &k.dpart));
   const bool vl = vec_ok(A) && ((uintptr_t)a.w % 16 == 0);
-  const int ps = prof_begin(h, NYS_K_NORMAL_PASS2);
+  const int ps = a.square ? -1 : prof_begin(h, NYS_K_NORMAL_PASS2);
   switch (A->dtype) {
-    case NYS_F64: dispatch_n<F64>(k, vl, h->stream); break;
-    case NYS_F32: dispatch_n<F32>(k, vl, h->stream); break;
-    case NYS_BF16: dispatch_n<BF16>(k, vl, h->stream); break;
+    case NYS_F64: dispatch_n<F64>(k, vl, a.square, h->stream); break;
+    case NYS_F32: dispatch_n<F32>(k, vl, a.square, h->stream); break;
+    case NYS_BF16: dispatch_n<BF16>(k, vl, a.square, h->stream); break;
     default: return set_error(h, NYS_EINVAL, "gemv_n: bad dtype");
   }
-  prof_end(h, ps);
+  if (ps >= 0) prof_end(h, ps);
   NYS_LAUNCH_CHECK(h);
   if (a.dot_out) {
     hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(NYS_BLOCK), 0, h->stream, a.skip,

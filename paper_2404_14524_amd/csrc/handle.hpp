@@ -32,6 +32,8 @@ enum nys_slot {
   WS_PCL,         // preconditioner lambda (ipm_solve / ipm_adjoint internal)
   WS_AT,          // transposed copy of A made by ipm_solve / ipm_adjoint
   WS_ALOT,        // transposed copy of the BF16 matrix of the sketch
+  WS_PCH,         // partial Cholesky: apply vectors (t1, sums)
+  WS_PCHB,        // partial Cholesky built by ipm_solve (pivots, L, Cinv, diag S)
   WS_NSLOTS
 };
 

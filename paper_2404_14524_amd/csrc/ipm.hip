@@ -28,14 +28,14 @@
 
 namespace nys {
 int ipm_pcg(nys_handle h, const nys_matrix* A, const double* d, double delta, const double* U,
-            const double* lam, int ell, const double* rhs, double* y, const nys_pcg_opts* o,
-            nys_pcg_info* info);
+            const double* lam, int ell, const nys_pchol* pch, const double* rhs, double* y,
+            const nys_pcg_opts* o, nys_pcg_info* info);
 int ipm_sketch(nys_handle h, const nys_matrix* A, const double* d, int ell, uint64_t seed,
                uint64_t counter, nys_dtype mode, double c_nu, double* U, double* lam, double* nu);
 int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
-               double delta, const double* U, const double* lam, int ell, const double* rd,
-               const double* rp, const double* rxz, const nys_pcg_opts* o, double mu_abs, double* dx,
-               double* dy, double* dz, nys_pcg_info* info);
+               double delta, const double* U, const double* lam, int ell, const nys_pchol* pch,
+               const double* rd, const double* rp, const double* rxz, const nys_pcg_opts* o,
+               double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info);
 int grad_A_rank2(nys_handle h, int64_t m, int64_t n, const double* y, const double* u1,
                  const double* u2, const double* x, double* G);
 
@@ -237,7 +237,23 @@ struct Opts {
   nys_pcg_opts pcg{};
   int verbose = 0;
   bool transpose = true;
+  int precond = NYS_PRECOND_NYSTROM;
 };
+
+// Workspace-backed partial Cholesky preconditioner for the comparator runs.
+int pchol_storage(nys_handle h, int64_t m, int ell, nys_pchol* P) {
+  const size_t nd = (size_t)m * ell + (size_t)ell * ell + m + ((size_t)ell + m + 1) / 2 + 4;
+  double* base;
+  NYS_CHECK(ws(h, WS_PCHB, nd, &base));
+  P->m = m;
+  P->ell = ell;
+  P->L = base;
+  P->Cinv = base + (size_t)m * ell;
+  P->diagS = P->Cinv + (size_t)ell * ell;
+  P->piv = reinterpret_cast<int32_t*>(P->diagS + m);
+  P->pos = P->piv + ell;
+  return NYS_OK;
+}
 
 Opts read_opts(const nys_ipm_opts* o) {
   Opts r;
@@ -251,6 +267,7 @@ Opts read_opts(const nys_ipm_opts* o) {
   r.pcg = o->pcg;
   r.verbose = o->verbose;
   r.transpose = o->no_transposed_copy == 0;
+  r.precond = o->precond;
   return r;
 }
 
@@ -270,6 +287,8 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
   const int64_t m = A->m, n = A->n;
   if (o.ell < 1 || o.ell > m) return set_error(h, NYS_EINVAL, "ipm_solve: ell must be in [1, m]");
   if (o.sk != NYS_F64 && o.sk != NYS_BF16) return set_error(h, NYS_EINVAL, "ipm_solve: bad sketch dtype");
+  if (o.precond < NYS_PRECOND_NYSTROM || o.precond > NYS_PRECOND_PCHOL)
+    return set_error(h, NYS_EINVAL, "ipm_solve: bad preconditioner kind %d", o.precond);
   if (o.sk == NYS_F64 && A->dtype != NYS_F64 && A->dtype != NYS_F32) return set_error(h, NYS_EINVAL, "ipm_solve: bad A");
   NYS_HIP(h, hipSetDevice(h->device));
   const auto t_start = clk::now();
@@ -320,17 +339,26 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
   nys_matrix Alo{};
   const nys_matrix* Ask = A;
   nys_matrix Alot{};
-  if (o.sk == NYS_BF16) {
+  if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM) {
     NYS_CHECK(lo_matrix(h, qp, &Alo));
     NYS_CHECK(with_transpose(h, &Alo, o.transpose, WS_ALOT, &Alot));
     Ask = &Alot;
   }
+  nys_pchol pch{};
+  if (o.precond == NYS_PRECOND_PCHOL) NYS_CHECK(pchol_storage(h, m, o.ell, &pch));
+  const double* Un = o.precond == NYS_PRECOND_NYSTROM ? U : nullptr;
+  const nys_pchol* pchp = o.precond == NYS_PRECOND_PCHOL ? &pch : nullptr;
   int pcg_total = 0;
 
-  auto timed_sketch = [&](const double* d, uint64_t ctr) -> int {
+  // preconditioner construction for the current D and delta (Nystrom sketch,
+  // partial Cholesky, or nothing for plain CG)
+  auto timed_sketch = [&](const double* d, uint64_t ctr, double dlt) -> int {
     const auto t0 = clk::now();
     double nu = 0;
-    NYS_CHECK(ipm_sketch(h, Ask, d, o.ell, o.seed, ctr, o.sk, o.c_nu, U, lamh, &nu));
+    if (o.precond == NYS_PRECOND_NYSTROM)
+      NYS_CHECK(ipm_sketch(h, Ask, d, o.ell, o.seed, ctr, o.sk, o.c_nu, U, lamh, &nu));
+    else if (o.precond == NYS_PRECOND_PCHOL)
+      NYS_CHECK(pchol_build(h, A, d, dlt, &pch));
     NYS_CHECK(sync(h));
     h->t_sketch += ms_since(t0);
     return NYS_OK;
@@ -345,13 +373,13 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
   // ---- initial point
   {
     NYS_CHECK(fill(h, ones, n, 1.0));
-    NYS_CHECK(timed_sketch(ones, CTR_INIT));
+    NYS_CHECK(timed_sketch(ones, CTR_INIT, INIT_REG));
     nys_pcg_opts ip = o.pcg;
     ip.rtol = 1e-10;
     ip.atol = 0.0;
     nys_pcg_info pi{};
     auto t0 = clk::now();
-    int rc = ipm_pcg(h, A, ones, INIT_REG, U, lamh, o.ell, qp->b, tm, &ip, &pi);
+    int rc = ipm_pcg(h, A, ones, INIT_REG, Un, lamh, o.ell, pchp, qp->b, tm, &ip, &pi);
     h->t_pcg += ms_since(t0);
     if (rc < 0) return rc;
     pcg_total += pi.iters;
@@ -367,7 +395,7 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     g2.out = rhs;
     NYS_CHECK(gemv_n(h, g2));                                          // A (c + Q x~)
     t0 = clk::now();
-    rc = ipm_pcg(h, A, ones, INIT_REG, U, lamh, o.ell, rhs, y, &ip, &pi);
+    rc = ipm_pcg(h, A, ones, INIT_REG, Un, lamh, o.ell, pchp, rhs, y, &ip, &pi);
     h->t_pcg += ms_since(t0);
     if (rc < 0) return rc;
     pcg_total += pi.iters;
@@ -436,7 +464,7 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     if (k >= o.max_iter) break;
 
     NYS_CHECK(map_reduce<0, 0>(h, n, Scaling{D, qp->q, x, z, rho}, nullptr));
-    NYS_CHECK(timed_sketch(D, (uint64_t)k));
+    NYS_CHECK(timed_sketch(D, (uint64_t)k, delta));
 
     // predictor
     NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho}, nullptr));
@@ -448,7 +476,7 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     const double tau = std::max(0.1 * mu, 0.1 * o.tol * (1.0 + bnorm));
     nys_pcg_info pi{};
     auto t0 = clk::now();
-    int rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp, &pi);
+    int rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, o.ell, pchp, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp, &pi);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;
@@ -470,7 +498,7 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     // corrector
     NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut}, nullptr));
     t0 = clk::now();
-    rc = ipm_newton(h, A, x, z, D, delta, U, lamh, o.ell, nullptr, nullptr, Rxz, &o.pcg, tau, dxc, dyc,
+    rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, o.ell, pchp, nullptr, nullptr, Rxz, &o.pcg, tau, dxc, dyc,
                     dzc, &pi);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
@@ -547,11 +575,15 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   nys_matrix Alo{};
   const nys_matrix* Ask = A;
   nys_matrix Alot{};
-  if (o.sk == NYS_BF16) {
+  if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM) {
     NYS_CHECK(lo_matrix(h, qp, &Alo));
     NYS_CHECK(with_transpose(h, &Alo, o.transpose, WS_ALOT, &Alot));
     Ask = &Alot;
   }
+  nys_pchol pch{};
+  if (o.precond == NYS_PRECOND_PCHOL) NYS_CHECK(pchol_storage(h, m, o.ell, &pch));
+  const double* Un = o.precond == NYS_PRECOND_NYSTROM ? U : nullptr;
+  const nys_pchol* pchp = o.precond == NYS_PRECOND_PCHOL ? &pch : nullptr;
   NYS_CHECK(map_reduce<0, 0>(h, n, AdjD{D, tn, qp->q, x, z, g, rho}, nullptr));
   GemvN g2;
   g2.A = A;
@@ -560,14 +592,19 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   NYS_CHECK(gemv_n(h, g2));                                            // A D g
   auto t0 = clk::now();
   double nu = 0;
-  NYS_CHECK(ipm_sketch(h, Ask, D, o.ell, o.seed, CTR_ADJ, o.sk, o.c_nu, U, lamh, &nu));
+  if (o.precond < NYS_PRECOND_NYSTROM || o.precond > NYS_PRECOND_PCHOL)
+    return set_error(h, NYS_EINVAL, "ipm_adjoint: bad preconditioner kind %d", o.precond);
+  if (o.precond == NYS_PRECOND_NYSTROM)
+    NYS_CHECK(ipm_sketch(h, Ask, D, o.ell, o.seed, CTR_ADJ, o.sk, o.c_nu, U, lamh, &nu));
+  else if (o.precond == NYS_PRECOND_PCHOL)
+    NYS_CHECK(pchol_build(h, A, D, delta, &pch));
   NYS_CHECK(sync(h));
   h->t_sketch += ms_since(t0);
   nys_pcg_opts po = o.pcg;
   if (!(po.rtol > 0)) po.rtol = 1e-10;
   if (po.maxit <= 0) po.maxit = (int)std::max<int64_t>(m, 20000);
   t0 = clk::now();
-  int rc = ipm_pcg(h, A, D, delta, U, lamh, o.ell, rhs, u2, &po, info);
+  int rc = ipm_pcg(h, A, D, delta, Un, lamh, o.ell, pchp, rhs, u2, &po, info);
   h->t_pcg += ms_since(t0);
   if (rc < 0) return rc;
   GemvT g1;

@@ -30,15 +30,17 @@ struct GemvT {
 int gemv_t(nys_handle h, const GemvT& a);
 
 // Pass 2 (reduction over the n columns of A):
-//   out[i] = sA * sum_j A[i,j] w[j] + sV * v[i] + x0[i]   (v, x0 may be NULL)
-// and, when dot_out is non-NULL, *dot_out = sum_i out[i] * v[i].
+//   out[i] = sA * sum_j A[i,j] w[j] + sV * v[i] + x0[i] + shift   (v, x0 may be NULL)
+// and, when dot_out is non-NULL, *dot_out = sum_i out[i] * v[i].  With
+// square, A[i,j] is replaced by A[i,j]^2 (the diagonal of A diag(w) A^T).
 struct GemvN {
   const nys_matrix* A;
   const double* skip = nullptr;
   const double* w = nullptr;
   const double* v = nullptr;
   const double* x0 = nullptr;
-  double sA = 1.0, sV = 0.0;
+  double sA = 1.0, sV = 0.0, shift = 0.0;
+  bool square = false;
   double* out = nullptr;
   double* dot_out = nullptr;
 };
@@ -83,11 +85,21 @@ int precond_expand(nys_handle h, const double* U, int64_t m, int ell, const doub
 
 // ---------------------------------------------------------------- PCG kernels
 // y += alpha p, r -= alpha q with alpha = rs/pq from the device words (zero
-// once done); then (with a preconditioner) the partial U^T r reduction, or
-// (without) rs_new = ||r||^2 and beta.  Sets done when ||r||^2 <= tol2.
+// once done); then (with a Nystrom preconditioner) the partial U^T r
+// reduction, or (without, unless ext: another preconditioner follows)
+// rs_new = ||r||^2 and beta.  Sets done when ||r||^2 <= tol2.
 int pcg_update(nys_handle h, int64_t m, double* y, double* r, const double* p,
                const double* q, const double* U, const double* lam, int ell, double delta,
-               double* t);
+               double* t, bool ext = false);
+
+// ---------------------------------------------------------------- partial Cholesky (comparator)
+// Builds P (caller-sized: P->m = A->m, P->ell) for N + delta I, N = A diag(d) A^T.
+// Synchronises (checks the Cholesky of the pivot block).
+int pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta, nys_pchol* P);
+// out = P^{-1} r.  pcg: the PCG form (skip once done; rs_new = r^T out, beta,
+// rs written to the device scalars); else *dot_out = r^T out when non-NULL.
+int pchol_apply(nys_handle h, const nys_pchol* P, const double* r, double* out, bool pcg,
+                double* dot_out);
 // ||r||^2 -> h->dscal[SC_RR] (no update).
 int residual_norm(nys_handle h, int64_t m, double* r);
 // With a preconditioner: s = r + U t, rs_new = r^T s, beta = rs_new/rs (zero once done).

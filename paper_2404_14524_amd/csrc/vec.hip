@@ -105,6 +105,7 @@ struct UpdArgs {
   double* t;            // PRECOND: ell-vector result
   double* scal;         // device scalar block
   double* part;         // per block: ell partial sums of U^T r, then ||r||^2
+  int ext;              // a separate preconditioner sets rs and beta (no-PRECOND form)
 };
 
 // alpha = rs/pq, zero once done; breakdown when pq <= 0 or alpha not finite.
@@ -199,7 +200,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_pcg_update_finish(UpdArgs a, int 
       } else if (!done0 && rrt <= a.scal[SC_TOL2]) {
         a.scal[SC_DONE] = 1.0;
       }
-      if constexpr (!PRECOND) {
+      if (!PRECOND && !a.ext) {
         const bool dn = a.scal[SC_DONE] != 0.0;
         const double rs = a.scal[SC_RS];
         a.scal[SC_BETA] = dn ? 0.0 : rrt / rs;
@@ -379,8 +380,9 @@ int precond_expand(nys_handle h, const double* U, int64_t m, int ell, const doub
 }
 
 int pcg_update(nys_handle h, int64_t m, double* y, double* r, const double* p, const double* q,
-               const double* U, const double* lam, int ell, double delta, double* t) {
+               const double* U, const double* lam, int ell, double delta, double* t, bool ext) {
   UpdArgs k{};
+  k.ext = ext ? 1 : 0;
   k.m = m;
   k.ell = ell;
   k.y = y;

@@ -41,6 +41,11 @@ class nys_precond(C.Structure):
     _fields_ = [("m", C.c_int64), ("ell", C.c_int32), ("U", C.c_void_p), ("lambda_", C.c_void_p)]
 
 
+class nys_pchol(C.Structure):
+    _fields_ = [("m", C.c_int64), ("ell", C.c_int32), ("piv", C.c_void_p), ("pos", C.c_void_p),
+                ("L", C.c_void_p), ("Cinv", C.c_void_p), ("diagS", C.c_void_p)]
+
+
 class nys_pcg_opts(C.Structure):
     _fields_ = [("rtol", C.c_double), ("atol", C.c_double), ("maxit", C.c_int32),
                 ("replace_every", C.c_int32), ("poll_every", C.c_int32)]
@@ -59,7 +64,8 @@ class nys_qp(C.Structure):
 class nys_ipm_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ell", C.c_int32),
                 ("seed", C.c_uint64), ("sketch_dtype", C.c_int), ("c_nu", C.c_double),
-                ("pcg", nys_pcg_opts), ("verbose", C.c_int32), ("no_transposed_copy", C.c_int32)]
+                ("pcg", nys_pcg_opts), ("verbose", C.c_int32), ("no_transposed_copy", C.c_int32),
+                ("precond", C.c_int32)]
 
 
 class nys_ipm_info(C.Structure):
@@ -72,7 +78,8 @@ class nys_ipm_info(C.Structure):
 EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
            "nys_profile_enable", "nys_profile_read", "nys_stream_read",
            "nys_normal_apply", "nys_transpose", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
-           "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint"]
+           "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint",
+           "nys_pchol_build", "nys_pchol_apply", "nys_pcg_solve_pchol"]
 
 _lib = None
 _lock = threading.Lock()
@@ -107,6 +114,10 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
             "nys_precond_apply": [vp, C.POINTER(nys_precond), dbl, vp, vp],
             "nys_pcg_solve": [vp, pm, vp, dbl, C.POINTER(nys_precond), vp, vp, C.POINTER(nys_pcg_opts),
                               C.POINTER(nys_pcg_info)],
+            "nys_pchol_build": [vp, pm, vp, dbl, C.POINTER(nys_pchol)],
+            "nys_pchol_apply": [vp, C.POINTER(nys_pchol), vp, vp],
+            "nys_pcg_solve_pchol": [vp, pm, vp, dbl, C.POINTER(nys_pchol), vp, vp, C.POINTER(nys_pcg_opts),
+                                    C.POINTER(nys_pcg_info)],
             "nys_newton_solve": [vp, pm, vp, vp, vp, dbl, dbl, C.POINTER(nys_precond), vp, vp, vp,
                                  C.POINTER(nys_pcg_opts), vp, vp, vp, C.POINTER(nys_pcg_info)],
             "ipm_solve": [vp, C.POINTER(nys_qp), C.POINTER(nys_ipm_opts), vp, vp, vp,
@@ -180,6 +191,44 @@ class Precond:
 
     def c(self) -> nys_precond:
         return nys_precond(self.U.shape[0], self.U.shape[1], self.U.data_ptr(), self.lam.data_ptr())
+
+
+@dataclass
+class PChol:
+    """Partial Cholesky preconditioner (the Chol-IP-PMM comparator); see nys_pchol."""
+    piv: torch.Tensor      # ell int32, ascending pivot rows
+    pos: torch.Tensor      # m int32, position in piv or -1
+    L: torch.Tensor        # m x ell float64: [L11; L21] in the original row order
+    Cinv: torch.Tensor     # ell x ell float64, upper: L11^{-T}
+    diagS: torch.Tensor    # m float64
+
+    def c(self) -> nys_pchol:
+        return nys_pchol(self.L.shape[0], self.L.shape[1], self.piv.data_ptr(), self.pos.data_ptr(),
+                         self.L.data_ptr(), self.Cinv.data_ptr(), self.diagS.data_ptr())
+
+
+def nys_pchol_build(A: torch.Tensor, d: torch.Tensor, delta: float, ell: int) -> PChol:
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    _vec(d, n, "d", A.device)
+    dev = A.device
+    P = PChol(torch.empty(ell, dtype=torch.int32, device=dev), torch.empty(m, dtype=torch.int32, device=dev),
+              torch.empty((m, ell), dtype=torch.float64, device=dev),
+              torch.empty((ell, ell), dtype=torch.float64, device=dev), torch.empty(m, dtype=torch.float64, device=dev))
+    Pc = P.c()
+    Am = _mat(A)
+    _check(lib, h, lib.nys_pchol_build(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc)))
+    return P
+
+
+def nys_pchol_apply(P: PChol, r: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    lib, h = _handle(r.device)
+    m = P.L.shape[0]
+    _vec(r, m, "r", r.device)
+    out = torch.empty_like(r) if out is None else _vec(out, m, "out", r.device)
+    Pc = P.c()
+    _check(lib, h, lib.nys_pchol_apply(h, C.byref(Pc), _ptr(r), _ptr(out)))
+    return out
 
 
 def _pcg_opts(rtol=1e-10, atol=0.0, maxit=0, replace_every=0, poll_every=0) -> nys_pcg_opts:
@@ -275,8 +324,12 @@ def nys_pcg_solve(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Ten
     o = _pcg_opts(**opts)
     info = nys_pcg_info()
     Pc = P.c() if P is not None else None
-    rc = lib.nys_pcg_solve(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc) if Pc else None,
-                           _ptr(rhs), _ptr(y), C.byref(o), C.byref(info))
+    if isinstance(P, PChol):
+        rc = lib.nys_pcg_solve_pchol(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc), _ptr(rhs), _ptr(y),
+                                     C.byref(o), C.byref(info))
+    else:
+        rc = lib.nys_pcg_solve(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc) if Pc else None,
+                               _ptr(rhs), _ptr(y), C.byref(o), C.byref(info))
     _check(lib, h, rc)
     return y, info
 
@@ -303,12 +356,15 @@ def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond
     return dx, dy, dz, info
 
 
+PRECONDS = {"nystrom": 0, "none": 1, "pchol": 2}
+
+
 def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0, verbose=False,
               pcg_rtol=0.0, pcg_maxit=0, replace_every=0, poll_every=0,
-              transposed_copy=True) -> nys_ipm_opts:
+              transposed_copy=True, precond="nystrom") -> nys_ipm_opts:
     return nys_ipm_opts(tol, max_iter, ell, seed, _SK[sketch_dtype], c_nu,
                         _pcg_opts(pcg_rtol, 0.0, pcg_maxit, replace_every, poll_every), int(verbose),
-                        0 if transposed_copy else 1)
+                        0 if transposed_copy else 1, PRECONDS[precond])
 
 
 def _qp(A, b, c, q, A_lo, A_t=None):

@@ -408,3 +408,74 @@ def test_ipm_adjoint_parity(nys):
         e = ref[k]
         gk = _np(grads[k])
         assert np.linalg.norm(gk - e) <= 1e-4 * np.linalg.norm(e), k
+
+
+# ------------------------------------------------------------------ comparators (partial Cholesky, plain CG)
+
+def _pchol_case(m, n, seed):
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) * rng.uniform(0.2, 3.0, m)[:, None] / np.sqrt(n)
+    d = rng.uniform(0.05, 4.0, n)
+    return A, d
+
+
+@pytest.mark.parametrize("m,n,ell", [(300, 900, 20), (1000, 2500, 64), (77, 200, 77)])
+def test_pchol_build_and_apply_parity(nys, m, n, ell):
+    from oracle import pchol as opc
+    print(f"pchol {m}x{n} ell={ell}", flush=True)
+    A, d = _pchol_case(m, n, seed=m + ell)
+    delta = 1e-3
+    P = nys.nys_pchol_build(_t(A), _t(d), delta, ell)
+    ref = opc.build(A, d, delta, ell)
+    np.testing.assert_array_equal(P.piv.cpu().numpy(), ref["piv"])
+    pos = P.pos.cpu().numpy()
+    assert np.all(pos[ref["piv"]] == np.arange(ell)) and np.all(pos[ref["rest"]] == -1)
+    Lo = np.empty((m, ell))
+    Lo[ref["piv"]] = ref["L11"]
+    Lo[ref["rest"]] = ref["L21"]
+    scale = np.abs(Lo).max()
+    np.testing.assert_allclose(_np(P.L), Lo, rtol=0, atol=1e-10 * scale)
+    np.testing.assert_allclose(_np(P.diagS)[ref["rest"]], ref["diagS"], rtol=1e-8)
+    r = np.random.default_rng(1).standard_normal(m)
+    out = _np(nys.nys_pchol_apply(P, _t(r)))
+    ro = opc.precond_inv_apply(ref, r)
+    np.testing.assert_allclose(out, ro, rtol=0, atol=1e-9 * np.abs(ro).max())
+
+
+def test_pchol_pivot_ties(nys):
+    """Equal diagonal entries: the smaller index is taken first."""
+    from oracle import pchol as opc
+    A, d = _pchol_case(50, 120, seed=9)
+    A[7] = A[3] = 10.0 * A[3]          # two equal, largest rows
+    for ell in (1, 2, 3):
+        P = nys.nys_pchol_build(_t(A), _t(d), 1e-3, ell)
+        ref = opc.build(A, d, 1e-3, ell)
+        np.testing.assert_array_equal(P.piv.cpu().numpy(), ref["piv"])
+        assert 3 in ref["piv"]
+
+
+@pytest.mark.parametrize("ell", [30, 120])
+def test_pcg_pchol_parity_with_dense_solve(nys, ell):
+    m, n = 120, 400
+    A, d = _pchol_case(m, n, seed=ell)
+    delta = 1e-4
+    P = nys.nys_pchol_build(_t(A), _t(d), delta, ell)
+    xi = np.random.default_rng(2).standard_normal(m)
+    y, info = nys.nys_pcg_solve(_t(A), _t(d), delta, _t(xi), P=P, rtol=1e-11, maxit=2000, poll_every=1)
+    M = normal_eq.normal_matrix(A, d, delta)
+    assert info.status == 0
+    if ell == m:                       # P_Chol = N + delta I exactly
+        assert info.iters <= 2, info.iters
+    assert np.linalg.norm(xi - M @ _np(y)) <= 1.01e-11 * np.linalg.norm(xi) + 1e-14
+
+
+@pytest.mark.parametrize("precond", ["pchol", "none"])
+def test_ipm_solve_comparators(nys, precond):
+    """Chol-IP-PMM and CG-IP-PMM reach the same optimum as Nys-IP-PMM."""
+    inst = make_instance("gauss_200x500", seed=1)
+    A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+    x, y, z, info = nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=20, tol=1e-6, seed=0, precond=precond)
+    assert info.status == 0, info.kkt_rel
+    assert problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))["kkt"] <= 1e-6
+    xs = inst.x_star.numpy()
+    assert np.linalg.norm(_np(x) - xs) <= 1e-5 * np.linalg.norm(xs)

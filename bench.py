@@ -17,6 +17,9 @@ oracle's per-iteration work on a bounded sample of the same instance.
 
 Modes:
   python bench.py [--steps K] [--warmup W] [--workload NAME] [--no-fp64] [--no-cpu-baseline]
+  python bench.py --compare [--workload NAME]   # Nys-IP-PMM against the paper's
+                                    # comparators (Chol-IP-PMM, CG-IP-PMM) on one
+                                    # workload: one JSON line per solver
   python bench.py --kernel-loop R   # only R normal-equation applies (pass 1 on a
                                     # transposed copy, as in the solver), a plain
                                     # copy and read-stream kernels of known size
@@ -197,6 +200,31 @@ def cpu_baseline(inst, D, delta, gpu_iters, budget_cols: int):
     }
 
 
+def compare(nys, inst, args):
+    """The paper's comparison (Nys-IP-PMM against Chol-IP-PMM and CG-IP-PMM,
+    section 5): same instance, same tolerance, same sketch/pivot count ell;
+    wall time of each solve (one warm-up solve of the method first)."""
+    import torch
+    A = inst.A
+    A_lo = A.to(torch.bfloat16) if A.dtype == torch.float32 else None
+    sk = "bf16" if A_lo is not None else "f64"
+    nys.ipm_solve(A, inst.b, inst.c, inst.q, ell=inst.ell, tol=TOL, seed=args.seed, sketch_dtype=sk, A_lo=A_lo)
+    torch.cuda.synchronize()
+    for name, pre in (("Nys-IP-PMM", "nystrom"), ("Chol-IP-PMM", "pchol"), ("CG-IP-PMM", "none")):
+        t0 = time.perf_counter()
+        x, y, z, info = nys.ipm_solve(A, inst.b, inst.c, inst.q, ell=inst.ell, tol=TOL, seed=args.seed,
+                                      sketch_dtype=sk, A_lo=A_lo if pre == "nystrom" else None, precond=pre)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        xs = inst.x_star
+        rec = {"solver": name, "workload": args.workload, "seconds": round(t, 3), "status": info.status,
+               "ipm_iters": info.iters, "pcg_iters": info.pcg_iters_total, "kkt_rel": info.kkt_rel,
+               "x_rel_err_vs_planted": float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)),
+               "time_split_ms": {"precond": round(info.t_sketch_ms, 1), "pcg": round(info.t_pcg_ms, 1),
+                                 "other": round(info.t_other_ms, 1)}}
+        print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -207,6 +235,7 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-loop", type=int, default=0)
+    ap.add_argument("--compare", action="store_true")
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"))
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
@@ -244,6 +273,10 @@ def main():
         f"generated in {time.perf_counter() - t0:.1f}s")
     b_A = A.element_size()
     bytes_pass = inst.m * inst.n * b_A
+
+    if args.compare:
+        compare(nys, inst, args)
+        return
 
     if args.kernel_loop:
         d = torch.rand(inst.n, dtype=torch.float64, device=dev)

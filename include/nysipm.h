@@ -189,7 +189,7 @@ typedef struct {
   double rtol;            /* stop when ||rhs - M y|| <= max(rtol ||rhs||, atol) */
   double atol;
   int32_t maxit;          /* <= 0: max(m, 2000)                                  */
-  int32_t replace_every;  /* FP64 true-residual replacement period; <= 0: 50     */
+  int32_t replace_every;  /* FP64 true-residual replacement period; <= 0: 100    */
   int32_t poll_every;     /* host convergence poll period; <= 0: 8               */
 } nys_pcg_opts;
 

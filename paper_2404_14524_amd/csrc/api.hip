@@ -174,7 +174,7 @@ int check_precond(nys_handle h, const nys_precond* P, int64_t m, const char* who
 
 struct PcgCfg {
   double rtol = 1e-10, atol = 0.0;
-  int maxit = 0, replace_every = 50, poll_every = 8;
+  int maxit = 0, replace_every = 100, poll_every = 8;
   // mu rule of the interior-point inner solves (mu_abs >= 0):
   // tol = max(floor_rel ||rhs||, min(rtol ||rhs||, mu_abs))
   double mu_abs = -1.0, floor_rel = 1e-12;
@@ -193,7 +193,7 @@ PcgCfg pcg_cfg(const nys_pcg_opts* o, int64_t m) {
   // late interior-point systems need thousands of iterations, and a capped,
   // unconverged direction costs more outer iterations than it saves
   if (c.maxit <= 0) c.maxit = (int)std::min<int64_t>(std::max<int64_t>(m, 2000), 1 << 30);
-  if (c.replace_every <= 0) c.replace_every = 50;
+  if (c.replace_every <= 0) c.replace_every = 100;
   if (c.poll_every <= 0) c.poll_every = 8;
   if (!(c.rtol >= 0)) c.rtol = 0;
   if (!(c.atol >= 0)) c.atol = 0;

@@ -12,6 +12,7 @@ problem    definitions of (P)/(D): objectives, KKT residuals, stopping measure
 normal_eq  the regularised normal-equation operator and the Newton step
 nystrom    randomized Nystrom approximation and the Nystrom preconditioner
 pchol      partial Cholesky preconditioner (the Chol-IP-PMM comparator)
+boxqp      IP-PMM with free, non-negative and box-constrained variables
 pcg        textbook preconditioned conjugate gradients
 ippmm      the IP-PMM outer loop with an exact (dense Cholesky) inner solve
 bruteforce active-set enumeration of the KKT conditions of tiny problems

@@ -392,3 +392,102 @@ def test_pchol_pivot_ties_go_to_smaller_index():
     from oracle import pchol
     piv = pchol.pivots(np.array([1.0, 3.0, 2.0, 3.0, 3.0, 0.5]), 2)
     np.testing.assert_array_equal(piv, [1, 3])
+
+
+# ------------------------------------------------------------------ free and box-constrained variables
+
+def _box_types(n, rng):
+    return rng.choice([0, 1, 2], size=n, p=[0.4, 0.2, 0.4])
+
+
+def test_box_newton_step_matches_unreduced_system():
+    """Algorithm 5 (xi_au by index kind, normal equations, closed-form
+    back-substitution) equals a dense solve of eq. Newton-free-box."""
+    from oracle import boxqp
+    rng = np.random.default_rng(0)
+    m, n = 7, 19
+    A = rng.standard_normal((m, n))
+    vt = _box_types(n, rng)
+    F, I, J = boxqp.kinds(vt)
+    q = rng.uniform(0.0, 1.0, n)
+    x = np.where(F, rng.standard_normal(n), rng.uniform(0.2, 2.0, n))
+    z = np.where(F, 0.0, rng.uniform(0.2, 2.0, n))
+    w = np.where(J, rng.uniform(0.2, 2.0, n), 0.0)
+    s = np.where(J, rng.uniform(0.2, 2.0, n), 0.0)
+    rho, delta = 0.3, 0.05
+    rd, rp = rng.standard_normal(n), rng.standard_normal(m)
+    ru = np.where(J, rng.standard_normal(n), 0.0)
+    rxz = np.where(F, 0.0, rng.standard_normal(n))
+    rws = np.where(J, rng.standard_normal(n), 0.0)
+    D = boxqp.scaling(vt, x, z, w, s, q, rho)
+    M = (A * D) @ A.T + delta * np.eye(m)
+    dx, dy, dz, dw, ds = boxqp.newton_step(A, vt, x, z, w, s, D, delta, rd, rp, ru, rxz, rws,
+                                           lambda xi: np.linalg.solve(M, xi))
+    K, (ox, oy, ow, oz, os_), (iJ, iIJ) = boxqp.newton_matrix(A, q, vt, x, z, w, s, rho, delta)
+    rhs = np.concatenate([rd, rp, ru[iJ], rxz[iIJ], rws[iJ]])
+    sol = np.linalg.solve(K, rhs)
+    np.testing.assert_allclose(dx, sol[ox:ox + n], rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(dy, sol[oy:oy + m], rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(dw[iJ], sol[ow:ow + len(iJ)], rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(dz[iIJ], sol[oz:oz + len(iIJ)], rtol=1e-9, atol=1e-11)
+    np.testing.assert_allclose(ds[iJ], sol[os_:os_ + len(iJ)], rtol=1e-9, atol=1e-11)
+    assert np.all(dz[F] == 0) and np.all(dw[~J] == 0) and np.all(ds[~J] == 0)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_box_solve_recovers_planted_optimum(seed):
+    from oracle import boxqp
+    rng = np.random.default_rng(10 + seed)
+    m, n = 25, 70
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    vt = _box_types(n, rng)
+    q = rng.uniform(0.5, 1.5, n)                  # strictly convex: unique optimum
+    u = np.where(vt == 2, rng.uniform(0.5, 2.0, n), 0.0)
+    b, c, xs, ys, zs, ws, ss = boxqp.planted(A, q, vt, u, rng)
+    assert boxqp.kkt_measure(A, b, c, q, u, vt, xs, ys, zs, ws, ss)["kkt"] <= 1e-13
+    assert np.all(xs[vt == 2] <= u[vt == 2]) and np.any(xs[vt == 2] == u[vt == 2])
+    res = boxqp.solve(A, b, c, q, u, vt, tol=1e-10)
+    assert res["status"] == 0
+    assert np.linalg.norm(res["x"] - xs) <= 1e-7 * np.linalg.norm(xs)
+    assert np.linalg.norm(res["y"] - ys) <= 1e-6 * np.linalg.norm(ys)
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_box_solve_matches_bruteforce(seed):
+    """Tiny non-planted instances: every free/zero/upper pattern enumerated."""
+    from oracle import boxqp
+    rng = np.random.default_rng(40 + seed)
+    m, n = 2, 7
+    A = rng.standard_normal((m, n))
+    vt = _box_types(n, rng)
+    q = rng.uniform(0.2, 1.0, n)
+    u = np.where(vt == 2, rng.uniform(0.5, 1.5, n), 0.0)
+    x0 = np.where(vt == 1, rng.standard_normal(n), np.where(vt == 2, 0.5 * u, rng.uniform(0.1, 1.0, n)))
+    b = A @ x0                                      # feasible
+    c = rng.standard_normal(n)
+    xb, yb = boxqp.bruteforce(A, b, c, q, u, vt)
+    res = boxqp.solve(A, b, c, q, u, vt, tol=1e-10)
+    assert res["status"] == 0
+    np.testing.assert_allclose(res["x"], xb, atol=1e-6 * (1 + np.abs(xb).max()))
+
+
+def test_box_all_nonneg_reduces_to_the_pinned_oracle():
+    """With every index NONNEG (u unused) the general algorithm takes the
+    same steps as the non-negative oracle."""
+    from oracle import boxqp
+    rng = np.random.default_rng(5)
+    m, n = 15, 40
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    q = rng.uniform(0.0, 1.0, n)
+    x0 = rng.uniform(0.1, 1.0, n)
+    b, c = A @ x0, rng.standard_normal(n)
+    vt = np.zeros(n, dtype=int)
+    r1 = oipm_solve(A, b, c, q)
+    r2 = boxqp.solve(A, b, c, q, np.zeros(n), vt, tol=1e-8)
+    assert r1["iters"] == r2["iters"]
+    np.testing.assert_allclose(r2["x"], r1["x"], rtol=1e-10, atol=1e-12)
+
+
+def oipm_solve(A, b, c, q):
+    from oracle import ippmm
+    return ippmm.solve(A, b, c, q, tol=1e-8)

@@ -268,12 +268,19 @@ int nys_newton_solve(nys_handle h, const nys_matrix* A, const double* q, const d
 
 /* ---------------------------------------------------------------- IP-PMM */
 
+/* Kinds of variables (section "Free and box-constrained variables"): the
+   problem (P~) has x_F free, x_I >= 0 and 0 <= x_J <= u_J. */
+enum { NYS_VAR_NONNEG = 0, NYS_VAR_FREE = 1, NYS_VAR_BOX = 2 };
+
 typedef struct {
   const nys_matrix* A;      /* problem-defining matrix (FP64 or FP32 storage)   */
   const nys_matrix* A_lo;   /* BF16 copy for the sketch, or NULL                */
   const double* b;          /* m */
   const double* c;          /* n */
   const double* q;          /* n, diag(Q) >= 0 */
+  const int8_t* vtype;      /* n NYS_VAR_* kinds, or NULL: every x_j >= 0       */
+  const double* u;          /* n upper bounds (read where vtype is BOX; > 0 and
+                               finite there), or NULL when vtype is NULL       */
 } nys_qp;
 
 typedef struct {
@@ -293,6 +300,7 @@ typedef struct {
   int32_t iters, pcg_iters_total, status;
   double kkt_rel, rp_rel, rd_rel, mu, rho, delta;
   double t_sketch_ms, t_pcg_ms, t_other_ms;
+  double ru_rel;            /* ||u_J - x_J - w_J|| / (1 + ||u_J||) (box variables) */
 } nys_ipm_info;
 
 /* Nys-IP-PMM (Algorithm 4 with the predictor-corrector of Algorithm 6 and the
@@ -303,9 +311,23 @@ typedef struct {
    rho = delta = max(5e-10, min(rho, mu)); stop when
    max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
    Outputs x, z (n) and y (m) FP64.  Returns NYS_OK, NYS_MAXIT, or an error.
-   Synchronises. */
+   With qp->vtype set this solves (P~) as ipm_solve_box does, keeping w and s
+   internal.  Synchronises. */
 int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* x, double* y,
               double* z, nys_ipm_info* info);
+
+/* The same method for (P~)/(D~) with free, non-negative and box-constrained
+   variables (qp->vtype, qp->u; section "Free and box-constrained variables"):
+   Theta^{-1}_jj = z_j/x_j (I), z_j/x_j + s_j/w_j (J), 0 (F); the Newton
+   direction of Algorithm 5 with xi_au by index kind and
+   dz = X^{-1}(r_xz - Z dx), dw_J = (r_u)_J - dx_J, ds = W^{-1}(r_ws - S dw);
+   the supplement's initial point (x~ centred at u/2) and step lengths over
+   (x_IJ, w_J) and (z_IJ, s_J); mu = (x_IJ^T z_IJ + w_J^T s_J)/(|IJ| + |J|);
+   stop when max(rp_rel, rd_rel, ||r_u||/(1+||u_J||), mu) <= tol with
+   r_d = c + Q x - A^T y - z + s.  Outputs x, z, w, s (n; z_F = 0, w and s
+   zero off J) and y (m).  w, s may be NULL.  Synchronises. */
+int ipm_solve_box(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* x, double* y,
+                  double* z, double* w, double* s, nys_ipm_info* info);
 
 /* Adjoint of the converged KKT system (not in the paper; derived from the
    optimality conditions of (P)/(D)).  With g = dL/dx at the solution (x, y, z)
@@ -321,7 +343,8 @@ int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* 
    Any output pointer may be NULL (skipped); grad_A is m x n row-major FP64
    with leading dimension n.  Returns the PCG status (NYS_MAXIT = the adjoint
    solve did not reach its tolerance; gradients from the last iterate).
-   Synchronises. */
+   Problems with free or box-constrained variables (qp->vtype set) are
+   rejected with NYS_EINVAL.  Synchronises. */
 int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, const double* x,
                 const double* y, const double* z, double rho, double delta, const double* g,
                 double* grad_c, double* grad_b, double* grad_q, double* grad_A,

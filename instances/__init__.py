@@ -7,6 +7,6 @@ a planted instance of the separable QP (P)/(D) of the paper's introduction.
 Both the HIP path and the CPU oracle receive exactly these arrays.
 """
 
-from .planted import CONFIGS, Instance, make_instance, random_feasible_instance
+from .planted import CONFIGS, Instance, make_instance, random_feasible_instance, svm_instance
 
-__all__ = ["CONFIGS", "Instance", "make_instance", "random_feasible_instance"]
+__all__ = ["CONFIGS", "Instance", "make_instance", "random_feasible_instance", "svm_instance"]

@@ -177,3 +177,32 @@ def random_feasible_instance(m: int, n: int, seed: int, q_lo: float = 0.1,
     c = torch.randn(n, generator=g, dtype=f64)
     q = q_lo + (q_hi - q_lo) * torch.rand(n, generator=g, dtype=f64)
     return dict(A=A, b=b, c=c, q=q)
+
+
+def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 1.0,
+                 device: str | torch.device = "cpu", dtype=torch.float64) -> dict:
+    """Dual linear SVM in the box-constrained form (P~) (the paper's SVM
+    formulation): x = [v; p], Q = diag(1_d, 0_n), A = [[I_d, -X diag(y)],
+    [0, y^T]], b = 0, c = [0_d; -1_n] (the objective 1/2 v^T v - sum p), v
+    free, 0 <= p <= tau.  Synthetic dense features: two classes with means
+    +-sep/sqrt(d) in every coordinate plus N(0, 1) noise, labels +-1 in equal
+    numbers (a seeded permutation).  Returns A (dtype), b, c, q, u (float64),
+    vtype (int8), labels."""
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    yl = torch.ones(n, dtype=f64, device=device)
+    yl[torch.randperm(n, generator=g, device=device)[: n // 2]] = -1.0
+    X = torch.randn((d, n), generator=g, dtype=f64, device=device) + (sep / d ** 0.5) * yl[None, :]
+    A = torch.zeros((d + 1, d + n), dtype=f64, device=device)
+    A[:d, :d] = torch.eye(d, dtype=f64, device=device)
+    A[:d, d:] = -X * yl[None, :]
+    A[d, d:] = yl
+    A = A.to(dtype)
+    b = torch.zeros(d + 1, dtype=f64, device=device)
+    c = torch.cat([torch.zeros(d, dtype=f64, device=device), -torch.ones(n, dtype=f64, device=device)])
+    q = torch.cat([torch.ones(d, dtype=f64, device=device), torch.zeros(n, dtype=f64, device=device)])
+    u = torch.cat([torch.zeros(d, dtype=f64, device=device), torch.full((n,), tau, dtype=f64, device=device)])
+    vtype = torch.cat([torch.full((d,), 1, dtype=torch.int8, device=device),
+                       torch.full((n,), 2, dtype=torch.int8, device=device)])
+    return dict(A=A, b=b, c=c, q=q, u=u, vtype=vtype, labels=yl)

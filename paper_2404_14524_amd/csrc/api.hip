@@ -453,26 +453,48 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
 
 // ---------------------------------------------------------------- Newton step (Alg. 5)
 struct NewtonPre {
-  // tn = D (r_d + xi_au), x0n = -(r_d + xi_au), xi_au = -r_xz / x
+  // tn = D (r_d + xi_au), x0n = -(r_d + xi_au), with xi_au by index kind:
+  // free 0; non-negative -r_xz/x; box -r_xz/x + r_ws/w - (s/w) r_u
   double* tn;
   double* x0n;
   const double* D;
   const double* rd;   // may be NULL (zero)
   const double* rxz;
   const double* x;
+  BoxNewton bx;
   __device__ void operator()(int64_t j, double*, double*) const {
-    const double a = (rd ? rd[j] : 0.0) - rxz[j] / x[j];
+    const int k = bx.vt ? bx.vt[j] : NYS_VAR_NONNEG;
+    double xa = 0.0;
+    if (k != NYS_VAR_FREE) xa = -rxz[j] / x[j];
+    if (k == NYS_VAR_BOX) {
+      const double ru = bx.ru ? bx.ru[j] : 0.0;
+      xa += (bx.rws[j] - bx.s[j] * ru) / bx.w[j];
+    }
+    const double a = (rd ? rd[j] : 0.0) + xa;
     tn[j] = D[j] * a;
     x0n[j] = -a;
   }
 };
-struct NewtonDz {
+struct NewtonDz {     // eq. delta-z/-w/-s-free-box (X^{-1}, W^{-1} on both terms)
   double* dz;
   const double* rxz;
   const double* z;
   const double* dx;
   const double* x;
-  __device__ void operator()(int64_t j, double*, double*) const { dz[j] = (rxz[j] - z[j] * dx[j]) / x[j]; }
+  BoxNewton bx;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    const int k = bx.vt ? bx.vt[j] : NYS_VAR_NONNEG;
+    dz[j] = k == NYS_VAR_FREE ? 0.0 : (rxz[j] - z[j] * dx[j]) / x[j];
+    if (bx.dw) {
+      double dw = 0.0, ds = 0.0;
+      if (k == NYS_VAR_BOX) {
+        dw = (bx.ru ? bx.ru[j] : 0.0) - dx[j];
+        ds = (bx.rws[j] - bx.s[j] * dw) / bx.w[j];
+      }
+      bx.dw[j] = dw;
+      bx.ds[j] = ds;
+    }
+  }
 };
 struct ScalingF {
   double* D;
@@ -485,14 +507,15 @@ struct ScalingF {
 
 int newton_run(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
                double delta, const Precond& P, const double* rd, const double* rp, const double* rxz,
-               const PcgCfg& cfg, double* dx, double* dy, double* dz, nys_pcg_info* info) {
+               const PcgCfg& cfg, double* dx, double* dy, double* dz, nys_pcg_info* info,
+               const BoxNewton& bx = BoxNewton{}) {
   const int64_t m = A->m, n = A->n;
   double* base;
   NYS_CHECK(ws(h, WS_NEWTON, (size_t)2 * n + m + 8, &base));
   double* tn = base;
   double* x0n = base + n;
   double* xi = base + 2 * n;
-  NYS_CHECK(map_reduce<0, 0>(h, n, NewtonPre{tn, x0n, D, rd, rxz, x}, nullptr));
+  NYS_CHECK(map_reduce<0, 0>(h, n, NewtonPre{tn, x0n, D, rd, rxz, x, bx}, nullptr));
   GemvN g2;
   g2.A = A;
   g2.w = tn;
@@ -512,7 +535,7 @@ int newton_run(nys_handle h, const nys_matrix* A, const double* x, const double*
   g1.d = D;
   g1.w = dx;
   NYS_CHECK(gemv_t(h, g1));
-  NYS_CHECK(map_reduce<0, 0>(h, n, NewtonDz{dz, rxz, z, dx, x}, nullptr));
+  NYS_CHECK(map_reduce<0, 0>(h, n, NewtonDz{dz, rxz, z, dx, x, bx}, nullptr));
   return rc;
 }
 
@@ -823,13 +846,14 @@ int ipm_sketch(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
 int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
                double delta, const double* U, const double* lam, int ell, const nys_pchol* pch,
                const double* rd, const double* rp, const double* rxz, const nys_pcg_opts* o,
-               double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info) {
+               double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info,
+               const BoxNewton& bx) {
   Precond pc{U, lam, U ? ell : 0, pch};
   PcgCfg cfg = pcg_cfg(o, A->m);
   cfg.rtol = (o && o->rtol > 0) ? o->rtol : 1e-2;
   cfg.atol = 0.0;
   cfg.mu_abs = mu_abs;
-  return newton_run(h, A, x, z, D, delta, pc, rd, rp, rxz, cfg, dx, dy, dz, info);
+  return newton_run(h, A, x, z, D, delta, pc, rd, rp, rxz, cfg, dx, dy, dz, info, bx);
 }
 int grad_A_rank2(nys_handle h, int64_t m, int64_t n, const double* y, const double* u1,
                  const double* u2, const double* x, double* G) {

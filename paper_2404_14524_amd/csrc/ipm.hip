@@ -35,7 +35,8 @@ int ipm_sketch(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
 int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
                double delta, const double* U, const double* lam, int ell, const nys_pchol* pch,
                const double* rd, const double* rp, const double* rxz, const nys_pcg_opts* o,
-               double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info);
+               double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info,
+               const BoxNewton& bx);
 int grad_A_rank2(nys_handle h, int64_t m, int64_t n, const double* y, const double* u1,
                  const double* u2, const double* x, double* G);
 
@@ -54,30 +55,60 @@ double ms_since(clk::time_point t0) {
 }
 
 // ---------------------------------------------------------------- element-wise steps
-struct ResidD {       // r_d = c + Q x - A^T y - z ; ||r_d||^2, x^T z, #non-finite
+// vt (index kinds) NULL: every variable non-negative and the box arrays
+// (w, s and their right-hand sides and directions) are not used.
+__device__ __forceinline__ int kind_of(const int8_t* vt, int64_t j) { return vt ? (int)vt[j] : NYS_VAR_NONNEG; }
+
+struct ResidD {       // r_d = c + Q x - A^T y - z + s; ||r_d||^2, mu numerator, #non-finite, ||r_u||^2
   double* rd;
   const double *c, *q, *x, *aty, *z;
-  __device__ void operator()(int64_t j, double* s, double*) const {
-    const double v = c[j] + q[j] * x[j] - aty[j] - z[j];
+  const int8_t* vt;
+  const double *u, *w, *s;
+  __device__ void operator()(int64_t j, double* a, double*) const {
+    const int k = kind_of(vt, j);
+    double v = c[j] + q[j] * x[j] - aty[j] - z[j];
+    if (k == NYS_VAR_BOX) v += s[j];
     rd[j] = v;
-    s[0] = fma(v, v, s[0]);
-    s[1] = fma(x[j], z[j], s[1]);
-    if (!isfinite(x[j]) || !isfinite(z[j])) s[2] += 1.0;
+    a[0] = fma(v, v, a[0]);
+    if (k != NYS_VAR_FREE) a[1] = fma(x[j], z[j], a[1]);
+    bool bad = !isfinite(x[j]) || !isfinite(z[j]);
+    if (k == NYS_VAR_BOX) {
+      a[1] = fma(w[j], s[j], a[1]);
+      const double ru = u[j] - x[j] - w[j];
+      a[3] = fma(ru, ru, a[3]);
+      bad = bad || !isfinite(w[j]) || !isfinite(s[j]);
+    }
+    if (bad) a[2] += 1.0;
   }
 };
-struct Scaling {      // D = (Q + Z X^{-1} + rho I)^{-1}
+struct Scaling {      // D = (Q + Theta^{-1} + rho I)^{-1}: z/x (I), z/x + s/w (J), 0 (F)
   double* D;
   const double *q, *x, *z;
   double rho;
-  __device__ void operator()(int64_t j, double*, double*) const { D[j] = 1.0 / (q[j] + z[j] / x[j] + rho); }
+  const int8_t* vt;
+  const double *w, *s;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    const int k = kind_of(vt, j);
+    double th = k == NYS_VAR_FREE ? 0.0 : z[j] / x[j];
+    if (k == NYS_VAR_BOX) th += s[j] / w[j];
+    D[j] = 1.0 / (q[j] + th + rho);
+  }
 };
-struct PredN {        // R_d = r_d + rho (x - zeta), R_xz = -X Z 1
+struct PredN {        // R_d = r_d + rho (x - zeta), R_xz = -X Z, R_ws = -W S, R_u = u - x - w
   double *Rd, *Rxz;
   const double *rd, *x, *zeta, *z;
   double rho;
+  const int8_t* vt;
+  double *Rws, *Ru;
+  const double *u, *w, *s;
   __device__ void operator()(int64_t j, double*, double*) const {
+    const int k = kind_of(vt, j);
     Rd[j] = rd[j] + rho * (x[j] - zeta[j]);
-    Rxz[j] = -x[j] * z[j];
+    Rxz[j] = k == NYS_VAR_FREE ? 0.0 : -x[j] * z[j];
+    if (Rws) {
+      Rws[j] = k == NYS_VAR_BOX ? -w[j] * s[j] : 0.0;
+      Ru[j] = k == NYS_VAR_BOX ? u[j] - x[j] - w[j] : 0.0;
+    }
   }
 };
 struct PredM {        // R_p = r_p - delta (y - lambda)
@@ -86,42 +117,74 @@ struct PredM {        // R_p = r_p - delta (y - lambda)
   double delta;
   __device__ void operator()(int64_t j, double*, double*) const { Rp[j] = rp[j] - delta * (y[j] - lam[j]); }
 };
-struct Ratio {        // min over dx<0 of -x/dx, and over dz<0 of -z/dz
+struct Ratio {        // primal: min -x/dx (I, J) and -w/dw (J); dual: min -z/dz (I, J) and -s/ds (J)
   const double *x, *dx, *z, *dz;
+  const int8_t* vt;
+  const double *w, *dw, *s, *ds;
   __device__ void operator()(int64_t j, double*, double* mn) const {
-    if (dx[j] < 0.0) mn[0] = fmin(mn[0], -x[j] / dx[j]);
-    if (dz[j] < 0.0) mn[1] = fmin(mn[1], -z[j] / dz[j]);
+    const int k = kind_of(vt, j);
+    if (k != NYS_VAR_FREE) {
+      if (dx[j] < 0.0) mn[0] = fmin(mn[0], -x[j] / dx[j]);
+      if (dz[j] < 0.0) mn[1] = fmin(mn[1], -z[j] / dz[j]);
+    }
+    if (k == NYS_VAR_BOX) {
+      if (dw[j] < 0.0) mn[0] = fmin(mn[0], -w[j] / dw[j]);
+      if (ds[j] < 0.0) mn[1] = fmin(mn[1], -s[j] / ds[j]);
+    }
   }
 };
-struct MuAff {        // (x + ap dx)^T (z + ad dz)
+struct MuAff {        // (x + ap dx)^T (z + ad dz) over I, J plus (w + ap dw)^T (s + ad ds) over J
   const double *x, *dx, *z, *dz;
   double ap, ad;
-  __device__ void operator()(int64_t j, double* s, double*) const {
-    s[0] = fma(fma(ap, dx[j], x[j]), fma(ad, dz[j], z[j]), s[0]);
+  const int8_t* vt;
+  const double *w, *dw, *s, *ds;
+  __device__ void operator()(int64_t j, double* a, double*) const {
+    const int k = kind_of(vt, j);
+    if (k != NYS_VAR_FREE) a[0] = fma(fma(ap, dx[j], x[j]), fma(ad, dz[j], z[j]), a[0]);
+    if (k == NYS_VAR_BOX) a[0] = fma(fma(ap, dw[j], w[j]), fma(ad, ds[j], s[j]), a[0]);
   }
 };
-struct CorrRxz {      // R_xz = mu~ 1 - dxp .* dzp
+struct CorrRxz {      // R_xz = mu~ - dxp .* dzp (I, J); R_ws = mu~ - dwp .* dsp (J)
   double* R;
   const double *dxp, *dzp;
   double mut;
-  __device__ void operator()(int64_t j, double*, double*) const { R[j] = mut - dxp[j] * dzp[j]; }
+  const int8_t* vt;
+  double* Rws;
+  const double *dwp, *dsp;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    const int k = kind_of(vt, j);
+    R[j] = k == NYS_VAR_FREE ? 0.0 : mut - dxp[j] * dzp[j];
+    if (Rws) Rws[j] = k == NYS_VAR_BOX ? mut - dwp[j] * dsp[j] : 0.0;
+  }
 };
 struct AddTo {        // a += b
   double* a;
   const double* b;
   __device__ void operator()(int64_t j, double*, double*) const { a[j] += b[j]; }
 };
-struct UpdXZ {        // x += ap dx, z += ad dz, zeta = x ; x^T z, #non-finite
+struct UpdXZ {        // x, w += ap (dx, dw); z, s += ad (dz, ds); zeta = x; mu numerator, #non-finite
   double *x, *z, *zeta;
   const double *dx, *dz;
   double ap, ad;
-  __device__ void operator()(int64_t j, double* s, double*) const {
+  const int8_t* vt;
+  double *w, *s;
+  const double *dw, *ds;
+  __device__ void operator()(int64_t j, double* a, double*) const {
+    const int k = kind_of(vt, j);
     const double xn = fma(ap, dx[j], x[j]), zn = fma(ad, dz[j], z[j]);
     x[j] = xn;
     z[j] = zn;
     zeta[j] = xn;
-    s[0] = fma(xn, zn, s[0]);
-    if (!isfinite(xn) || !isfinite(zn)) s[1] += 1.0;
+    if (k != NYS_VAR_FREE) a[0] = fma(xn, zn, a[0]);
+    bool bad = !isfinite(xn) || !isfinite(zn);
+    if (k == NYS_VAR_BOX) {
+      const double wn = fma(ap, dw[j], w[j]), sn = fma(ad, ds[j], s[j]);
+      w[j] = wn;
+      s[j] = sn;
+      a[0] = fma(wn, sn, a[0]);
+      bad = bad || !isfinite(wn) || !isfinite(sn);
+    }
+    if (bad) a[1] += 1.0;
   }
 };
 struct UpdY {         // y += ad dy, lambda = y ; #non-finite
@@ -140,33 +203,105 @@ struct CPlusQX {      // t = c + Q x
   const double *c, *q, *x;
   __device__ void operator()(int64_t j, double*, double*) const { t[j] = c[j] + q[j] * x[j]; }
 };
-struct MinXZ {
-  const double *x, *z;
-  __device__ void operator()(int64_t j, double*, double* mn) const {
-    mn[0] = fmin(mn[0], x[j]);
-    mn[1] = fmin(mn[1], z[j]);
+struct HalfU {        // t = u/2 on J, 0 elsewhere (centre of the initial primal candidate)
+  double* t;
+  const int8_t* vt;
+  const double* u;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    t[j] = kind_of(vt, j) == NYS_VAR_BOX ? 0.5 * u[j] : 0.0;
   }
 };
-struct InitSums {     // (x+dp)^T (z+dd), sum(z+dd), sum(x+dp)
+struct InitZ {        // from g = c + Q x~ - A^T y~ (in z): z~_J = g/2, s~_J = -g/2, w~_J = u - x~
+  double *z, *w, *s;
+  const double *x, *u;
+  const int8_t* vt;
+  __device__ void operator()(int64_t j, double*, double*) const {
+    if (kind_of(vt, j) == NYS_VAR_BOX) {
+      const double g = z[j];
+      z[j] = 0.5 * g;
+      s[j] = -0.5 * g;
+      w[j] = u[j] - x[j];
+    } else {
+      w[j] = 0.0;
+      s[j] = 0.0;
+    }
+  }
+};
+struct MinXZ {        // min of (x~_IJ, w~_J) and of (z~_IJ, s~_J)
+  const double *x, *z;
+  const int8_t* vt;
+  const double *w, *s;
+  __device__ void operator()(int64_t j, double*, double* mn) const {
+    const int k = kind_of(vt, j);
+    if (k != NYS_VAR_FREE) {
+      mn[0] = fmin(mn[0], x[j]);
+      mn[1] = fmin(mn[1], z[j]);
+    }
+    if (k == NYS_VAR_BOX) {
+      mn[0] = fmin(mn[0], w[j]);
+      mn[1] = fmin(mn[1], s[j]);
+    }
+  }
+};
+struct InitSums {     // gamma_xz + gamma_ws, sum of dual and of primal shifted entries
   const double *x, *z;
   double dp, dd;
-  __device__ void operator()(int64_t j, double* s, double*) const {
-    const double a = x[j] + dp, b = z[j] + dd;
-    s[0] = fma(a, b, s[0]);
-    s[1] += b;
-    s[2] += a;
+  const int8_t* vt;
+  const double *w, *s;
+  __device__ void operator()(int64_t j, double* a, double*) const {
+    const int k = kind_of(vt, j);
+    if (k != NYS_VAR_FREE) {
+      const double xa = x[j] + dp, zb = z[j] + dd;
+      a[0] = fma(xa, zb, a[0]);
+      a[1] += zb;
+      a[2] += xa;
+    }
+    if (k == NYS_VAR_BOX) {
+      const double wa = w[j] + dp, sb = s[j] + dd;
+      a[0] = fma(wa, sb, a[0]);
+      a[1] += sb;
+      a[2] += wa;
+    }
   }
 };
-struct InitShift {
+struct InitShift {    // x_IJ, w_J += sp; z_IJ, s_J += sd (entries still <= 0 set to 1); z_F = 0
   double *x, *z, *zeta;
   double sp, sd;
+  const int8_t* vt;
+  double *w, *s;
   __device__ void operator()(int64_t j, double*, double*) const {
-    double xn = x[j] + sp, zn = z[j] + sd;
-    if (!(xn > 0.0)) xn = 1.0;
-    if (!(zn > 0.0)) zn = 1.0;
-    x[j] = xn;
-    z[j] = zn;
-    zeta[j] = xn;
+    const int k = kind_of(vt, j);
+    if (k != NYS_VAR_FREE) {
+      double xn = x[j] + sp, zn = z[j] + sd;
+      if (!(xn > 0.0)) xn = 1.0;
+      if (!(zn > 0.0)) zn = 1.0;
+      x[j] = xn;
+      z[j] = zn;
+    } else {
+      z[j] = 0.0;
+    }
+    if (k == NYS_VAR_BOX) {
+      double wn = w[j] + sp, sn = s[j] + sd;
+      if (!(wn > 0.0)) wn = 1.0;
+      if (!(sn > 0.0)) sn = 1.0;
+      w[j] = wn;
+      s[j] = sn;
+    }
+    zeta[j] = x[j];
+  }
+};
+struct KindStats {    // #free, #box, #bad kind or bound, ||u_J||^2
+  const int8_t* vt;
+  const double* u;
+  __device__ void operator()(int64_t j, double* a, double*) const {
+    const int k = vt[j];
+    if (k == NYS_VAR_FREE) a[0] += 1.0;
+    if (k == NYS_VAR_BOX) {
+      a[1] += 1.0;
+      if (!(u[j] > 0.0) || !isfinite(u[j])) a[2] += 1.0;
+      else a[3] = fma(u[j], u[j], a[3]);
+    }
+    if (k != NYS_VAR_NONNEG && k != NYS_VAR_FREE && k != NYS_VAR_BOX) a[2] += 1.0;
   }
 };
 struct AdjD {         // D_adj = 0 where x <= z, else max(q, rho)^{-1}; tn = D g
@@ -277,8 +412,8 @@ Opts read_opts(const nys_ipm_opts* o) {
 
 using namespace nys;
 
-extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in, double* x,
-                         double* y, double* z, nys_ipm_info* info) {
+static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in, double* x, double* y,
+                    double* z, double* w_out, double* s_out, nys_ipm_info* info) {
   if (!h) return NYS_EINVAL;
   NYS_CHECK(check_qp(h, qp, "ipm_solve"));
   if (!x || !y || !z) return set_error(h, NYS_EINVAL, "ipm_solve: NULL output");
@@ -306,13 +441,26 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     if (hs[0] + hs[1] + hs[3] + hs[5] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: non-finite problem data");
     if (hs[6] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: q has negative entries");
   }
+  // ---- variable kinds: counts for mu, ||u_J||, validation
+  const int8_t* vt = qp->vtype;
+  double cnt = (double)n, unorm = 0.0;
+  if (vt) {
+    if (!qp->u) return set_error(h, NYS_EINVAL, "ipm_solve: vtype given without u");
+    NYS_CHECK((map_reduce<4, 0>(h, n, KindStats{vt, qp->u}, sc + SC_RED0)));
+    NYS_CHECK(read_scalars(h, SC_RED0, 4));
+    const double* hs = h->hscal + SC_RED0;
+    if (hs[2] > 0) return set_error(h, NYS_EINVAL, "ipm_solve: bad variable kind or upper bound (need 0 < u < inf)");
+    cnt = (double)n - hs[0] + hs[1];
+    unorm = std::sqrt(hs[3]);
+  }
+  const bool box = vt != nullptr;
   nys_matrix At{};
   NYS_CHECK(with_transpose(h, A, o.transpose, WS_AT, &At));
   A = &At;
 
   // ---- workspace
   double* base;
-  NYS_CHECK(ws(h, WS_IPM, (size_t)12 * n + 8 * m + 64, &base));
+  NYS_CHECK(ws(h, WS_IPM, (size_t)12 * n + 8 * m + 64 + (box ? (size_t)8 * n : 0), &base));
   double* D = base;
   double* zeta = base + n;
   double* aty = base + 2 * n;
@@ -333,6 +481,21 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
   double* dyc = mb + 4 * m;
   double* rhs = mb + 5 * m;
   double* tm = mb + 6 * m;
+  // box arrays: slack w and its dual s (the caller's when given), the r_ws
+  // and r_u right-hand sides, and the w, s directions of both solves
+  double *w = nullptr, *s = nullptr, *Rws = nullptr, *Ru = nullptr;
+  double *dwp = nullptr, *dsp = nullptr, *dwc = nullptr, *dsc = nullptr;
+  if (box) {
+    double* bb = base + 12 * n + 8 * m + 64;
+    w = w_out ? w_out : bb;
+    s = s_out ? s_out : bb + n;
+    Rws = bb + 2 * n;
+    Ru = bb + 3 * n;
+    dwp = bb + 4 * n;
+    dsp = bb + 5 * n;
+    dwc = bb + 6 * n;
+    dsc = bb + 7 * n;
+  }
   double *U, *lamh;
   NYS_CHECK(ws(h, WS_PCU, (size_t)m * o.ell, &U));
   NYS_CHECK(ws(h, WS_PCL, (size_t)o.ell + 8, &lamh));
@@ -378,16 +541,30 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     ip.rtol = 1e-10;
     ip.atol = 0.0;
     nys_pcg_info pi{};
+    // x~ = u/2 + A^T (A A^T + 10 I)^{-1} (b - A u/2)  (u/2 on J only; 0 without box variables)
+    const double* r0 = qp->b;
+    if (box) {
+      NYS_CHECK(map_reduce<0, 0>(h, n, HalfU{tn, vt, qp->u}, nullptr));
+      GemvN gu;
+      gu.A = A;
+      gu.w = tn;
+      gu.sA = -1.0;
+      gu.x0 = qp->b;
+      gu.out = rhs;
+      NYS_CHECK(gemv_n(h, gu));
+      r0 = rhs;
+    }
     auto t0 = clk::now();
-    int rc = ipm_pcg(h, A, ones, INIT_REG, Un, lamh, o.ell, pchp, qp->b, tm, &ip, &pi);
+    int rc = ipm_pcg(h, A, ones, INIT_REG, Un, lamh, o.ell, pchp, r0, tm, &ip, &pi);
     h->t_pcg += ms_since(t0);
     if (rc < 0) return rc;
     pcg_total += pi.iters;
     GemvT g1;
     g1.A = A;
     g1.v = tm;
+    g1.x0 = box ? tn : nullptr;
     g1.w = x;
-    NYS_CHECK(gemv_t(h, g1));                                          // x~ = A^T t
+    NYS_CHECK(gemv_t(h, g1));                                          // x~
     NYS_CHECK(map_reduce<0, 0>(h, n, CPlusQX{tn, qp->c, qp->q, x}, nullptr));
     GemvN g2;
     g2.A = A;
@@ -406,17 +583,18 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     g3.x0 = tn;
     g3.w = z;
     NYS_CHECK(gemv_t(h, g3));                                          // z~ = c + Q x~ - A^T y~
-    NYS_CHECK((map_reduce<0, 2>(h, n, MinXZ{x, z}, sc + SC_RED0)));
+    if (box) NYS_CHECK(map_reduce<0, 0>(h, n, InitZ{z, w, s, x, qp->u, vt}, nullptr));
+    NYS_CHECK((map_reduce<0, 2>(h, n, MinXZ{x, z, vt, w, s}, sc + SC_RED0)));
     NYS_CHECK(read_scalars(h, SC_RED0, 2));
     const double dp = std::max(-1.5 * h->hscal[SC_RED0], 0.0);
     const double dd = std::max(-1.5 * h->hscal[SC_RED0 + 1], 0.0);
-    NYS_CHECK((map_reduce<3, 0>(h, n, InitSums{x, z, dp, dd}, sc + SC_RED0)));
+    NYS_CHECK((map_reduce<3, 0>(h, n, InitSums{x, z, dp, dd, vt, w, s}, sc + SC_RED0)));
     NYS_CHECK(read_scalars(h, SC_RED0, 3));
     const double gamma = h->hscal[SC_RED0];
     const double sz = h->hscal[SC_RED0 + 1], sx = h->hscal[SC_RED0 + 2];
     const double sp = dp + (sz != 0 ? 0.5 * gamma / sz : 0.0);
     const double sd = dd + (sx != 0 ? 0.5 * gamma / sx : 0.0);
-    NYS_CHECK(map_reduce<0, 0>(h, n, InitShift{x, z, zeta, sp, sd}, nullptr));
+    NYS_CHECK(map_reduce<0, 0>(h, n, InitShift{x, z, zeta, sp, sd, vt, w, s}, nullptr));
     NYS_CHECK(copy(h, lam, y, m));
   }
 
@@ -438,21 +616,23 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     gp.x0 = qp->b;
     gp.out = rp;
     NYS_CHECK(gemv_n(h, gp));                                          // r_p = b - A x
-    NYS_CHECK((map_reduce<3, 0>(h, n, ResidD{rd, qp->c, qp->q, x, aty, z}, sc + SC_RED0)));
-    NYS_CHECK(dot(h, rp, rp, m, sc + SC_RED0 + 3));
-    NYS_CHECK(read_scalars(h, SC_RED0, 4));
+    NYS_CHECK((map_reduce<4, 0>(h, n, ResidD{rd, qp->c, qp->q, x, aty, z, vt, qp->u, w, s}, sc + SC_RED0)));
+    NYS_CHECK(dot(h, rp, rp, m, sc + SC_RED0 + 4));
+    NYS_CHECK(read_scalars(h, SC_RED0, 5));
     const double* hs = h->hscal + SC_RED0;
     if (hs[2] > 0) {
       status = set_error(h, NYS_ENUMERIC, "ipm_solve: non-finite iterate at iteration %d", k);
       break;
     }
-    const double mu = hs[1] / n;
-    const double rp_rel = std::sqrt(hs[3]) / (1.0 + bnorm);
+    const double mu = cnt > 0 ? hs[1] / cnt : 0.0;
+    const double rp_rel = std::sqrt(hs[4]) / (1.0 + bnorm);
     const double rd_rel = std::sqrt(hs[0]) / (1.0 + cnorm);
-    const double kkt = std::max(std::max(rp_rel, rd_rel), mu);
+    const double ru_rel = std::sqrt(hs[3]) / (1.0 + unorm);
+    const double kkt = std::max(std::max(rp_rel, rd_rel), std::max(ru_rel, mu));
     inf.kkt_rel = kkt;
     inf.rp_rel = rp_rel;
     inf.rd_rel = rd_rel;
+    inf.ru_rel = ru_rel;
     inf.mu = mu;
     if (o.verbose)
       std::fprintf(stderr, "[nysipm] k=%d rp=%.2e rd=%.2e mu=%.2e rho=%.2e pcg_total=%d t=%.1fms\n", k,
@@ -463,11 +643,11 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     }
     if (k >= o.max_iter) break;
 
-    NYS_CHECK(map_reduce<0, 0>(h, n, Scaling{D, qp->q, x, z, rho}, nullptr));
+    NYS_CHECK(map_reduce<0, 0>(h, n, Scaling{D, qp->q, x, z, rho, vt, w, s}, nullptr));
     NYS_CHECK(timed_sketch(D, (uint64_t)k, delta));
 
     // predictor
-    NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho}, nullptr));
+    NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho, vt, Rws, Ru, qp->u, w, s}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, m, PredM{Rp, rp, y, lam, delta}, nullptr));
     // inner tolerance: max(1e-12 ||xi||, min(cap ||xi||, tau)), cap = pcg.rtol or 1e-2,
     // tau = max(0.1 mu, 0.1 tol (1 + ||b||)): the normal-equation residual enters
@@ -476,7 +656,9 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     const double tau = std::max(0.1 * mu, 0.1 * o.tol * (1.0 + bnorm));
     nys_pcg_info pi{};
     auto t0 = clk::now();
-    int rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, o.ell, pchp, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp, &pi);
+    const BoxNewton bxp = box ? BoxNewton{vt, w, s, Ru, Rws, dwp, dsp} : BoxNewton{};
+    int rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, o.ell, pchp, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp, &pi,
+                        bxp);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;
@@ -486,20 +668,21 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     if (o.verbose)
       std::fprintf(stderr, "[nysipm]   predictor pcg: iters=%d status=%d |res|=%.2e tau=%.2e\n", pi.iters,
                    pi.status, pi.true_res, tau);
-    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp}, sc + SC_RED0)));
+    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp, vt, w, dwp, s, dsp}, sc + SC_RED0)));
     NYS_CHECK(read_scalars(h, SC_RED0, 2));
     double ap = STEP * std::min(1.0, h->hscal[SC_RED0]);
     double ad = STEP * std::min(1.0, h->hscal[SC_RED0 + 1]);
-    NYS_CHECK((map_reduce<1, 0>(h, n, MuAff{x, dxp, z, dzp, ap, ad}, sc + SC_RED0)));
+    NYS_CHECK((map_reduce<1, 0>(h, n, MuAff{x, dxp, z, dzp, ap, ad, vt, w, dwp, s, dsp}, sc + SC_RED0)));
     NYS_CHECK(read_scalars(h, SC_RED0, 1));
-    const double mu_aff = h->hscal[SC_RED0] / n;
-    const double mut = mu_aff * mu_aff * mu_aff / (mu * mu);
+    const double mu_aff = cnt > 0 ? h->hscal[SC_RED0] / cnt : 0.0;
+    const double mut = mu > 0 ? mu_aff * mu_aff * mu_aff / (mu * mu) : 0.0;
 
     // corrector
-    NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut}, nullptr));
+    NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut, vt, Rws, dwp, dsp}, nullptr));
     t0 = clk::now();
+    const BoxNewton bxc = box ? BoxNewton{vt, w, s, nullptr, Rws, dwc, dsc} : BoxNewton{};
     rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, o.ell, pchp, nullptr, nullptr, Rxz, &o.pcg, tau, dxc, dyc,
-                    dzc, &pi);
+                    dzc, &pi, bxc);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;
@@ -512,18 +695,22 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
     NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dxp, dxc}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dzp, dzc}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, m, AddTo{dyp, dyc}, nullptr));
-    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp}, sc + SC_RED0)));
+    if (box) {
+      NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dwp, dwc}, nullptr));
+      NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dsp, dsc}, nullptr));
+    }
+    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp, vt, w, dwp, s, dsp}, sc + SC_RED0)));
     NYS_CHECK(read_scalars(h, SC_RED0, 2));
     ap = STEP * std::min(1.0, h->hscal[SC_RED0]);
     ad = STEP * std::min(1.0, h->hscal[SC_RED0 + 1]);
-    NYS_CHECK((map_reduce<2, 0>(h, n, UpdXZ{x, z, zeta, dxp, dzp, ap, ad}, sc + SC_RED0)));
+    NYS_CHECK((map_reduce<2, 0>(h, n, UpdXZ{x, z, zeta, dxp, dzp, ap, ad, vt, w, s, dwp, dsp}, sc + SC_RED0)));
     NYS_CHECK((map_reduce<1, 0>(h, m, UpdY{y, lam, dyp, ad}, sc + SC_RED0 + 2)));
     NYS_CHECK(read_scalars(h, SC_RED0, 3));
     if (h->hscal[SC_RED0 + 1] + h->hscal[SC_RED0 + 2] > 0) {
       status = set_error(h, NYS_ENUMERIC, "ipm_solve: non-finite iterate at iteration %d", k);
       break;
     }
-    const double mu_new = h->hscal[SC_RED0] / n;
+    const double mu_new = cnt > 0 ? h->hscal[SC_RED0] / cnt : 0.0;
     rho = delta = std::max(REG_FLOOR, std::min(rho, mu_new));
   }
   NYS_CHECK(sync(h));
@@ -543,6 +730,17 @@ extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opt
   return status;
 }
 
+extern "C" int ipm_solve(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* x, double* y,
+                         double* z, nys_ipm_info* info) {
+  return ipm_core(h, qp, opts, x, y, z, nullptr, nullptr, info);
+}
+
+extern "C" int ipm_solve_box(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, double* x, double* y,
+                             double* z, double* w, double* s, nys_ipm_info* info) {
+  if (h && qp && !qp->vtype) return set_error(h, NYS_EINVAL, "ipm_solve_box: vtype is NULL (use ipm_solve)");
+  return ipm_core(h, qp, opts, x, y, z, w, s, info);
+}
+
 extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in, const double* x,
                            const double* y, const double* z, double rho, double delta, const double* g,
                            double* grad_c, double* grad_b, double* grad_q, double* grad_A,
@@ -550,6 +748,7 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   if (!h) return NYS_EINVAL;
   NYS_CHECK(check_qp(h, qp, "ipm_adjoint"));
   if (!x || !y || !z || !g) return set_error(h, NYS_EINVAL, "ipm_adjoint: NULL input");
+  if (qp->vtype) return set_error(h, NYS_EINVAL, "ipm_adjoint: free or box-constrained variables are not supported");
   if (!(delta > 0) || !std::isfinite(delta) || !(rho >= 0) || !std::isfinite(rho))
     return set_error(h, NYS_EINVAL, "ipm_adjoint: need delta > 0 and rho >= 0");
   Opts o = read_opts(opts_in);

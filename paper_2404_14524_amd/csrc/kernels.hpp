@@ -92,6 +92,20 @@ int pcg_update(nys_handle h, int64_t m, double* y, double* r, const double* p,
                const double* q, const double* U, const double* lam, int ell, double delta,
                double* t, bool ext = false);
 
+// ---------------------------------------------------------------- Newton step data
+// Box and free variables of Algorithm 5 (all NULL: every variable non-negative).
+// vt: index kinds (NYS_VAR_*); w, s: slack and its dual; ru, rws: the r_u and
+// r_ws right-hand sides (ru may be NULL: zero); dw, ds: outputs.
+struct BoxNewton {
+  const int8_t* vt = nullptr;
+  const double* w = nullptr;
+  const double* s = nullptr;
+  const double* ru = nullptr;
+  const double* rws = nullptr;
+  double* dw = nullptr;
+  double* ds = nullptr;
+};
+
 // ---------------------------------------------------------------- partial Cholesky (comparator)
 // Builds P (caller-sized: P->m = A->m, P->ell) for N + delta I, N = A diag(d) A^T.
 // Synchronises (checks the Cholesky of the pivot block).

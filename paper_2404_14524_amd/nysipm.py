@@ -58,7 +58,7 @@ class nys_pcg_info(C.Structure):
 
 class nys_qp(C.Structure):
     _fields_ = [("A", C.POINTER(nys_matrix)), ("A_lo", C.POINTER(nys_matrix)), ("b", C.c_void_p),
-                ("c", C.c_void_p), ("q", C.c_void_p)]
+                ("c", C.c_void_p), ("q", C.c_void_p), ("vtype", C.c_void_p), ("u", C.c_void_p)]
 
 
 class nys_ipm_opts(C.Structure):
@@ -72,14 +72,15 @@ class nys_ipm_info(C.Structure):
     _fields_ = [("iters", C.c_int32), ("pcg_iters_total", C.c_int32), ("status", C.c_int32),
                 ("kkt_rel", C.c_double), ("rp_rel", C.c_double), ("rd_rel", C.c_double),
                 ("mu", C.c_double), ("rho", C.c_double), ("delta", C.c_double),
-                ("t_sketch_ms", C.c_double), ("t_pcg_ms", C.c_double), ("t_other_ms", C.c_double)]
+                ("t_sketch_ms", C.c_double), ("t_pcg_ms", C.c_double), ("t_other_ms", C.c_double),
+                ("ru_rel", C.c_double)]
 
 
 EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
            "nys_profile_enable", "nys_profile_read", "nys_stream_read",
            "nys_normal_apply", "nys_transpose", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint",
-           "nys_pchol_build", "nys_pchol_apply", "nys_pcg_solve_pchol"]
+           "nys_pchol_build", "nys_pchol_apply", "nys_pcg_solve_pchol", "ipm_solve_box"]
 
 _lib = None
 _lock = threading.Lock()
@@ -122,6 +123,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                                  C.POINTER(nys_pcg_opts), vp, vp, vp, C.POINTER(nys_pcg_info)],
             "ipm_solve": [vp, C.POINTER(nys_qp), C.POINTER(nys_ipm_opts), vp, vp, vp,
                           C.POINTER(nys_ipm_info)],
+            "ipm_solve_box": [vp, C.POINTER(nys_qp), C.POINTER(nys_ipm_opts), vp, vp, vp, vp, vp,
+                              C.POINTER(nys_ipm_info)],
             "ipm_adjoint": [vp, C.POINTER(nys_qp), C.POINTER(nys_ipm_opts), vp, vp, vp, dbl, dbl, vp,
                             vp, vp, vp, vp, C.POINTER(nys_pcg_info)],
         }
@@ -367,13 +370,42 @@ def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0,
                         0 if transposed_copy else 1, PRECONDS[precond])
 
 
-def _qp(A, b, c, q, A_lo, A_t=None):
+def _qp(A, b, c, q, A_lo, A_t=None, vtype=None, u=None):
     Am = _mat(A, A_t)
     Alo = _mat(A_lo) if A_lo is not None else None
     keep = (Am, Alo)
     qp = nys_qp(C.pointer(Am), C.pointer(Alo) if Alo is not None else None, b.data_ptr(),
-                c.data_ptr(), q.data_ptr())
+                c.data_ptr(), q.data_ptr(), _ptr(vtype), _ptr(u))
     return qp, keep
+
+
+VAR_NONNEG, VAR_FREE, VAR_BOX = 0, 1, 2
+
+
+def ipm_solve_box(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor, vtype: torch.Tensor,
+                  u: torch.Tensor, ell: int, A_lo: Optional[torch.Tensor] = None,
+                  A_t: Optional[torch.Tensor] = None, **kw):
+    """Nys-IP-PMM for free (VAR_FREE), non-negative (VAR_NONNEG) and box-constrained
+    (VAR_BOX, 0 <= x_j <= u_j) variables.  vtype: n int8; u: n float64 (read on
+    box indices).  Returns (x, y, z, w, s, info)."""
+    lib, h = _handle(A.device)
+    m, n = A.shape
+    dev = A.device
+    _vec(b, m, "b", dev)
+    _vec(c, n, "c", dev)
+    _vec(q, n, "q", dev)
+    _vec(u, n, "u", dev)
+    if vtype.dtype != torch.int8 or vtype.numel() != n or not vtype.is_contiguous() or vtype.device != dev:
+        raise ValueError(f"vtype: need a contiguous int8 tensor of {n} elements on {dev}")
+    x, z, w, s = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4))
+    y = torch.empty(m, dtype=torch.float64, device=dev)
+    qp, keep = _qp(A, b, c, q, A_lo, A_t, vtype, u)
+    o = _ipm_opts(ell, **kw)
+    info = nys_ipm_info()
+    rc = lib.ipm_solve_box(h, C.byref(qp), C.byref(o), _ptr(x), _ptr(y), _ptr(z), _ptr(w), _ptr(s), C.byref(info))
+    _check(lib, h, rc)
+    del keep
+    return x, y, z, w, s, info
 
 
 def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor, ell: int,

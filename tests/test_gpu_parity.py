@@ -479,3 +479,83 @@ def test_ipm_solve_comparators(nys, precond):
     assert problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))["kkt"] <= 1e-6
     xs = inst.x_star.numpy()
     assert np.linalg.norm(_np(x) - xs) <= 1e-5 * np.linalg.norm(xs)
+
+
+# ------------------------------------------------------------------ free and box-constrained variables
+
+def _box_case(m, n, seed, q_lo=0.5):
+    from oracle import boxqp
+    rng = np.random.default_rng(seed)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    vt = rng.choice([0, 1, 2], size=n, p=[0.4, 0.2, 0.4]).astype(np.int8)
+    q = rng.uniform(q_lo, 1.5, n)
+    u = np.where(vt == 2, rng.uniform(0.5, 2.0, n), 0.0)
+    b, c, xs, ys, zs, ws, ss = boxqp.planted(A, q, vt, u, rng)
+    return A, b, c, q, u, vt, xs, ys
+
+
+@pytest.mark.parametrize("m,n,precond", [(40, 120, "nystrom"), (300, 1000, "nystrom"), (300, 1000, "pchol")])
+def test_ipm_solve_box_planted(nys, m, n, precond):
+    """Free, non-negative and box-constrained variables: the planted optimum
+    (some x at 0, some at u, some inside, some free), and the oracle's."""
+    from oracle import boxqp
+    print(f"ipm_solve_box {m}x{n} {precond}", flush=True)
+    A, b, c, q, u, vt, xs, ys = _box_case(m, n, seed=m + n)
+    x, y, z, w, s, info = nys.ipm_solve_box(_t(A), _t(b), _t(c), _t(q),
+                                            torch.as_tensor(vt, device=DEV), _t(u), ell=20, tol=1e-8,
+                                            precond=precond)
+    assert info.status == 0, (info.kkt_rel, info.iters)
+    xg, yg, zg, wg, sg = (_np(t) for t in (x, y, z, w, s))
+    meas = boxqp.kkt_measure(A, b, c, q, u, vt.astype(int), xg, yg, zg, wg, sg)
+    assert meas["kkt"] <= 1e-8, meas
+    assert np.all(xg[vt == 2] >= 0) and np.all(xg[vt == 2] <= u[vt == 2]) and np.all(xg[vt == 0] >= 0)
+    assert np.all(zg[vt == 1] == 0) and np.all(wg[vt != 2] == 0) and np.all(sg[vt != 2] == 0)
+    assert np.linalg.norm(xg - xs) <= 1e-6 * np.linalg.norm(xs)
+    ref = boxqp.solve(A, b, c, q, u, vt.astype(int), tol=1e-10)
+    assert np.linalg.norm(xg - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+
+
+def test_ipm_solve_box_all_nonneg_matches_ipm_solve(nys):
+    """vtype all NONNEG: the box form takes the same steps as ipm_solve."""
+    inst = make_instance("gauss_200x500", seed=1)
+    A, b, c, q = (_t(inst.A.double().numpy()), _t(inst.b.numpy()), _t(inst.c.numpy()), _t(inst.q.numpy()))
+    n = A.shape[1]
+    x1, y1, z1, i1 = nys.ipm_solve(A, b, c, q, ell=20, tol=1e-8, seed=0)
+    vt = torch.zeros(n, dtype=torch.int8, device=DEV)
+    x2, y2, z2, w2, s2, i2 = nys.ipm_solve_box(A, b, c, q, vt, torch.zeros(n, dtype=torch.float64, device=DEV),
+                                               ell=20, tol=1e-8, seed=0)
+    assert i1.iters == i2.iters
+    assert float((x1 - x2).abs().max()) <= 1e-12 * float(x1.abs().max())
+    assert not bool(w2.any()) and not bool(s2.any())
+
+
+def test_ipm_solve_box_svm_form(nys):
+    """The dual linear SVM in form (P~): v free with Q = I, 0 <= p <= tau,
+    A = [I, -X diag(y); 0, y^T] -- against the oracle (v and the objective
+    are unique; p need not be)."""
+    from instances import svm_instance
+    from oracle import boxqp
+    S = svm_instance(40, 400, seed=7, sep=2.0)
+    A, b, c, q, u, vt = (S[k].numpy() for k in ("A", "b", "c", "q", "u", "vtype"))
+    x, y, z, w, s, info = nys.ipm_solve_box(_t(A), _t(b), _t(c), _t(q), torch.as_tensor(vt, device=DEV), _t(u),
+                                            ell=20, tol=1e-8)
+    assert info.status == 0, info.kkt_rel
+    xg = _np(x)
+    assert boxqp.kkt_measure(A, b, c, q, u, vt.astype(int), xg, _np(y), _np(z), _np(w), _np(s))["kkt"] <= 1e-8
+    ref = boxqp.solve(A, b, c, q, u, vt.astype(int), tol=1e-10)
+    obj = lambda v: 0.5 * float(v @ (q * v)) + float(c @ v)
+    assert abs(obj(xg) - obj(ref["x"])) <= 1e-6 * (1 + abs(obj(ref["x"])))
+    np.testing.assert_allclose(xg[:40], ref["x"][:40], atol=1e-5 * (1 + np.abs(ref["x"][:40]).max()))
+
+
+def test_ipm_solve_box_rejects_bad_kinds(nys):
+    A, b, c, q, u, vt, xs, ys = _box_case(20, 50, seed=3)
+    bad = vt.copy()
+    bad[4] = 7
+    with pytest.raises(nys.NysError):
+        nys.ipm_solve_box(_t(A), _t(b), _t(c), _t(q), torch.as_tensor(bad, device=DEV), _t(u), ell=5)
+    j = int(np.flatnonzero(vt == 2)[0])
+    ub = u.copy()
+    ub[j] = 0.0
+    with pytest.raises(nys.NysError):
+        nys.ipm_solve_box(_t(A), _t(b), _t(c), _t(q), torch.as_tensor(vt, device=DEV), _t(ub), ell=5)

@@ -491,3 +491,25 @@ def test_box_all_nonneg_reduces_to_the_pinned_oracle():
 def oipm_solve(A, b, c, q):
     from oracle import ippmm
     return ippmm.solve(A, b, c, q, tol=1e-8)
+
+
+def test_box_oracle_solves_the_svm_form():
+    """The dual SVM in form (P~) (v free, 0 <= p <= tau): at the oracle's
+    solution v = X diag(y) p (first constraint block), y^T p = 0, and the
+    classifier separates most of the training set."""
+    from instances import svm_instance
+    from oracle import boxqp
+    S = svm_instance(8, 60, seed=3, sep=3.0)
+    A, b, c, q, u, vt = (S[k].numpy() for k in ("A", "b", "c", "q", "u", "vtype"))
+    res = boxqp.solve(A, b, c, q, u, vt.astype(int), tol=1e-9)
+    assert res["status"] == 0
+    d = 8
+    v, p = res["x"][:d], res["x"][d:]
+    yl = S["labels"].numpy()
+    X = -A[:d, d:] * yl[None, :]
+    np.testing.assert_allclose(v, X @ (yl * p), atol=1e-8)
+    assert abs(yl @ p) <= 1e-8 and p.min() >= -1e-9 and p.max() <= 1.0 + 1e-9
+    sv = (p > 1e-6) & (p < 1 - 1e-6)                  # margin support vectors fix the bias
+    bias = float(np.median(yl[sv] - X[:, sv].T @ v)) if sv.any() else 0.0
+    acc = float(np.mean(np.sign(X.T @ v + bias) == yl))
+    assert acc >= 0.9, acc

@@ -200,6 +200,46 @@ def cpu_baseline(inst, D, delta, gpu_iters, budget_cols: int):
     }
 
 
+# SVM-form workloads at the shapes of the paper's dense SVM datasets (Table 3),
+# with synthetic features (the datasets are not available): d, n, ell.
+SVM_SHAPES = {"svm_sensit": (100, 98528, 50), "svm_cifar10": (3072, 60000, 200),
+              "svm_rnaseq": (20531, 801, 200)}
+
+
+def compare_svm(nys, args):
+    """The paper's SVM comparison (section 5.2) on the dual linear SVM in form
+    (P~) with synthetic dense features: Nys-IP-PMM, CG-IP-PMM, Chol-IP-PMM."""
+    import torch
+    from instances import svm_instance
+    d, n, ell = SVM_SHAPES[args.workload]
+    S = svm_instance(d, n, seed=args.seed, device="cuda", dtype=torch.float32)
+    A = S["A"]
+    A_lo = A.to(torch.bfloat16)
+    box = (S["vtype"], S["u"])
+    extra = dict(verbose=args.verbose, max_iter=args.max_iter)
+    nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=TOL, seed=args.seed, sketch_dtype="bf16",
+                      A_lo=A_lo, **extra)
+    torch.cuda.synchronize()
+    for name, pre in (("Nys-IP-PMM", "nystrom"), ("Chol-IP-PMM", "pchol"), ("CG-IP-PMM", "none")):
+        log(f"{args.workload}: {name}")
+        t0 = time.perf_counter()
+        try:
+            x, y, z, w, s, info = nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=TOL,
+                                                    seed=args.seed, sketch_dtype="bf16",
+                                                    A_lo=A_lo if pre == "nystrom" else None, precond=pre, **extra)
+        except nys.NysError as e:          # e.g. the iteration limit: report it
+            print(json.dumps({"solver": name, "workload": args.workload, "error": str(e)}), flush=True)
+            continue
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        rec = {"solver": name, "workload": args.workload, "d": d, "n": n, "ell": ell, "seconds": round(t, 3),
+               "status": info.status, "ipm_iters": info.iters, "pcg_iters": info.pcg_iters_total,
+               "kkt_rel": info.kkt_rel,
+               "time_split_ms": {"precond": round(info.t_sketch_ms, 1), "pcg": round(info.t_pcg_ms, 1),
+                                 "other": round(info.t_other_ms, 1)}}
+        print(json.dumps(rec), flush=True)
+
+
 def compare(nys, inst, args):
     """The paper's comparison (Nys-IP-PMM against Chol-IP-PMM and CG-IP-PMM,
     section 5): same instance, same tolerance, same sketch/pivot count ell;
@@ -236,12 +276,17 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-loop", type=int, default=0)
     ap.add_argument("--compare", action="store_true")
+    ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"))
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DB", "WRITE_DB"))
     ap.add_argument("--command", default="")
     ap.add_argument("--out", default="")
     args = ap.parse_args()
+    if args.compare and args.workload in SVM_SHAPES:
+        import paper_2404_14524_amd as nys
+        compare_svm(nys, args)
+        return
     if args.summarize_trace or args.summarize_pmc:
         from instances import CONFIGS
         cfg = CONFIGS[args.workload]

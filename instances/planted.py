@@ -179,21 +179,31 @@ def random_feasible_instance(m: int, n: int, seed: int, q_lo: float = 0.1,
     return dict(A=A, b=b, c=c, q=q)
 
 
-def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 1.0,
+def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 2.0, decay: float = 1.5,
                  device: str | torch.device = "cpu", dtype=torch.float64) -> dict:
     """Dual linear SVM in the box-constrained form (P~) (the paper's SVM
     formulation): x = [v; p], Q = diag(1_d, 0_n), A = [[I_d, -X diag(y)],
     [0, y^T]], b = 0, c = [0_d; -1_n] (the objective 1/2 v^T v - sum p), v
-    free, 0 <= p <= tau.  Synthetic dense features: two classes with means
-    +-sep/sqrt(d) in every coordinate plus N(0, 1) noise, labels +-1 in equal
-    numbers (a seeded permutation).  Returns A (dtype), b, c, q, u (float64),
-    vtype (int8), labels."""
+    free, 0 <= p <= tau.  Synthetic dense features standing in for the paper's
+    datasets: latent coordinate i has variance i^-decay (a power-law covariance
+    spectrum, as in image or expression data) and the class label shifts the
+    first min(10, d) latent coordinates by +-sep/sqrt(min(10, d)); the features
+    are a dense random mixing M (d x d, N(0, 1/d) entries) of the latent
+    coordinates, so the dominant directions are not aligned with the feature
+    axes; labels +-1 in equal numbers (a seeded permutation).  Returns A
+    (dtype), b, c, q, u (float64), vtype (int8), labels."""
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     f64 = torch.float64
     yl = torch.ones(n, dtype=f64, device=device)
     yl[torch.randperm(n, generator=g, device=device)[: n // 2]] = -1.0
-    X = torch.randn((d, n), generator=g, dtype=f64, device=device) + (sep / d ** 0.5) * yl[None, :]
+    sd = torch.arange(1, d + 1, dtype=f64, device=device) ** (-0.5 * decay)
+    L = torch.randn((d, n), generator=g, dtype=f64, device=device) * sd[:, None]
+    k = min(10, d)
+    L[:k] += (sep / k ** 0.5) * yl[None, :]
+    M = torch.randn((d, d), generator=g, dtype=f64, device=device) / d ** 0.5
+    X = M @ L
+    del L, M
     A = torch.zeros((d + 1, d + n), dtype=f64, device=device)
     A[:d, :d] = torch.eye(d, dtype=f64, device=device)
     A[:d, d:] = -X * yl[None, :]

@@ -16,6 +16,7 @@ boxqp      IP-PMM with free, non-negative and box-constrained variables
 pcg        textbook preconditioned conjugate gradients
 ippmm      the IP-PMM outer loop with an exact (dense Cholesky) inner solve
 bruteforce active-set enumeration of the KKT conditions of tiny problems
+adaptive   sketch size from the effective dimension; reuse rule
 adjoint    gradient of a loss of the solution through the KKT conditions
 lowprec    round-to-nearest-even emulation of BF16 / FP32 storage
 philox     the Philox4x32-10 counter-based generator and Box-Muller normals

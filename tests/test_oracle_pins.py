@@ -513,3 +513,89 @@ def test_box_oracle_solves_the_svm_form():
     bias = float(np.median(yl[sv] - X[:, sv].T @ v)) if sv.any() else 0.0
     acc = float(np.mean(np.sign(X.T @ v + bias) == yl))
     assert acc >= 0.9, acc
+
+
+# ---------------------------------------------------------------- sketch size and reuse
+
+from oracle import adaptive  # noqa: E402
+
+
+def test_deff_closed_forms_and_limits():
+    """eq. effective-dim: c times a rank-r projector gives r c/(c+mu); mu -> 0
+    counts the rank, mu -> inf gives tr(N)/mu."""
+    m, r, cval = 50, 7, 3.5
+    rng = np.random.default_rng(11)
+    Q, _ = np.linalg.qr(rng.standard_normal((m, r)))
+    N = cval * (Q @ Q.T)
+    for mu in (1e-3, 0.7, 3.5, 40.0):
+        # the m - r zero eigenvalues come out at about eps c and add eps c / mu each
+        tol = 10 * m * np.finfo(float).eps * cval / mu
+        assert abs(adaptive.d_eff_matrix(N, mu) - r * cval / (cval + mu)) <= tol
+    N2 = _lowrank_psd(m, 12, 12, decay=1.0)
+    # mu far below the smallest non-zero eigenvalue (1/12), far above eps |N|
+    assert abs(adaptive.d_eff_matrix(N2, 1e-8) - 12) <= 1e-5
+    big = 1e9
+    assert abs(big * adaptive.d_eff_matrix(N2, big) - np.trace(N2)) <= 1e-6 * np.trace(N2)
+
+
+@pytest.mark.parametrize("mu", [1e-4, 1e-2, 1.0])
+def test_deff_estimate_is_a_lower_bound_and_exact_at_full_rank(mu):
+    """N_hat <= N (Loewner), so the estimate from the Nystrom eigenvalues never
+    exceeds d_eff(N, mu); it grows with nested test matrices and equals
+    d_eff once the sketch covers the rank."""
+    m, r = 90, 30
+    N = _lowrank_psd(m, r, 13, decay=1.5)
+    de = adaptive.d_eff_matrix(N, mu)
+    Om = np.random.default_rng(14).standard_normal((m, 40))
+    prev = -1.0
+    for ell in (5, 10, 20, 29):
+        U, lam, _ = nystrom.nystrom(lambda V: N @ V, nystrom.orthonormalize(Om[:, :ell]))
+        dh = adaptive.d_eff_estimate(lam, mu)
+        assert dh <= de + 1e-10
+        assert dh >= prev - 1e-10
+        prev = dh
+    U, lam, _ = nystrom.nystrom(lambda V: N @ V, nystrom.orthonormalize(Om[:, :35]))
+    assert abs(adaptive.d_eff_estimate(lam, mu) - de) <= 1e-8 * max(de, 1.0)
+
+
+def test_theorem_sketch_size_values():
+    """eq. main-thm-sketch-size at points evaluated by hand (natural log):
+    d=0, k=0: 256 ln 32; d=100, k=0: 8 (10 + sqrt(32 ln 32))^2;
+    d=0, k=3: 256 ln 80."""
+    assert abs(adaptive.theorem_sketch_size(0.0, 0) - 887.2283911) < 1e-6
+    assert abs(adaptive.theorem_sketch_size(100.0, 0) - 3372.2004537) < 1e-6
+    assert abs(adaptive.theorem_sketch_size(0.0, 3) - 1121.7988185) < 1e-6
+    assert adaptive.theorem_sketch_size(5.0, 4) > adaptive.theorem_sketch_size(5.0, 3)
+    assert adaptive.theorem_sketch_size(6.0, 3) > adaptive.theorem_sketch_size(5.0, 3)
+
+
+def test_sketch_size_rule_cases():
+    F, D, T = adaptive.RULE_FIXED, adaptive.RULE_DEFF, adaptive.RULE_THEOREM
+    rule = adaptive.sketch_size_rule
+    # fixed: the previous size
+    assert rule(F, 123.0, 5.0, 1.0, 3, 77, 8, 500, 2.0) == 77
+    # ceil(2 * 10.2) = 21, sketch not saturated (lambda_hat_ell <= mu)
+    assert rule(D, 10.2, 0.5, 1.0, 3, 40, 8, 500, 2.0) == 21
+    # exact integer stays: 2 * 10 = 20
+    assert rule(D, 10.0, 0.5, 1.0, 3, 40, 8, 500, 2.0) == 20
+    # lower clamp
+    assert rule(D, 1.0, 0.5, 1.0, 0, 40, 8, 500, 2.0) == 8
+    # saturated: max(ceil(100), 2 * 60) = 120, then the upper clamp
+    assert rule(D, 50.0, 2.0, 1.0, 3, 60, 8, 500, 2.0) == 120
+    assert rule(D, 50.0, 2.0, 1.0, 3, 60, 8, 100, 2.0) == 100
+    # lambda_hat_ell == mu is not saturated
+    assert rule(D, 50.0, 1.0, 1.0, 3, 60, 8, 500, 2.0) == 100
+    # theorem: ceil(887.228...) = 888, clamped or not
+    assert rule(T, 0.0, 0.0, 1.0, 0, 60, 8, 2000, 2.0) == 888
+    assert rule(T, 0.0, 0.0, 1.0, 0, 60, 8, 500, 2.0) == 500
+    assert rule(T, 100.0, 0.0, 1.0, 0, 60, 8, 5000, 2.0) == 3373
+
+
+def test_rebuild_due_cases():
+    due = adaptive.rebuild_due
+    assert due(0, -1, 0, 0, 3, 1.5)                  # nothing built yet
+    assert due(5, 4, 100, 10, 0, 1.5)                # reuse off: every iteration
+    assert not due(5, 4, 15, 10, 3, 1.5)             # age 1, 15 <= 1.5 * 10
+    assert due(5, 4, 16, 10, 3, 1.5)                 # 16 > 15
+    assert due(7, 4, 10, 10, 3, 1.5)                 # age 3 reaches the maximum
+    assert not due(6, 4, 10, 10, 3, 1.5)

@@ -283,6 +283,41 @@ typedef struct {
                                finite there), or NULL when vtype is NULL       */
 } nys_qp;
 
+/* Sketch size per IP-PMM iteration (options ell_rule; section "Convergence
+   analysis of Nys-IP-PMM": the main theorem asks for ell_k of order
+   d_eff(N_k, mu_k), eq. main-thm-sketch-size, with d_eff of eq. effective-dim).
+   d_eff(N_k, mu_k) is estimated from the eigenvalues lambda_hat (descending)
+   of the most recent Nystrom approximation at the current mu_k:
+   d_hat = sum_i lambda_hat_i / (lambda_hat_i + mu_k) (a lower estimate: the
+   Nystrom approximation lies below N in the Loewner order).
+     NYS_ELL_FIXED    ell_k = ell (the paper's experiments).
+     NYS_ELL_DEFF     target = ceil(c_ell d_hat); when lambda_hat_ell > mu_k
+                      also target >= 2 ell_prev (that sketch saw no eigenvalue
+                      below mu_k); ell_k = min(ell_max, max(ell_min, target)).
+     NYS_ELL_THEOREM  target = ceil(8 (sqrt(d_hat) + sqrt(32 ln(16 (k+2))))^2),
+                      clamped the same way (the bound itself is >= 887).
+   The first iteration's d_hat comes from the initial point's sketch of A A^T. */
+enum { NYS_ELL_FIXED = 0, NYS_ELL_DEFF = 1, NYS_ELL_THEOREM = 2 };
+
+/* Fields of one record of the per-iteration trace (nys_ipm_opts.trace), all
+   stored as double: */
+enum {
+  NYS_TR_K = 0,        /* IP-PMM iteration                                    */
+  NYS_TR_MU,           /* mu_k                                                */
+  NYS_TR_DELTA,        /* delta_k (= rho_k)                                   */
+  NYS_TR_ELL,          /* size of the preconditioner used at k (0: plain CG)  */
+  NYS_TR_BUILT,        /* 1 when the preconditioner was built at k, else 0    */
+  NYS_TR_DHAT,         /* d_hat of that Nystrom preconditioner at mu_k (NaN
+                          for the other preconditioners)                      */
+  NYS_TR_LAMLAST,      /* its smallest eigenvalue lambda_hat_ell (NaN likewise) */
+  NYS_TR_PCG,          /* PCG iterations at k, predictor plus corrector       */
+  NYS_TR_RULE_DHAT,    /* inputs of the sketch-size rule when it chose ell at k:
+                          d_hat and lambda_hat_ell of the previous Nystrom
+                          preconditioner at mu_k (NaN when no rule ran)       */
+  NYS_TR_RULE_LAMLAST,
+  NYS_TRACE_FIELDS
+};
+
 typedef struct {
   double tol;               /* max(rp_rel, rd_rel, mu) target; <= 0: 1e-6      */
   int32_t max_iter;         /* IP-PMM iterations; <= 0: 100                     */
@@ -294,6 +329,27 @@ typedef struct {
   int32_t verbose;          /* 1: one line per iteration on stderr              */
   int32_t no_transposed_copy; /* 1: never copy A^T into the workspace         */
   int32_t precond;          /* NYS_PRECOND_*: the inner solver's preconditioner */
+  /* sketch size per iteration (NYS_ELL_*; anything but FIXED needs the
+     Nystrom preconditioner).  ell is the initial size.                        */
+  int32_t ell_rule;
+  int32_t ell_min;          /* lower clamp; <= 0: min(8, ell)                    */
+  int32_t ell_max;          /* upper clamp, <= m; <= 0: min(m, 4 ell).  The
+                               workspace holds an m x ell_max basis.            */
+  double c_ell;             /* factor of NYS_ELL_DEFF; <= 0: 2                   */
+  /* reuse of the preconditioner across iterations (the paper names it as a
+     further improvement without a rule; this one is ours): 0 builds it anew at
+     every iteration.  a > 0 builds it at the first iteration and afterwards at
+     iteration k only when k - k_build >= a, or when the PCG iterations of
+     iteration k-1 exceed reuse_growth times those of iteration k_build; a
+     kept Nystrom preconditioner is applied with the current delta_k, a kept
+     partial Cholesky factor as built.                                         */
+  int32_t reuse_max_age;
+  double reuse_growth;      /* <= 0: 1.5                                         */
+  double* trace;            /* host, caller-owned: NULL, or trace_len records of
+                               NYS_TRACE_FIELDS doubles, one per IP-PMM
+                               iteration that reaches the Newton solve (later
+                               iterations are not recorded)                    */
+  int32_t trace_len;
 } nys_ipm_opts;
 
 typedef struct {
@@ -301,6 +357,10 @@ typedef struct {
   double kkt_rel, rp_rel, rd_rel, mu, rho, delta;
   double t_sketch_ms, t_pcg_ms, t_other_ms;
   double ru_rel;            /* ||u_J - x_J - w_J|| / (1 + ||u_J||) (box variables) */
+  double deff_last;         /* d_hat of the last Nystrom preconditioner at its
+                               build iteration's mu (NaN otherwise)             */
+  int32_t builds;           /* preconditioners built in the IP-PMM iterations  */
+  int32_t ell_last;         /* size of the last one                            */
 } nys_ipm_info;
 
 /* Nys-IP-PMM (Algorithm 4 with the predictor-corrector of Algorithm 6 and the
@@ -344,11 +404,35 @@ int ipm_solve_box(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, doub
    with leading dimension n.  Returns the PCG status (NYS_MAXIT = the adjoint
    solve did not reach its tolerance; gradients from the last iterate).
    Problems with free or box-constrained variables (qp->vtype set) are
-   rejected with NYS_EINVAL.  Synchronises. */
+   rejected with NYS_EINVAL.  One sketch of size opts->ell; the sketch-size
+   rule, reuse and trace fields of opts are not used.  Synchronises. */
 int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts, const double* x,
                 const double* y, const double* z, double rho, double delta, const double* g,
                 double* grad_c, double* grad_b, double* grad_q, double* grad_A,
                 nys_pcg_info* info);
+
+/* The estimate d_hat = sum_i lambda[i] / (lambda[i] + mu) of the effective
+   dimension d_eff(N, mu) (eq. effective-dim) from the ell eigenvalues lambda
+   (device, FP64, >= 0) of a Nystrom approximation of N; *out_host receives it.
+   Needs 1 <= ell, mu > 0, lambda and out_host non-NULL.  Synchronises. */
+int nys_deff_estimate(nys_handle h, const double* lambda, int32_t ell, double mu, double* out_host);
+
+/* The sketch size of the preconditioner built at IP-PMM iteration k under rule
+   (NYS_ELL_*, defined above), from d_hat, the previous preconditioner's
+   smallest eigenvalue lam_last, mu_k, its size ell_prev, the clamps
+   1 <= ell_min <= ell_max and c_ell > 0.  Host only, no handle.  Returns the
+   size, or NYS_EINVAL for a bad rule or bad clamps; a d_hat that is NaN or
+   infinite gives ell_max. */
+int nys_sketch_size_rule(int32_t rule, double d_hat, double lam_last, double mu, int32_t k,
+                         int32_t ell_prev, int32_t ell_min, int32_t ell_max, double c_ell);
+
+/* The reuse rule of nys_ipm_opts.reuse_max_age: 1 when the preconditioner is
+   built anew at IP-PMM iteration k, else 0.  k_build < 0: none built yet (1);
+   max_age <= 0: no reuse (1); otherwise 1 when k - k_build >= max_age or
+   pcg_prev > growth * pcg_ref (the PCG iterations of iterations k-1 and
+   k_build).  Host only, no handle. */
+int nys_precond_rebuild_due(int32_t k, int32_t k_build, int32_t pcg_prev, int32_t pcg_ref,
+                            int32_t max_age, double growth);
 
 #ifdef __cplusplus
 }

@@ -373,6 +373,13 @@ struct Opts {
   int verbose = 0;
   bool transpose = true;
   int precond = NYS_PRECOND_NYSTROM;
+  int ell_rule = NYS_ELL_FIXED;
+  int ell_min = 0, ell_max = 0;
+  double c_ell = 2.0;
+  int reuse_age = 0;
+  double reuse_growth = 1.5;
+  double* trace = nullptr;
+  int trace_len = 0;
 };
 
 // Workspace-backed partial Cholesky preconditioner for the comparator runs.
@@ -403,7 +410,36 @@ Opts read_opts(const nys_ipm_opts* o) {
   r.verbose = o->verbose;
   r.transpose = o->no_transposed_copy == 0;
   r.precond = o->precond;
+  r.ell_rule = o->ell_rule;
+  r.ell_min = o->ell_min;
+  r.ell_max = o->ell_max;
+  if (o->c_ell > 0) r.c_ell = o->c_ell;
+  r.reuse_age = o->reuse_max_age;
+  if (o->reuse_growth > 0) r.reuse_growth = o->reuse_growth;
+  r.trace = o->trace;
+  r.trace_len = o->trace_len;
   return r;
+}
+
+struct DeffSum {      // sum_i lambda_i / (lambda_i + mu), and lambda[last]
+  const double* lam;
+  double mu;
+  int64_t last;
+  __device__ void operator()(int64_t j, double* a, double*) const {
+    const double l = fmax(lam[j], 0.0);
+    a[0] += l / (l + mu);
+    if (j == last) a[1] += lam[j];
+  }
+};
+
+// d_hat of eq. effective-dim from the Nystrom eigenvalues, and the smallest one
+int deff_pair(nys_handle h, const double* lam, int ell, double mu, double* dhat, double* lam_last) {
+  double* sc = h->dscal;
+  NYS_CHECK((map_reduce<2, 0>(h, ell, DeffSum{lam, mu, (int64_t)ell - 1}, sc + SC_RED0)));
+  NYS_CHECK(read_scalars(h, SC_RED0, 2));
+  *dhat = h->hscal[SC_RED0];
+  if (lam_last) *lam_last = h->hscal[SC_RED0 + 1];
+  return NYS_OK;
 }
 
 
@@ -425,6 +461,22 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   if (o.precond < NYS_PRECOND_NYSTROM || o.precond > NYS_PRECOND_PCHOL)
     return set_error(h, NYS_EINVAL, "ipm_solve: bad preconditioner kind %d", o.precond);
   if (o.sk == NYS_F64 && A->dtype != NYS_F64 && A->dtype != NYS_F32) return set_error(h, NYS_EINVAL, "ipm_solve: bad A");
+  if (o.ell_rule < NYS_ELL_FIXED || o.ell_rule > NYS_ELL_THEOREM)
+    return set_error(h, NYS_EINVAL, "ipm_solve: bad ell_rule %d", o.ell_rule);
+  if (o.ell_rule != NYS_ELL_FIXED && o.precond != NYS_PRECOND_NYSTROM)
+    return set_error(h, NYS_EINVAL, "ipm_solve: a sketch-size rule needs the Nystrom preconditioner");
+  if (o.reuse_age < 0) return set_error(h, NYS_EINVAL, "ipm_solve: reuse_max_age < 0");
+  if (o.trace_len < 0 || (o.trace_len > 0 && !o.trace)) return set_error(h, NYS_EINVAL, "ipm_solve: bad trace buffer");
+  if (!o.trace) o.trace_len = 0;
+  // sizes the basis may take: ell alone, or [ell_min, ell_max] under a rule
+  int ell_cap = o.ell;
+  if (o.ell_rule != NYS_ELL_FIXED) {
+    if (o.ell_min <= 0) o.ell_min = std::min(8, o.ell);
+    if (o.ell_max <= 0) o.ell_max = (int)std::min<int64_t>(m, 4 * (int64_t)o.ell);
+    if (o.ell_min > o.ell_max || o.ell_max > m || o.ell > o.ell_max)
+      return set_error(h, NYS_EINVAL, "ipm_solve: need 1 <= ell_min <= ell_max <= m and ell <= ell_max");
+    ell_cap = o.ell_max;
+  }
   NYS_HIP(h, hipSetDevice(h->device));
   const auto t_start = clk::now();
   h->t_sketch = h->t_pcg = h->t_other = 0.0;
@@ -497,8 +549,8 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     dsc = bb + 7 * n;
   }
   double *U, *lamh;
-  NYS_CHECK(ws(h, WS_PCU, (size_t)m * o.ell, &U));
-  NYS_CHECK(ws(h, WS_PCL, (size_t)o.ell + 8, &lamh));
+  NYS_CHECK(ws(h, WS_PCU, (size_t)m * ell_cap, &U));
+  NYS_CHECK(ws(h, WS_PCL, (size_t)ell_cap + 8, &lamh));
   nys_matrix Alo{};
   const nys_matrix* Ask = A;
   nys_matrix Alot{};
@@ -515,11 +567,11 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
 
   // preconditioner construction for the current D and delta (Nystrom sketch,
   // partial Cholesky, or nothing for plain CG)
-  auto timed_sketch = [&](const double* d, uint64_t ctr, double dlt) -> int {
+  auto timed_sketch = [&](const double* d, uint64_t ctr, double dlt, int ell) -> int {
     const auto t0 = clk::now();
     double nu = 0;
     if (o.precond == NYS_PRECOND_NYSTROM)
-      NYS_CHECK(ipm_sketch(h, Ask, d, o.ell, o.seed, ctr, o.sk, o.c_nu, U, lamh, &nu));
+      NYS_CHECK(ipm_sketch(h, Ask, d, ell, o.seed, ctr, o.sk, o.c_nu, U, lamh, &nu));
     else if (o.precond == NYS_PRECOND_PCHOL)
       NYS_CHECK(pchol_build(h, A, d, dlt, &pch));
     NYS_CHECK(sync(h));
@@ -536,7 +588,7 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   // ---- initial point
   {
     NYS_CHECK(fill(h, ones, n, 1.0));
-    NYS_CHECK(timed_sketch(ones, CTR_INIT, INIT_REG));
+    NYS_CHECK(timed_sketch(ones, CTR_INIT, INIT_REG, o.ell));
     nys_pcg_opts ip = o.pcg;
     ip.rtol = 1e-10;
     ip.atol = 0.0;
@@ -601,6 +653,12 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   double rho = REG0, delta = REG0;
   nys_ipm_info inf{};
   int status = NYS_MAXIT;
+  // preconditioner in use: its size, build iteration, the PCG iterations of
+  // that iteration and of the previous one, and its d_hat and smallest
+  // eigenvalue at the current mu (Nystrom only)
+  const bool nys_pc = o.precond == NYS_PRECOND_NYSTROM;
+  int ell_cur = o.ell, k_build = -1, pcg_ref = 0, pcg_prev = 0, builds = 0;
+  double dhat = NAN, lam_last = NAN, deff_last = NAN;
   int k = 0;
   for (k = 0;; ++k) {
     // residuals and stopping test
@@ -635,8 +693,8 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     inf.ru_rel = ru_rel;
     inf.mu = mu;
     if (o.verbose)
-      std::fprintf(stderr, "[nysipm] k=%d rp=%.2e rd=%.2e mu=%.2e rho=%.2e pcg_total=%d t=%.1fms\n", k,
-                   rp_rel, rd_rel, mu, rho, pcg_total, ms_since(t_start));
+      std::fprintf(stderr, "[nysipm] k=%d rp=%.2e rd=%.2e mu=%.2e rho=%.2e pcg_total=%d t=%.1fms ell=%d\n", k,
+                   rp_rel, rd_rel, mu, rho, pcg_total, ms_since(t_start), ell_cur);
     if (kkt <= o.tol) {
       status = NYS_OK;
       break;
@@ -644,7 +702,26 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     if (k >= o.max_iter) break;
 
     NYS_CHECK(map_reduce<0, 0>(h, n, Scaling{D, qp->q, x, z, rho, vt, w, s}, nullptr));
-    NYS_CHECK(timed_sketch(D, (uint64_t)k, delta));
+    const int built = nys_precond_rebuild_due(k, k_build, pcg_prev, pcg_ref, o.reuse_age, o.reuse_growth);
+    double rule_dhat = NAN, rule_lam = NAN;
+    if (built) {
+      // the size from the most recent Nystrom eigenvalues (the initial point's
+      // sketch at k = 0) taken at the current mu
+      if (o.ell_rule != NYS_ELL_FIXED) {
+        NYS_CHECK(deff_pair(h, lamh, ell_cur, mu, &rule_dhat, &rule_lam));
+        ell_cur = nys_sketch_size_rule(o.ell_rule, rule_dhat, rule_lam, mu, k, ell_cur, o.ell_min, o.ell_max,
+                                       o.c_ell);
+        if (ell_cur < 1) return set_error(h, NYS_EINVAL, "ipm_solve: sketch-size rule failed");
+      }
+      NYS_CHECK(timed_sketch(D, (uint64_t)k, delta, ell_cur));
+      k_build = k;
+      if (o.precond != NYS_PRECOND_NONE) ++builds;
+    }
+    if (nys_pc && (built || o.trace_len > k)) {
+      NYS_CHECK(deff_pair(h, lamh, ell_cur, mu, &dhat, &lam_last));
+      if (built) deff_last = dhat;
+    }
+    const int pcg_before = pcg_total;
 
     // predictor
     NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho, vt, Rws, Ru, qp->u, w, s}, nullptr));
@@ -657,8 +734,8 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     nys_pcg_info pi{};
     auto t0 = clk::now();
     const BoxNewton bxp = box ? BoxNewton{vt, w, s, Ru, Rws, dwp, dsp} : BoxNewton{};
-    int rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, o.ell, pchp, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp, &pi,
-                        bxp);
+    int rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, ell_cur, pchp, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp,
+                        &pi, bxp);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;
@@ -681,7 +758,7 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut, vt, Rws, dwp, dsp}, nullptr));
     t0 = clk::now();
     const BoxNewton bxc = box ? BoxNewton{vt, w, s, nullptr, Rws, dwc, dsc} : BoxNewton{};
-    rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, o.ell, pchp, nullptr, nullptr, Rxz, &o.pcg, tau, dxc, dyc,
+    rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, ell_cur, pchp, nullptr, nullptr, Rxz, &o.pcg, tau, dxc, dyc,
                     dzc, &pi, bxc);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
@@ -711,6 +788,22 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
       break;
     }
     const double mu_new = cnt > 0 ? h->hscal[SC_RED0] / cnt : 0.0;
+    const int pcg_k = pcg_total - pcg_before;
+    if (k < o.trace_len) {
+      double* t = o.trace + (size_t)k * NYS_TRACE_FIELDS;
+      t[NYS_TR_K] = k;
+      t[NYS_TR_MU] = mu;
+      t[NYS_TR_DELTA] = delta;
+      t[NYS_TR_ELL] = o.precond == NYS_PRECOND_NONE ? 0 : ell_cur;
+      t[NYS_TR_BUILT] = built && o.precond != NYS_PRECOND_NONE ? 1 : 0;
+      t[NYS_TR_DHAT] = nys_pc ? dhat : NAN;
+      t[NYS_TR_LAMLAST] = nys_pc ? lam_last : NAN;
+      t[NYS_TR_PCG] = pcg_k;
+      t[NYS_TR_RULE_DHAT] = rule_dhat;
+      t[NYS_TR_RULE_LAMLAST] = rule_lam;
+    }
+    if (k == k_build) pcg_ref = pcg_k;
+    pcg_prev = pcg_k;
     rho = delta = std::max(REG_FLOOR, std::min(rho, mu_new));
   }
   NYS_CHECK(sync(h));
@@ -724,6 +817,9 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   inf.t_sketch_ms = h->t_sketch;
   inf.t_pcg_ms = h->t_pcg;
   inf.t_other_ms = h->t_other;
+  inf.deff_last = deff_last;
+  inf.builds = builds;
+  inf.ell_last = o.precond == NYS_PRECOND_NONE ? 0 : ell_cur;
   if (info) *info = inf;
   if (status == NYS_MAXIT)
     set_error(h, NYS_MAXIT, "ipm_solve: %d iterations without reaching tol (KKT %.3e)", k, inf.kkt_rel);
@@ -820,4 +916,43 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   NYS_CHECK(sync(h));
   h->t_other = std::max(0.0, ms_since(t_start) - h->t_sketch - h->t_pcg);
   return rc;
+}
+
+extern "C" int nys_deff_estimate(nys_handle h, const double* lambda, int32_t ell, double mu, double* out_host) {
+  if (!h) return NYS_EINVAL;
+  if (!lambda || !out_host || ell < 1 || !(mu > 0) || !std::isfinite(mu))
+    return set_error(h, NYS_EINVAL, "nys_deff_estimate: need lambda, out_host, ell >= 1 and finite mu > 0");
+  NYS_HIP(h, hipSetDevice(h->device));
+  return deff_pair(h, lambda, ell, mu, out_host, nullptr);
+}
+
+extern "C" int nys_sketch_size_rule(int32_t rule, double d_hat, double lam_last, double mu, int32_t k,
+                                    int32_t ell_prev, int32_t ell_min, int32_t ell_max, double c_ell) {
+  if (ell_min < 1 || ell_min > ell_max) return NYS_EINVAL;
+  double target;
+  switch (rule) {
+    case NYS_ELL_FIXED:
+      return ell_prev;
+    case NYS_ELL_DEFF:
+      if (!(c_ell > 0)) return NYS_EINVAL;
+      target = std::ceil(c_ell * d_hat);
+      if (lam_last > mu) target = std::max(target, 2.0 * (double)ell_prev);
+      break;
+    case NYS_ELL_THEOREM: {
+      const double r = std::sqrt(d_hat) + std::sqrt(32.0 * std::log(16.0 * (double)(k + 2)));
+      target = std::ceil(8.0 * r * r);
+      break;
+    }
+    default:
+      return NYS_EINVAL;
+  }
+  if (!std::isfinite(target)) return ell_max;
+  return (int32_t)std::min((double)ell_max, std::max((double)ell_min, target));
+}
+
+extern "C" int nys_precond_rebuild_due(int32_t k, int32_t k_build, int32_t pcg_prev, int32_t pcg_ref,
+                                       int32_t max_age, double growth) {
+  if (k_build < 0 || max_age <= 0) return 1;
+  if (k - k_build >= max_age) return 1;
+  return (double)pcg_prev > growth * (double)pcg_ref ? 1 : 0;
 }

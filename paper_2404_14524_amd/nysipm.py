@@ -14,6 +14,7 @@ import threading
 from dataclasses import dataclass
 from typing import Optional
 
+import numpy as np
 import torch
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
@@ -65,7 +66,9 @@ class nys_ipm_opts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int32), ("ell", C.c_int32),
                 ("seed", C.c_uint64), ("sketch_dtype", C.c_int), ("c_nu", C.c_double),
                 ("pcg", nys_pcg_opts), ("verbose", C.c_int32), ("no_transposed_copy", C.c_int32),
-                ("precond", C.c_int32)]
+                ("precond", C.c_int32), ("ell_rule", C.c_int32), ("ell_min", C.c_int32),
+                ("ell_max", C.c_int32), ("c_ell", C.c_double), ("reuse_max_age", C.c_int32),
+                ("reuse_growth", C.c_double), ("trace", C.c_void_p), ("trace_len", C.c_int32)]
 
 
 class nys_ipm_info(C.Structure):
@@ -73,14 +76,16 @@ class nys_ipm_info(C.Structure):
                 ("kkt_rel", C.c_double), ("rp_rel", C.c_double), ("rd_rel", C.c_double),
                 ("mu", C.c_double), ("rho", C.c_double), ("delta", C.c_double),
                 ("t_sketch_ms", C.c_double), ("t_pcg_ms", C.c_double), ("t_other_ms", C.c_double),
-                ("ru_rel", C.c_double)]
+                ("ru_rel", C.c_double), ("deff_last", C.c_double), ("builds", C.c_int32),
+                ("ell_last", C.c_int32)]
 
 
 EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys_last_timing",
            "nys_profile_enable", "nys_profile_read", "nys_stream_read",
            "nys_normal_apply", "nys_transpose", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint",
-           "nys_pchol_build", "nys_pchol_apply", "nys_pcg_solve_pchol", "ipm_solve_box"]
+           "nys_pchol_build", "nys_pchol_apply", "nys_pcg_solve_pchol", "ipm_solve_box",
+           "nys_deff_estimate", "nys_sketch_size_rule", "nys_precond_rebuild_due"]
 
 _lib = None
 _lock = threading.Lock()
@@ -127,6 +132,9 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
                               C.POINTER(nys_ipm_info)],
             "ipm_adjoint": [vp, C.POINTER(nys_qp), C.POINTER(nys_ipm_opts), vp, vp, vp, dbl, dbl, vp,
                             vp, vp, vp, vp, C.POINTER(nys_pcg_info)],
+            "nys_deff_estimate": [vp, vp, i32, dbl, C.POINTER(dbl)],
+            "nys_sketch_size_rule": [i32, dbl, dbl, dbl, i32, i32, i32, i32, dbl],
+            "nys_precond_rebuild_due": [i32, i32, i32, i32, i32, dbl],
         }
         for name, args in sig.items():
             f = getattr(lib, name)
@@ -360,14 +368,55 @@ def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond
 
 
 PRECONDS = {"nystrom": 0, "none": 1, "pchol": 2}
+ELL_RULES = {"fixed": 0, "deff": 1, "theorem": 2}
+# fields of one record of the per-iteration trace (NYS_TR_*)
+TRACE_FIELDS = ("k", "mu", "delta", "ell", "built", "d_hat", "lam_last", "pcg", "rule_d_hat", "rule_lam_last")
 
 
 def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0, verbose=False,
               pcg_rtol=0.0, pcg_maxit=0, replace_every=0, poll_every=0,
-              transposed_copy=True, precond="nystrom") -> nys_ipm_opts:
+              transposed_copy=True, precond="nystrom", ell_rule="fixed", ell_min=0, ell_max=0,
+              c_ell=0.0, reuse_max_age=0, reuse_growth=0.0, trace=None) -> nys_ipm_opts:
+    """trace: None, or a C-contiguous float64 numpy array of shape
+    (L, len(TRACE_FIELDS)) that receives one record per IP-PMM iteration k < L."""
+    tp, tl = None, 0
+    if trace is not None:
+        if (not isinstance(trace, np.ndarray) or trace.dtype != np.float64 or trace.ndim != 2
+                or trace.shape[1] != len(TRACE_FIELDS) or not trace.flags.c_contiguous):
+            raise ValueError(f"trace: need a C-contiguous float64 numpy array of shape (L, {len(TRACE_FIELDS)})")
+        tp, tl = trace.ctypes.data, trace.shape[0]
     return nys_ipm_opts(tol, max_iter, ell, seed, _SK[sketch_dtype], c_nu,
                         _pcg_opts(pcg_rtol, 0.0, pcg_maxit, replace_every, poll_every), int(verbose),
-                        0 if transposed_copy else 1, PRECONDS[precond])
+                        0 if transposed_copy else 1, PRECONDS[precond], ELL_RULES[ell_rule], ell_min,
+                        ell_max, c_ell, reuse_max_age, reuse_growth, tp, tl)
+
+
+def nys_deff_estimate(lam: torch.Tensor, mu: float) -> float:
+    """sum_i lam_i / (lam_i + mu) over the Nystrom eigenvalues lam (device)."""
+    lib, h = _handle(lam.device)
+    _vec(lam, lam.numel(), "lam", lam.device)
+    out = C.c_double()
+    _check(lib, h, lib.nys_deff_estimate(h, _ptr(lam), lam.numel(), float(mu), C.byref(out)))
+    return out.value
+
+
+def nys_sketch_size_rule(rule: str, d_hat: float, lam_last: float, mu: float, k: int, ell_prev: int,
+                         ell_min: int, ell_max: int, c_ell: float = 2.0) -> int:
+    """Sketch size for the preconditioner built at IP-PMM iteration k (host)."""
+    lib = load_library()
+    r = lib.nys_sketch_size_rule(ELL_RULES[rule], float(d_hat), float(lam_last), float(mu), int(k),
+                                 int(ell_prev), int(ell_min), int(ell_max), float(c_ell))
+    if r < 0:
+        raise NysError(r, "nys_sketch_size_rule: bad rule or clamps")
+    return r
+
+
+def nys_precond_rebuild_due(k: int, k_build: int, pcg_prev: int, pcg_ref: int, max_age: int,
+                            growth: float) -> bool:
+    """The reuse rule: True when the preconditioner is built anew at iteration k (host)."""
+    lib = load_library()
+    return bool(lib.nys_precond_rebuild_due(int(k), int(k_build), int(pcg_prev), int(pcg_ref), int(max_age),
+                                            float(growth)))
 
 
 def _qp(A, b, c, q, A_lo, A_t=None, vtype=None, u=None):

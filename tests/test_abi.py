@@ -56,3 +56,59 @@ def test_create_rejects_bad_device_without_gpu_work():
     h = ctypes.c_void_p()
     assert lib.nys_create(ctypes.byref(h), -1, None) == nysipm.NYS_EINVAL
     assert lib.nys_create(None, 0, None) == nysipm.NYS_EINVAL
+
+
+# ---------------------------------------------------------------- host logic of the IP-PMM driver
+
+def _rule_cases(seed, count):
+    import numpy as np
+    rng = np.random.default_rng(seed)
+    for _ in range(count):
+        rule = int(rng.integers(0, 3))
+        ell_min = int(rng.integers(1, 60))
+        ell_max = int(rng.integers(ell_min, 6000))
+        if rng.random() < 0.3:                       # exact products c * d_hat
+            d_hat = float(rng.integers(0, 3000)) / 2.0
+        else:
+            d_hat = float(np.exp(rng.uniform(-3, np.log(5000))))
+        mu = float(np.exp(rng.uniform(-20, 2)))
+        r = rng.random()
+        lam_last = mu if r < 0.1 else float(mu * np.exp(rng.uniform(-5, 5)))
+        c_ell = float(rng.choice([0.5, 1.0, 2.0, 3.7]))
+        yield (rule, d_hat, lam_last, mu, int(rng.integers(0, 80)), int(rng.integers(1, 3000)), ell_min,
+               ell_max, c_ell)
+
+
+def test_sketch_size_rule_matches_oracle():
+    """nys_sketch_size_rule against the oracle's rule, bit-exact, on seeded
+    inputs that include exact products c_ell d_hat and lambda_hat_ell = mu."""
+    from oracle import adaptive
+    from paper_2404_14524_amd import nysipm
+    lib = nysipm.load_library()
+    for case in _rule_cases(21, 4000):
+        got = lib.nys_sketch_size_rule(*case)
+        assert got == adaptive.sketch_size_rule(*case), case
+    # documented edge behaviour: non-finite d_hat gives ell_max; bad clamps / rule fail
+    assert lib.nys_sketch_size_rule(1, float("nan"), 1.0, 1.0, 0, 10, 4, 77, 2.0) == 77
+    assert lib.nys_sketch_size_rule(1, float("inf"), 1.0, 1.0, 0, 10, 4, 77, 2.0) == 77
+    assert lib.nys_sketch_size_rule(1, 3.0, 1.0, 1.0, 0, 10, 9, 8, 2.0) == nysipm.NYS_EINVAL
+    assert lib.nys_sketch_size_rule(7, 3.0, 1.0, 1.0, 0, 10, 1, 8, 2.0) == nysipm.NYS_EINVAL
+    assert lib.nys_sketch_size_rule(1, 3.0, 1.0, 1.0, 0, 10, 1, 8, 0.0) == nysipm.NYS_EINVAL
+
+
+def test_rebuild_rule_matches_oracle():
+    import numpy as np
+    from oracle import adaptive
+    from paper_2404_14524_amd import nysipm
+    lib = nysipm.load_library()
+    rng = np.random.default_rng(22)
+    for _ in range(4000):
+        k = int(rng.integers(0, 60))
+        k_build = int(rng.integers(-1, k + 1))
+        pcg_ref = int(rng.integers(0, 500))
+        pcg_prev = int(pcg_ref * rng.choice([0.5, 1.0, 1.5, 2.0]) + rng.integers(-2, 3)) if rng.random() < 0.5 \
+            else int(rng.integers(0, 1000))
+        max_age = int(rng.integers(-1, 6))
+        growth = float(rng.choice([1.0, 1.5, 2.0, 1.25]))
+        case = (k, k_build, pcg_prev, pcg_ref, max_age, growth)
+        assert bool(lib.nys_precond_rebuild_due(*case)) == adaptive.rebuild_due(*case), case

@@ -559,3 +559,115 @@ def test_ipm_solve_box_rejects_bad_kinds(nys):
     ub[j] = 0.0
     with pytest.raises(nys.NysError):
         nys.ipm_solve_box(_t(A), _t(b), _t(c), _t(q), torch.as_tensor(vt, device=DEV), _t(ub), ell=5)
+
+
+# ------------------------------------------------------------------ sketch size from d_eff; reuse
+
+@pytest.mark.parametrize("ell", [1, 7, 200, 1000])
+def test_deff_estimate_parity(nys, ell):
+    """nys_deff_estimate against the oracle's estimate (eq. effective-dim over
+    the Nystrom eigenvalues), zero eigenvalues included."""
+    from oracle import adaptive
+    print(f"deff_estimate ell={ell}", flush=True)
+    rng = np.random.default_rng(ell)
+    lam = np.sort(np.exp(rng.uniform(-12, 6, ell)))[::-1].copy()
+    if ell > 3:
+        lam[-2:] = 0.0
+    for mu in (1e-9, 1e-3, 1.0, 1e4):
+        got = nys.nys_deff_estimate(_t(lam), mu)
+        ref = adaptive.d_eff_estimate(lam, mu)
+        assert abs(got - ref) <= 1e-13 * max(ref, 1.0), (mu, got, ref)
+
+
+def _check_trace(nys, tr, info, rule, ell0, ell_min, ell_max, c_ell, max_age, growth, nystrom=True):
+    """The driver's decisions follow its (CPU-pinned) rules on what it observed:
+    a build exactly when the reuse rule says so, the size the sketch-size rule
+    gives for the recorded inputs, the size kept between builds, and
+    0 <= d_hat <= ell."""
+    K = info.iters
+    tr = tr[:K]
+    assert np.array_equal(tr[:, 0], np.arange(K))
+    built = tr[:, 4] == 1.0
+    ells = tr[:, 3].astype(int)
+    assert built[0] and int(built.sum()) == info.builds and ells[-1] == info.ell_last
+    k_build, pcg_ref, pcg_prev, ell_prev = -1, 0, 0, ell0
+    for k in range(K):
+        assert nys.nys_precond_rebuild_due(k, k_build, pcg_prev, pcg_ref, max_age, growth) == built[k], k
+        if built[k]:
+            if rule == "fixed":
+                assert ells[k] == ell0
+            else:
+                exp = nys.nys_sketch_size_rule(rule, tr[k, 8], tr[k, 9], tr[k, 1], k, ell_prev, ell_min, ell_max,
+                                               c_ell)
+                assert ells[k] == exp, (k, ells[k], exp)
+            k_build, pcg_ref = k, int(tr[k, 7])
+        else:
+            assert ells[k] == ell_prev and np.isnan(tr[k, 8])
+        if nystrom:
+            assert 0.0 <= tr[k, 5] <= ells[k] + 1e-9
+        pcg_prev, ell_prev = int(tr[k, 7]), ells[k]
+    assert int(tr[:, 7].sum()) <= info.pcg_iters_total
+
+
+@pytest.mark.parametrize("rule,max_age,growth", [("deff", 0, 1.5), ("deff", 3, 1.5), ("theorem", 0, 1.5),
+                                                  ("fixed", 2, 1.5), ("fixed", 50, 1e9)])
+def test_ipm_solve_sketch_size_rule_and_reuse(nys, rule, max_age, growth):
+    """Sketch size from the d_eff estimate (and the main theorem's bound), and
+    reuse of the preconditioner: the planted optimum (the oracle's, pinned)
+    at KKT <= 1e-6, with decisions that follow the rules."""
+    print(f"ipm rule={rule} reuse={max_age}", flush=True)
+    inst = make_instance("lowrank_5000x20000", seed=3, m=500, n=2000, rank=40)
+    A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+    ell0, ell_min, ell_max, c_ell = 20, 8, 160, 2.0
+    tr = np.full((100, len(nys.TRACE_FIELDS)), -1.0)
+    x, y, z, info = nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=ell0, tol=1e-6, seed=2, ell_rule=rule,
+                                  ell_min=ell_min, ell_max=ell_max, c_ell=c_ell, reuse_max_age=max_age,
+                                  reuse_growth=growth, trace=tr)
+    assert info.status == 0, (info.kkt_rel, info.iters)
+    assert problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))["kkt"] <= 1e-6
+    xs = inst.x_star.numpy()
+    assert np.linalg.norm(_np(x) - xs) <= 1e-5 * np.linalg.norm(xs)
+    _check_trace(nys, tr, info, rule, ell0, ell_min, ell_max, c_ell, max_age, growth)
+    if max_age == 0:
+        assert info.builds == info.iters
+    if max_age == 50:                                  # one preconditioner for the whole solve
+        assert info.builds == 1
+    assert np.all(tr[info.iters:] == -1.0)           # nothing written past the last Newton solve
+
+
+def test_ipm_solve_reuse_with_partial_cholesky(nys):
+    print("ipm pchol reuse", flush=True)
+    inst = make_instance("gauss_200x500", seed=1)
+    A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+    tr = np.zeros((100, len(nys.TRACE_FIELDS)))
+    x, y, z, info = nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=20, tol=1e-6, seed=0, precond="pchol",
+                                  reuse_max_age=3, trace=tr)
+    assert info.status == 0
+    xs = inst.x_star.numpy()
+    assert np.linalg.norm(_np(x) - xs) <= 1e-5 * np.linalg.norm(xs)
+    _check_trace(nys, tr, info, "fixed", 20, 1, 20, 2.0, 3, 1.5, nystrom=False)
+    assert np.all(np.isnan(tr[:info.iters, 5]))       # no Nystrom estimate for this preconditioner
+
+
+def test_ipm_solve_defaults_unchanged_by_trace(nys):
+    """Fixed size, no reuse: the same iterates with and without a trace, one
+    build per iteration."""
+    inst = make_instance("gauss_200x500", seed=1)
+    A, b, c, q = (_t(inst.A.double().numpy()), _t(inst.b.numpy()), _t(inst.c.numpy()), _t(inst.q.numpy()))
+    x1, y1, z1, i1 = nys.ipm_solve(A, b, c, q, ell=20, tol=1e-6, seed=0)
+    tr = np.zeros((100, len(nys.TRACE_FIELDS)))
+    x2, y2, z2, i2 = nys.ipm_solve(A, b, c, q, ell=20, tol=1e-6, seed=0, trace=tr)
+    assert torch.equal(x1, x2) and torch.equal(y1, y2) and i1.pcg_iters_total == i2.pcg_iters_total
+    assert i2.builds == i2.iters and np.all(tr[:i2.iters, 3] == 20) and np.all(np.isnan(tr[:i2.iters, 8]))
+
+
+def test_ipm_solve_rejects_bad_rule_options(nys):
+    inst = make_instance("gauss_200x500", seed=1)
+    A, b, c, q = (_t(inst.A.double().numpy()), _t(inst.b.numpy()), _t(inst.c.numpy()), _t(inst.q.numpy()))
+    for kw in (dict(ell_rule="deff", precond="pchol"), dict(ell_rule="deff", ell_max=201),
+               dict(ell_rule="deff", ell_min=30, ell_max=25), dict(ell_rule="deff", ell_max=10),
+               dict(reuse_max_age=-1)):
+        with pytest.raises(nys.NysError):
+            nys.ipm_solve(A, b, c, q, ell=20, tol=1e-6, **kw)
+    with pytest.raises(ValueError):
+        nys.ipm_solve(A, b, c, q, ell=20, tol=1e-6, trace=np.zeros((10, 3)))

@@ -20,6 +20,9 @@ Modes:
   python bench.py --compare [--workload NAME]   # Nys-IP-PMM against the paper's
                                     # comparators (Chol-IP-PMM, CG-IP-PMM) on one
                                     # workload: one JSON line per solver
+  python bench.py --adaptive [--workload NAME]  # sketch size from the d_eff
+                                    # estimate and preconditioner reuse against
+                                    # the fixed size: one JSON line per variant
   python bench.py --kernel-loop R   # only R normal-equation applies (pass 1 on a
                                     # transposed copy, as in the solver), a plain
                                     # copy and read-stream kernels of known size
@@ -265,6 +268,48 @@ def compare(nys, inst, args):
         print(json.dumps(rec), flush=True)
 
 
+ADAPTIVE_VARIANTS = (
+    ("fixed", dict()),
+    ("deff", dict(ell_rule="deff")),
+    ("theorem", dict(ell_rule="theorem")),
+    ("reuse3", dict(reuse_max_age=3)),
+    ("deff+reuse3", dict(ell_rule="deff", reuse_max_age=3)),
+)
+
+
+def adaptive_compare(nys, inst, args):
+    """Sketch size from the d_eff estimate and preconditioner reuse against
+    the fixed sketch size, on one workload: same instance, tolerance and
+    initial size ell (the rules clamp to [min(8, ell), min(m, 4 ell)]); one
+    JSON line per variant with the per-iteration sizes and d_hat."""
+    import numpy as np
+    import torch
+    A = inst.A
+    A_lo = A.to(torch.bfloat16) if A.dtype == torch.float32 else None
+    sk = "bf16" if A_lo is not None else "f64"
+    A_t = nys.nys_transpose(A)
+    base = dict(ell=inst.ell, tol=TOL, seed=args.seed, sketch_dtype=sk, A_lo=A_lo, A_t=A_t,
+                max_iter=args.max_iter, verbose=args.verbose)
+    nys.ipm_solve(A, inst.b, inst.c, inst.q, **base)           # warm-up
+    torch.cuda.synchronize()
+    for name, kw in ADAPTIVE_VARIANTS:
+        tr = np.full((args.max_iter + 1, len(nys.TRACE_FIELDS)), np.nan)
+        t0 = time.perf_counter()
+        x, y, z, info = nys.ipm_solve(A, inst.b, inst.c, inst.q, trace=tr, **base, **kw)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        K = info.iters
+        xs = inst.x_star
+        rec = {"variant": name, "workload": args.workload, "seconds": round(t, 3), "status": info.status,
+               "ipm_iters": K, "pcg_iters": info.pcg_iters_total, "builds": info.builds, "kkt_rel": info.kkt_rel,
+               "x_rel_err_vs_planted": float(torch.linalg.norm(x - xs) / torch.linalg.norm(xs)),
+               "time_split_ms": {"precond": round(info.t_sketch_ms, 1), "pcg": round(info.t_pcg_ms, 1),
+                                 "other": round(info.t_other_ms, 1)},
+               "ell_k": [int(v) for v in tr[:K, 3]], "d_hat_k": [round(float(v), 1) for v in tr[:K, 5]],
+               "pcg_k": [int(v) for v in tr[:K, 7]]}
+        print(json.dumps(rec), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -276,6 +321,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-loop", type=int, default=0)
     ap.add_argument("--compare", action="store_true")
+    ap.add_argument("--adaptive", action="store_true")
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"))
@@ -321,6 +367,9 @@ def main():
 
     if args.compare:
         compare(nys, inst, args)
+        return
+    if args.adaptive:
+        adaptive_compare(nys, inst, args)
         return
 
     if args.kernel_loop:

@@ -216,3 +216,59 @@ def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 2
     vtype = torch.cat([torch.full((d,), 1, dtype=torch.int8, device=device),
                        torch.full((n,), 2, dtype=torch.int8, device=device)])
     return dict(A=A, b=b, c=c, q=q, u=u, vtype=vtype, labels=yl)
+
+
+def portfolio_instance(n: int = 80000, d: int = 50000, s: int = 100, seed: int = 0, gamma: float = 1.0,
+                       components: Optional[int] = None, device: str | torch.device = "cpu",
+                       dtype=torch.float64, with_parts: bool = False) -> dict:
+    """The factor-model portfolio problem (the paper's portfolio experiment)
+    min -r^T x + gamma x^T (F F^T + diag(Dg)) x  s.t.  M x <= u_p, 1^T x = 1,
+    x >= 0, in the form (P~) of its reformulation with y = F^T x free and a
+    slack t = u_p - M x >= 0, the objective divided by gamma:
+      variables [x (n, >= 0); y (s, free); t (d, >= 0)],
+      A = [[F^T, -I_s, 0], [M, 0, I_d], [1^T, 0, 0]]  ((s + d + 1) x (n + s + d)),
+      b = [0_s; u_p; 1], c = [-r / gamma; 0; 0], Q = diag(2 Dg, 2 I_s, 0_d).
+    Data: a true covariance Sigma = G diag(lam) G^T + sig2 I with G (n x R)
+    orthonormal, lam_i = i^-2 for i <= R/10 then decaying as i^-1/2 (rapid,
+    then slow decay), scaled so that the mean variance is 1 (sig2 = 0.1);
+    F = G_s diag(sqrt(lam_{1..s} + sig2)), the exact rank-s truncation of
+    Sigma, and Dg = diag(Sigma - F F^T) >= sig2 (1 - |G_{j,1..s}|^2); rows of M
+    ~ N(0, I); r ~ N(0, 1); u_p ~ U[0.05, 1] (x = 1/n is strictly feasible).
+    A holds the stored values (dtype); F and M of the returned parts are those
+    values promoted to FP64.  Returns A, b, c, q, u, vtype and, with
+    with_parts, F, Dg, M, u_p, r, gamma."""
+    g = torch.Generator(device=device)
+    g.manual_seed(int(seed))
+    f64 = torch.float64
+    R = components if components is not None else min(1000, max(s + 1, n // 2))
+    k0 = max(1, R // 10)
+    i = torch.arange(1, R + 1, dtype=f64, device=device)
+    lam = torch.where(i <= k0, i ** -2.0, (k0 ** -2.0) * (i / k0) ** -0.5)
+    sig2 = 0.1
+    lam = lam * (0.9 * n / lam.sum())
+    G = _orthonormal_columns(torch.randn((n, R), generator=g, dtype=f64, device=device))
+    F = G[:, :s] * torch.sqrt(lam[:s] + sig2)[None, :]
+    Dg = (G[:, s:] ** 2) @ lam[s:] + sig2 * (1.0 - (G[:, :s] ** 2).sum(dim=1))
+    del G
+    r = torch.randn(n, generator=g, dtype=f64, device=device)
+    u_p = 0.05 + 0.95 * torch.rand(d, generator=g, dtype=f64, device=device)
+    m, N = s + d + 1, n + s + d
+    A = torch.zeros((m, N), dtype=dtype, device=device)
+    A[:s, :n] = F.T.to(dtype)
+    A[:s, n:n + s] = -torch.eye(s, dtype=dtype, device=device)
+    step = _panel_rows(d, n)
+    for r0 in range(0, d, step):                    # M in row panels, drawn in the storage type
+        r1 = min(d, r0 + step)
+        A[s + r0:s + r1, :n] = torch.randn((r1 - r0, n), generator=g, dtype=f64 if dtype == f64 else torch.float32,
+                                           device=device).to(dtype)
+    A[s:s + d, n + s:] = torch.eye(d, dtype=dtype, device=device)
+    A[s + d, :n] = 1.0
+    b = torch.cat([torch.zeros(s, dtype=f64, device=device), u_p, torch.ones(1, dtype=f64, device=device)])
+    c = torch.cat([-r / gamma, torch.zeros(s + d, dtype=f64, device=device)])
+    q = torch.cat([2.0 * Dg, torch.full((s,), 2.0, dtype=f64, device=device), torch.zeros(d, dtype=f64, device=device)])
+    vtype = torch.cat([torch.zeros(n, dtype=torch.int8, device=device), torch.ones(s, dtype=torch.int8, device=device),
+                       torch.zeros(d, dtype=torch.int8, device=device)])
+    out = dict(A=A, b=b, c=c, q=q, u=torch.zeros(N, dtype=f64, device=device), vtype=vtype)
+    if with_parts:
+        out.update(F=A[:s, :n].T.to(f64), Dg=Dg, M=A[s:s + d, :n].to(f64), u_p=u_p, r=r, gamma=gamma)
+    return out

@@ -13,6 +13,7 @@ normal_eq  the regularised normal-equation operator and the Newton step
 nystrom    randomized Nystrom approximation and the Nystrom preconditioner
 pchol      partial Cholesky preconditioner (the Chol-IP-PMM comparator)
 boxqp      IP-PMM with free, non-negative and box-constrained variables
+portfolio  the factor-model portfolio problem in its original form; brute force
 pcg        textbook preconditioned conjugate gradients
 ippmm      the IP-PMM outer loop with an exact (dense Cholesky) inner solve
 bruteforce active-set enumeration of the KKT conditions of tiny problems

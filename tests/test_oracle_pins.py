@@ -599,3 +599,56 @@ def test_rebuild_due_cases():
     assert due(5, 4, 16, 10, 3, 1.5)                 # 16 > 15
     assert due(7, 4, 10, 10, 3, 1.5)                 # age 3 reaches the maximum
     assert not due(6, 4, 10, 10, 3, 1.5)
+
+
+# ---------------------------------------------------------------- portfolio problem
+
+from oracle import portfolio  # noqa: E402
+
+
+def _np_parts(P):
+    return {k: (v.numpy() if isinstance(v, torch.Tensor) else v) for k, v in P.items()}
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_portfolio_form_matches_bruteforce_of_the_original_problem(seed):
+    """The (P~) form built by the instances (y = F^T x free, slack t >= 0),
+    solved by the box-form IP-PMM oracle, gives the optimum of the original
+    portfolio problem found by active-set enumeration (which never uses that
+    form); y = F^T x and t = u - M x; the objectives agree after the 1/gamma
+    scaling."""
+    from oracle import boxqp
+    n, d, s = 6, 3, 2
+    P = _np_parts(_portfolio_tiny(n, d, s, seed))
+    ref = portfolio.bruteforce(P["r"], P["F"], P["Dg"], P["M"], P["u_p"], P["gamma"])
+    assert portfolio.kkt_residual(ref["x"], ref["eta"], ref["nu"], ref["zeta"], P["r"], P["F"], P["Dg"], P["M"],
+                                  P["u_p"], P["gamma"]) <= 1e-9
+    out = boxqp.solve(P["A"], P["b"], P["c"], P["q"], P["u"], P["vtype"], tol=1e-10)
+    assert out["status"] == 0
+    x = out["x"][:n]
+    np.testing.assert_allclose(x, ref["x"], atol=1e-7)
+    np.testing.assert_allclose(out["x"][n:n + s], P["F"].T @ x, atol=1e-7)
+    np.testing.assert_allclose(out["x"][n + s:], P["u_p"] - P["M"] @ x, atol=1e-7)
+    ob = 0.5 * out["x"] @ (P["q"] * out["x"]) + P["c"] @ out["x"]
+    assert abs(ob * P["gamma"] - portfolio.objective(ref["x"], P["r"], P["F"], P["Dg"], P["gamma"])) <= 1e-7
+
+
+def _portfolio_tiny(n, d, s, seed, gamma=2.0):
+    from instances import portfolio_instance
+    return portfolio_instance(n, d, s, seed=seed, gamma=gamma, with_parts=True)
+
+
+def test_portfolio_bruteforce_matches_a_library_solver():
+    """The enumeration against scipy's SLSQP on the original problem."""
+    from scipy.optimize import minimize
+    for seed in (0, 3):
+        P = _np_parts(_portfolio_tiny(7, 4, 2, seed))
+        ref = portfolio.bruteforce(P["r"], P["F"], P["Dg"], P["M"], P["u_p"], P["gamma"])
+        n = len(P["r"])
+        res = minimize(lambda x: portfolio.objective(x, P["r"], P["F"], P["Dg"], P["gamma"]), np.full(n, 1.0 / n),
+                       method="SLSQP", bounds=[(0, None)] * n,
+                       constraints=[dict(type="eq", fun=lambda x: x.sum() - 1.0),
+                                    dict(type="ineq", fun=lambda x: P["u_p"] - P["M"] @ x)],
+                       options=dict(ftol=1e-14, maxiter=500))
+        assert res.success
+        np.testing.assert_allclose(res.x, ref["x"], atol=1e-5)

@@ -209,6 +209,11 @@ SVM_SHAPES = {"svm_sensit": (100, 98528, 50), "svm_cifar10": (3072, 60000, 200),
               "svm_rnaseq": (20531, 801, 200)}
 
 
+# The portfolio workload (section 5.1): n assets, d correlation constraints,
+# s factors, sketch size, tolerance.
+PORTFOLIO_SHAPES = {"portfolio_80000x50000": (80000, 50000, 100, 20, 1e-8)}
+
+
 def compare_svm(nys, args):
     """The paper's SVM comparison (section 5.2) on the dual linear SVM in form
     (P~) with synthetic dense features: Nys-IP-PMM, CG-IP-PMM, Chol-IP-PMM."""
@@ -216,18 +221,40 @@ def compare_svm(nys, args):
     from instances import svm_instance
     d, n, ell = SVM_SHAPES[args.workload]
     S = svm_instance(d, n, seed=args.seed, device="cuda", dtype=torch.float32)
+    compare_box(nys, args, S, ell, TOL, {"d": d, "n": n})
+
+
+def compare_portfolio(nys, args):
+    """The paper's portfolio comparison (section 5.1): the factor-model
+    problem in form (P~) (y = F^T x free, slacks for M x <= u), tolerance
+    1e-8, Nys-IP-PMM with ell = 20 against CG-IP-PMM and Chol-IP-PMM."""
+    import torch
+    from instances import portfolio_instance
+    n, d, s_f, ell, tol = PORTFOLIO_SHAPES[args.workload]
+    t0 = time.perf_counter()
+    S = portfolio_instance(n, d, s_f, seed=args.seed, device="cuda", dtype=torch.float32)
+    torch.cuda.synchronize()
+    log(f"{args.workload}: A {tuple(S['A'].shape)} FP32 generated in {time.perf_counter() - t0:.1f}s")
+    compare_box(nys, args, S, ell, tol, {"n": n, "d": d, "s": s_f})
+
+
+def compare_box(nys, args, S, ell, tol, shape):
+    """Nys-IP-PMM, Chol-IP-PMM and CG-IP-PMM on one (P~) instance (FP32 A,
+    BF16 sketch): one warm-up solve, then one JSON line per solver."""
+    import torch
     A = S["A"]
     A_lo = A.to(torch.bfloat16)
+    A_t = nys.nys_transpose(A)
     box = (S["vtype"], S["u"])
-    extra = dict(verbose=args.verbose, max_iter=args.max_iter)
-    nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=TOL, seed=args.seed, sketch_dtype="bf16",
+    extra = dict(verbose=args.verbose, max_iter=args.max_iter, A_t=A_t)
+    nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=tol, seed=args.seed, sketch_dtype="bf16",
                       A_lo=A_lo, **extra)
     torch.cuda.synchronize()
     for name, pre in (("Nys-IP-PMM", "nystrom"), ("Chol-IP-PMM", "pchol"), ("CG-IP-PMM", "none")):
         log(f"{args.workload}: {name}")
         t0 = time.perf_counter()
         try:
-            x, y, z, w, s, info = nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=TOL,
+            x, y, z, w, s, info = nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=tol,
                                                     seed=args.seed, sketch_dtype="bf16",
                                                     A_lo=A_lo if pre == "nystrom" else None, precond=pre, **extra)
         except nys.NysError as e:          # e.g. the iteration limit: report it
@@ -235,9 +262,9 @@ def compare_svm(nys, args):
             continue
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        rec = {"solver": name, "workload": args.workload, "d": d, "n": n, "ell": ell, "seconds": round(t, 3),
-               "status": info.status, "ipm_iters": info.iters, "pcg_iters": info.pcg_iters_total,
-               "kkt_rel": info.kkt_rel,
+        rec = {"solver": name, "workload": args.workload, **shape, "m": A.shape[0], "n_vars": A.shape[1],
+               "ell": ell, "tol": tol, "seconds": round(t, 3), "status": info.status, "ipm_iters": info.iters,
+               "pcg_iters": info.pcg_iters_total, "kkt_rel": info.kkt_rel,
                "time_split_ms": {"precond": round(info.t_sketch_ms, 1), "pcg": round(info.t_pcg_ms, 1),
                                  "other": round(info.t_other_ms, 1)}}
         print(json.dumps(rec), flush=True)
@@ -332,6 +359,10 @@ def main():
     if args.compare and args.workload in SVM_SHAPES:
         import paper_2404_14524_amd as nys
         compare_svm(nys, args)
+        return
+    if args.compare and args.workload in PORTFOLIO_SHAPES:
+        import paper_2404_14524_amd as nys
+        compare_portfolio(nys, args)
         return
     if args.summarize_trace or args.summarize_pmc:
         from instances import CONFIGS

@@ -671,3 +671,32 @@ def test_ipm_solve_rejects_bad_rule_options(nys):
             nys.ipm_solve(A, b, c, q, ell=20, tol=1e-6, **kw)
     with pytest.raises(ValueError):
         nys.ipm_solve(A, b, c, q, ell=20, tol=1e-6, trace=np.zeros((10, 3)))
+
+
+# ------------------------------------------------------------------ portfolio problem
+
+@pytest.mark.parametrize("precond,storage", [("nystrom", "f64"), ("nystrom", "f32"), ("pchol", "f64"),
+                                             ("none", "f64")])
+def test_ipm_solve_box_portfolio(nys, precond, storage):
+    """The factor-model portfolio problem in form (P~) (x >= 0, y = F^T x
+    free, slacks >= 0) at tolerance 1e-8: the oracle's optimum (unique: the
+    objective is strictly convex in x and y, and t = u - M x)."""
+    from instances import portfolio_instance
+    from oracle import boxqp
+    print(f"portfolio precond={precond} storage={storage}", flush=True)
+    dt = torch.float64 if storage == "f64" else torch.float32
+    P = portfolio_instance(600, 300, 12, seed=1, dtype=dt)
+    npd = {k: v.double().numpy() if k == "A" else v.numpy() for k, v in P.items()}
+    ref = boxqp.solve(npd["A"], npd["b"], npd["c"], npd["q"], npd["u"], npd["vtype"], tol=1e-11)
+    assert ref["status"] == 0
+    A = P["A"].to(DEV)
+    x, y, z, w, s, info = nys.ipm_solve_box(A, _t(npd["b"]), _t(npd["c"]), _t(npd["q"]),
+                                            _t(npd["vtype"], torch.int8), _t(npd["u"]), ell=20, tol=1e-8, seed=3,
+                                            precond=precond, sketch_dtype="bf16" if storage == "f32" else "f64",
+                                            A_lo=A.to(torch.bfloat16) if storage == "f32" else None)
+    assert info.status == 0, (info.kkt_rel, info.iters)
+    meas = boxqp.kkt_measure(npd["A"], npd["b"], npd["c"], npd["q"], npd["u"], npd["vtype"], _np(x), _np(y), _np(z),
+                             _np(w), _np(s))
+    assert meas["kkt"] <= 1e-8
+    assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+    assert abs(_np(x)[:600].sum() - 1.0) <= 1e-8

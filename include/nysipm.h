@@ -59,19 +59,33 @@ enum { NYS_PRECOND_NYSTROM = 0, NYS_PRECOND_NONE = 1, NYS_PRECOND_PCHOL = 2 };
 
 typedef struct nys_handle_s* nys_handle;
 
-/* A: m x n, row-major, leading dimension ld (elements), storage dtype.
-   data_t (optional, may be NULL): the same matrix transposed, n x m row-major
-   with leading dimension ld_t >= m, same dtype, caller-owned and not modified.
+/* A = [A_d | E]: a dense block A_d (m x n, row-major, leading dimension ld
+   in elements, storage dtype) followed by n_unit unit columns E (optional).
+   Unit column t (variable n + t) has the single entry unit_val[t] in row
+   unit_row[t]; unit_row is strictly increasing within [0, m) (so no two unit
+   columns share a row), unit_val finite FP64; both are device arrays of
+   n_unit elements (NULL when n_unit = 0).  Such columns are the identity and
+   slack blocks of the forms (P~) of the paper's SVM and portfolio problems;
+   they are applied exactly in FP64 and never stored densely.  Vectors indexed
+   by the columns of A (d, x, z, c, q, ...) have n + n_unit entries, dense
+   columns first.  Entry points that take a matrix check the unit arrays on
+   the device (NYS_EINVAL when they break the rules above).
+   data_t (optional, may be NULL): A_d transposed, n x m row-major with
+   leading dimension ld_t >= m, same dtype, caller-owned and not modified.
    When present, the products that reduce over the m rows (A^T v) stream whole
-   rows of it instead of column stripes of A (same results up to the order of
-   the FP64 additions).  ipm_solve and ipm_adjoint make such a copy in their
-   workspace when none is given (see nys_ipm_opts.no_transposed_copy). */
+   rows of it instead of column stripes of A_d (same results up to the order
+   of the FP64 additions).  ipm_solve and ipm_adjoint make such a copy in their
+   workspace when none is given (see nys_ipm_opts.no_transposed_copy).
+   Zero-initialise the struct: n_unit = 0 gives the plain dense matrix. */
 typedef struct {
   int64_t m, n, ld;
   nys_dtype dtype;
   const void* data;
   const void* data_t;
   int64_t ld_t;
+  int64_t n_unit;
+  const int32_t* unit_row;
+  const double* unit_val;
 } nys_matrix;
 
 /* Nystrom preconditioner {U_hat, Lambda_hat} (Algorithm 2; eq. Nys_precond).

@@ -180,7 +180,7 @@ def random_feasible_instance(m: int, n: int, seed: int, q_lo: float = 0.1,
 
 
 def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 2.0, decay: float = 1.5,
-                 device: str | torch.device = "cpu", dtype=torch.float64) -> dict:
+                 device: str | torch.device = "cpu", dtype=torch.float64, unit_columns: bool = False) -> dict:
     """Dual linear SVM in the box-constrained form (P~) (the paper's SVM
     formulation): x = [v; p], Q = diag(1_d, 0_n), A = [[I_d, -X diag(y)],
     [0, y^T]], b = 0, c = [0_d; -1_n] (the objective 1/2 v^T v - sum p), v
@@ -191,7 +191,10 @@ def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 2
     are a dense random mixing M (d x d, N(0, 1/d) entries) of the latent
     coordinates, so the dominant directions are not aligned with the feature
     axes; labels +-1 in equal numbers (a seeded permutation).  Returns A
-    (dtype), b, c, q, u (float64), vtype (int8), labels."""
+    (dtype), b, c, q, u (float64), vtype (int8), labels.  With unit_columns
+    the variables are ordered [p; v]: A holds only the dense block
+    [-X diag(y); y^T] and units = (rows 0..d-1 int32, values 1.0) describes
+    the identity on v (same draws, so x_unit = [p; v] for x_dense = [v; p])."""
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     f64 = torch.float64
@@ -204,6 +207,18 @@ def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 2
     M = torch.randn((d, d), generator=g, dtype=f64, device=device) / d ** 0.5
     X = M @ L
     del L, M
+    if unit_columns:
+        Ad = torch.empty((d + 1, n), dtype=f64, device=device)
+        Ad[:d] = -X * yl[None, :]
+        Ad[d] = yl
+        units = (torch.arange(d, dtype=torch.int32, device=device), torch.ones(d, dtype=f64, device=device))
+        b = torch.zeros(d + 1, dtype=f64, device=device)
+        c = torch.cat([-torch.ones(n, dtype=f64, device=device), torch.zeros(d, dtype=f64, device=device)])
+        q = torch.cat([torch.zeros(n, dtype=f64, device=device), torch.ones(d, dtype=f64, device=device)])
+        u = torch.cat([torch.full((n,), tau, dtype=f64, device=device), torch.zeros(d, dtype=f64, device=device)])
+        vtype = torch.cat([torch.full((n,), 2, dtype=torch.int8, device=device),
+                           torch.full((d,), 1, dtype=torch.int8, device=device)])
+        return dict(A=Ad.to(dtype), units=units, b=b, c=c, q=q, u=u, vtype=vtype, labels=yl)
     A = torch.zeros((d + 1, d + n), dtype=f64, device=device)
     A[:d, :d] = torch.eye(d, dtype=f64, device=device)
     A[:d, d:] = -X * yl[None, :]
@@ -220,7 +235,7 @@ def svm_instance(d: int, n: int, seed: int = 0, tau: float = 1.0, sep: float = 2
 
 def portfolio_instance(n: int = 80000, d: int = 50000, s: int = 100, seed: int = 0, gamma: float = 1.0,
                        components: Optional[int] = None, device: str | torch.device = "cpu",
-                       dtype=torch.float64, with_parts: bool = False) -> dict:
+                       dtype=torch.float64, with_parts: bool = False, unit_columns: bool = False) -> dict:
     """The factor-model portfolio problem (the paper's portfolio experiment)
     min -r^T x + gamma x^T (F F^T + diag(Dg)) x  s.t.  M x <= u_p, 1^T x = 1,
     x >= 0, in the form (P~) of its reformulation with y = F^T x free and a
@@ -236,7 +251,9 @@ def portfolio_instance(n: int = 80000, d: int = 50000, s: int = 100, seed: int =
     ~ N(0, I); r ~ N(0, 1); u_p ~ U[0.05, 1] (x = 1/n is strictly feasible).
     A holds the stored values (dtype); F and M of the returned parts are those
     values promoted to FP64.  Returns A, b, c, q, u, vtype and, with
-    with_parts, F, Dg, M, u_p, r, gamma."""
+    with_parts, F, Dg, M, u_p, r, gamma.  With unit_columns A holds only the
+    dense columns [F^T; M; 1^T] (m x n) and units = (rows int32, values)
+    describes the -I_s and I_d blocks (same variable order and draws)."""
     g = torch.Generator(device=device)
     g.manual_seed(int(seed))
     f64 = torch.float64
@@ -253,22 +270,29 @@ def portfolio_instance(n: int = 80000, d: int = 50000, s: int = 100, seed: int =
     r = torch.randn(n, generator=g, dtype=f64, device=device)
     u_p = 0.05 + 0.95 * torch.rand(d, generator=g, dtype=f64, device=device)
     m, N = s + d + 1, n + s + d
-    A = torch.zeros((m, N), dtype=dtype, device=device)
+    A = torch.zeros((m, n if unit_columns else N), dtype=dtype, device=device)
     A[:s, :n] = F.T.to(dtype)
-    A[:s, n:n + s] = -torch.eye(s, dtype=dtype, device=device)
     step = _panel_rows(d, n)
     for r0 in range(0, d, step):                    # M in row panels, drawn in the storage type
         r1 = min(d, r0 + step)
         A[s + r0:s + r1, :n] = torch.randn((r1 - r0, n), generator=g, dtype=f64 if dtype == f64 else torch.float32,
                                            device=device).to(dtype)
-    A[s:s + d, n + s:] = torch.eye(d, dtype=dtype, device=device)
     A[s + d, :n] = 1.0
+    units = None
+    if unit_columns:
+        units = (torch.arange(s + d, dtype=torch.int32, device=device),
+                 torch.cat([torch.full((s,), -1.0, dtype=f64, device=device), torch.ones(d, dtype=f64, device=device)]))
+    else:
+        A[:s, n:n + s] = -torch.eye(s, dtype=dtype, device=device)
+        A[s:s + d, n + s:] = torch.eye(d, dtype=dtype, device=device)
     b = torch.cat([torch.zeros(s, dtype=f64, device=device), u_p, torch.ones(1, dtype=f64, device=device)])
     c = torch.cat([-r / gamma, torch.zeros(s + d, dtype=f64, device=device)])
     q = torch.cat([2.0 * Dg, torch.full((s,), 2.0, dtype=f64, device=device), torch.zeros(d, dtype=f64, device=device)])
     vtype = torch.cat([torch.zeros(n, dtype=torch.int8, device=device), torch.ones(s, dtype=torch.int8, device=device),
                        torch.zeros(d, dtype=torch.int8, device=device)])
     out = dict(A=A, b=b, c=c, q=q, u=torch.zeros(N, dtype=f64, device=device), vtype=vtype)
+    if unit_columns:
+        out["units"] = units
     if with_parts:
         out.update(F=A[:s, :n].T.to(f64), Dg=Dg, M=A[s:s + d, :n].to(f64), u_p=u_p, r=r, gamma=gamma)
     return out

@@ -161,7 +161,7 @@ int check_matrix(nys_handle h, const nys_matrix* A, const char* who) {
   if (A->m > 0 && A->n > 0 && !A->data) return set_error(h, NYS_EINVAL, "%s: data is NULL", who);
   if (A->data_t && A->ld_t < std::max<int64_t>(A->m, 1))
     return set_error(h, NYS_EINVAL, "%s: ld_t=%lld < m=%lld", who, (long long)A->ld_t, (long long)A->m);
-  return NYS_OK;
+  return check_units(h, A, who);
 }
 
 int check_precond(nys_handle h, const nys_precond* P, int64_t m, const char* who) {
@@ -296,7 +296,7 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
     g1.beta = sc + SC_BETA;
     g1.d = d;
     double* w;
-    NYS_CHECK(ws(h, WS_W, (size_t)std::max<int64_t>(A->n, 1), &w));
+    NYS_CHECK(ws(h, WS_W, (size_t)std::max<int64_t>(ncols(A), 1), &w));
     g1.w = w;
     NYS_CHECK(gemv_t(h, g1));
     GemvN g2;
@@ -509,7 +509,7 @@ int newton_run(nys_handle h, const nys_matrix* A, const double* x, const double*
                double delta, const Precond& P, const double* rd, const double* rp, const double* rxz,
                const PcgCfg& cfg, double* dx, double* dy, double* dz, nys_pcg_info* info,
                const BoxNewton& bx = BoxNewton{}) {
-  const int64_t m = A->m, n = A->n;
+  const int64_t m = A->m, n = ncols(A);
   double* base;
   NYS_CHECK(ws(h, WS_NEWTON, (size_t)2 * n + m + 8, &base));
   double* tn = base;
@@ -665,7 +665,7 @@ extern "C" int nys_normal_apply(nys_handle h, const nys_matrix* A, const double*
   NYS_CHECK(check_matrix(h, A, "nys_normal_apply"));
   if (!is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_normal_apply: non-finite delta");
   if (A->m > 0 && (!v || !out)) return set_error(h, NYS_EINVAL, "nys_normal_apply: NULL vector");
-  if (A->n > 0 && A->m > 0 && !d) return set_error(h, NYS_EINVAL, "nys_normal_apply: NULL d");
+  if (ncols(A) > 0 && A->m > 0 && !d) return set_error(h, NYS_EINVAL, "nys_normal_apply: NULL d");
   if (v == out && A->m > 0) return set_error(h, NYS_EINVAL, "nys_normal_apply: out aliases v");
   NYS_HIP(h, hipSetDevice(h->device));
   if (A->m == 0) return NYS_OK;
@@ -775,7 +775,7 @@ extern "C" int nys_pchol_build(nys_handle h, const nys_matrix* A, const double* 
   if (A->m < 1) return set_error(h, NYS_EINVAL, "nys_pchol_build: m must be >= 1");
   NYS_CHECK(check_pchol(h, P, A->m, "nys_pchol_build"));
   if (!(delta > 0) || !is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_pchol_build: delta must be finite and > 0");
-  if (A->n > 0 && !d) return set_error(h, NYS_EINVAL, "nys_pchol_build: NULL d");
+  if (ncols(A) > 0 && !d) return set_error(h, NYS_EINVAL, "nys_pchol_build: NULL d");
   NYS_HIP(h, hipSetDevice(h->device));
   return pchol_build(h, A, d, delta, P);
 }
@@ -796,7 +796,7 @@ extern "C" int nys_pcg_solve_pchol(nys_handle h, const nys_matrix* A, const doub
   if (A->m < 1) return set_error(h, NYS_EINVAL, "nys_pcg_solve_pchol: m must be >= 1");
   NYS_CHECK(check_pchol(h, P, A->m, "nys_pcg_solve_pchol"));
   if (!(delta > 0) || !is_fin(delta)) return set_error(h, NYS_EINVAL, "nys_pcg_solve_pchol: delta must be finite and > 0");
-  if (!rhs || !y || (A->n > 0 && !d)) return set_error(h, NYS_EINVAL, "nys_pcg_solve_pchol: NULL vector");
+  if (!rhs || !y || (ncols(A) > 0 && !d)) return set_error(h, NYS_EINVAL, "nys_pcg_solve_pchol: NULL vector");
   NYS_HIP(h, hipSetDevice(h->device));
   Precond pc;
   pc.pc = P;
@@ -817,8 +817,8 @@ extern "C" int nys_newton_solve(nys_handle h, const nys_matrix* A, const double*
     return set_error(h, NYS_EINVAL, "nys_newton_solve: NULL vector");
   NYS_HIP(h, hipSetDevice(h->device));
   double* D;
-  NYS_CHECK(ws(h, WS_IPM, (size_t)A->n + 8, &D));
-  NYS_CHECK(map_reduce<0, 0>(h, A->n, ScalingF{D, q, x, z, rho}, nullptr));
+  NYS_CHECK(ws(h, WS_IPM, (size_t)ncols(A) + 8, &D));
+  NYS_CHECK(map_reduce<0, 0>(h, ncols(A), ScalingF{D, q, x, z, rho}, nullptr));
   Precond pc;
   if (P) pc = Precond{P->U, P->lambda, P->ell};
   int rc = newton_run(h, A, x, z, D, delta, pc, r_d, r_p, r_xz, pcg_cfg(opts, A->m), dx, dy, dz, info);

@@ -451,7 +451,14 @@ int n_blocks_pass2(int64_t m) {
 
 }  // namespace
 
+int gemv_t_dense(nys_handle h, const GemvT& a);
+
 int gemv_t(nys_handle h, const GemvT& a) {
+  NYS_CHECK(gemv_t_dense(h, a));
+  return unit_pass1(h, a, a.s ? a.pnew : a.v);
+}
+
+int gemv_t_dense(nys_handle h, const GemvT& a) {
   const nys_matrix* A = a.A;
   const int es = elem_size(A->dtype);
   const int vec = 16 / es;
@@ -509,6 +516,8 @@ int gemv_n(nys_handle h, const GemvN& a) {
   const nys_matrix* A = a.A;
   if (A->m == 0) return NYS_OK;
   const int es = elem_size(A->dtype);
+  const double* x0 = a.x0;
+  NYS_CHECK(unit_pass2_base(h, a, &x0));
   T2Args k{};
   k.skip = a.skip;
   k.A = (const char*)A->data;
@@ -517,7 +526,7 @@ int gemv_n(nys_handle h, const GemvN& a) {
   k.row_bytes = A->ld * es;
   k.w = a.w;
   k.v = a.v;
-  k.x0 = a.x0;
+  k.x0 = x0;
   k.sA = a.sA;
   k.sV = a.sV;
   k.out = a.out;
@@ -586,7 +595,7 @@ int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, int slot, ny
 int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
                  const double* v, double* out, double* dot_out) {
   double* w;
-  NYS_CHECK(ws(h, WS_W, (size_t)std::max<int64_t>(A->n, 1), &w));
+  NYS_CHECK(ws(h, WS_W, (size_t)std::max<int64_t>(ncols(A), 1), &w));
   GemvT t;
   t.A = A;
   t.v = v;

@@ -34,6 +34,7 @@ enum nys_slot {
   WS_ALOT,        // transposed copy of the BF16 matrix of the sketch
   WS_PCH,         // partial Cholesky: apply vectors (t1, sums)
   WS_PCHB,        // partial Cholesky built by ipm_solve (pivots, L, Cinv, diag S)
+  WS_UNIT,        // m-vector: the unit columns' part of a pass 2 (transient, per call)
   WS_NSLOTS
 };
 
@@ -93,6 +94,9 @@ int sync(nys_handle h);
 int prof_begin(nys_handle h, int kclass);
 void prof_end(nys_handle h, int slot);
 int prof_drain(nys_handle h);
+
+// Columns of A including the unit columns (the length of column-indexed vectors).
+inline int64_t ncols(const nys_matrix* A) { return A->n + A->n_unit; }
 
 }  // namespace nys
 

@@ -340,13 +340,20 @@ int check_qp(nys_handle h, const nys_qp* qp, const char* who) {
     if (L->m != A->m || L->n != A->n || L->ld < L->n || L->dtype != NYS_BF16 || !L->data)
       return set_error(h, NYS_EINVAL, "%s: A_lo must be a BF16 matrix of A's shape", who);
   }
-  return NYS_OK;
+  return check_units(h, A, who);
 }
 
 // BF16 storage for the matrix-core sketch: the caller's copy, or one made here.
 int lo_matrix(nys_handle h, const nys_qp* qp, nys_matrix* out) {
+  // the unit columns are A's (applied exactly, whatever the storage of A_d)
+  auto with_units = [&](nys_matrix* L) {
+    L->n_unit = qp->A->n_unit;
+    L->unit_row = qp->A->unit_row;
+    L->unit_val = qp->A->unit_val;
+  };
   if (qp->A_lo) {
     *out = *qp->A_lo;
+    with_units(out);
     return NYS_OK;
   }
   const nys_matrix* A = qp->A;
@@ -359,6 +366,7 @@ int lo_matrix(nys_handle h, const nys_qp* qp, nys_matrix* out) {
       NYS_CHECK(to_bf16(h, (const double*)A->data + i * A->ld, lo + i * A->n, A->n));
   }
   *out = nys_matrix{A->m, A->n, A->n, NYS_BF16, lo};
+  with_units(out);
   return NYS_OK;
 }
 
@@ -455,7 +463,7 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   if (!x || !y || !z) return set_error(h, NYS_EINVAL, "ipm_solve: NULL output");
   Opts o = read_opts(opts_in);
   const nys_matrix* A = qp->A;
-  const int64_t m = A->m, n = A->n;
+  const int64_t m = A->m, n = ncols(A);
   if (o.ell < 1 || o.ell > m) return set_error(h, NYS_EINVAL, "ipm_solve: ell must be in [1, m]");
   if (o.sk != NYS_F64 && o.sk != NYS_BF16) return set_error(h, NYS_EINVAL, "ipm_solve: bad sketch dtype");
   if (o.precond < NYS_PRECOND_NYSTROM || o.precond > NYS_PRECOND_PCHOL)
@@ -845,6 +853,7 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   NYS_CHECK(check_qp(h, qp, "ipm_adjoint"));
   if (!x || !y || !z || !g) return set_error(h, NYS_EINVAL, "ipm_adjoint: NULL input");
   if (qp->vtype) return set_error(h, NYS_EINVAL, "ipm_adjoint: free or box-constrained variables are not supported");
+  if (qp->A->n_unit != 0) return set_error(h, NYS_EINVAL, "ipm_adjoint: unit columns are not supported");
   if (!(delta > 0) || !std::isfinite(delta) || !(rho >= 0) || !std::isfinite(rho))
     return set_error(h, NYS_EINVAL, "ipm_adjoint: need delta > 0 and rho >= 0");
   Opts o = read_opts(opts_in);

@@ -45,6 +45,21 @@ struct GemvN {
   double* dot_out = nullptr;
 };
 int gemv_n(nys_handle h, const GemvN& a);
+// Both passes include the unit columns of A (nys_matrix.n_unit): pass 1 writes
+// w[n + t] as well, pass 2 adds their terms (squared with square) in FP64.
+// (Internal to the two passes: unit_pass1 writes w[n + t] from v; unit_pass2_base
+// returns in *x0_eff the per-row vector x0 + unit terms for the dense pass 2.)
+int unit_pass1(nys_handle h, const GemvT& a, const double* v);
+int unit_pass2_base(nys_handle h, const GemvN& a, const double** x0_eff);
+// e[i] = sum over unit columns t in row i of val_t^2 d[n + t] (zero elsewhere):
+// the unit columns' part of the diagonal of A diag(d) A^T.
+int unit_diag(nys_handle h, const nys_matrix* A, const double* d, double* e);
+// Y[row_t, :] += val_t^2 d[n + t] Omega[row_t, :] for every unit column t
+// (their part of the sketch N Omega; Y and Omega m x ell row-major).
+int unit_sketch(nys_handle h, const nys_matrix* A, const double* d, const double* Omega, int ell, double* Y);
+// Device check of the unit arrays (rows strictly increasing in [0, m), values
+// finite); NYS_EINVAL with a message naming `who` otherwise.  Synchronises.
+int check_units(nys_handle h, const nys_matrix* A, const char* who);
 
 // At (n x m, leading dimension ld_t >= m elements, A's dtype) = A^T.
 int transpose(nys_handle h, const nys_matrix* A, void* At, int64_t ld_t);

@@ -237,6 +237,13 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_pchol_fin2(ApArgs a) {
 
 int elem_bytes(nys_dtype dt) { return dt == NYS_F64 ? 8 : dt == NYS_F32 ? 4 : 2; }
 
+// Y[piv[k], k] += e[piv[k]]: the unit columns' part of N[:, piv] (diagonal only,
+// since no two unit columns share a row)
+__global__ __launch_bounds__(NYS_BLOCK) void k_pchol_unit(double* Y, int ell, const int* piv, const double* e) {
+  for (int k = blockIdx.x * NYS_BLOCK + threadIdx.x; k < ell; k += gridDim.x * NYS_BLOCK)
+    Y[(int64_t)piv[k] * ell + k] += e[piv[k]];
+}
+
 }  // namespace
 
 int pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta, nys_pchol* P) {
@@ -270,6 +277,14 @@ int pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta
     NYS_CHECK(gemm_f64(h, false, true, m, ell, n, A->data, A->dtype, A->ld, Wt, n, Y, ell, nullptr));
   } else {
     NYS_CHECK(fill(h, Y, m * ell, 0.0));
+  }
+  if (A->n_unit > 0) {
+    double* e;
+    NYS_CHECK(ws(h, WS_UNIT, (size_t)m, &e));
+    NYS_CHECK(unit_diag(h, A, d, e));
+    hipLaunchKernelGGL(k_pchol_unit, dim3((unsigned)((ell + NYS_BLOCK - 1) / NYS_BLOCK)), dim3(NYS_BLOCK), 0,
+                       h->stream, Y, ell, (const int*)P->piv, (const double*)e);
+    NYS_LAUNCH_CHECK(h);
   }
   hipLaunchKernelGGL(k_pchol_n11, dim3((unsigned)ell), dim3(NYS_BLOCK), 0, h->stream, Y, ell, (const int*)P->piv,
                      delta, G);

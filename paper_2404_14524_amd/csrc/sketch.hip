@@ -12,7 +12,10 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
 
 int sketch_product(nys_handle h, const nys_matrix* A, const double* d, const double* Omega,
                    int ell, nys_dtype mode, double* Y) {
-  if (mode == NYS_BF16) return sketch_bf16(h, A, d, Omega, ell, Y);
+  if (mode == NYS_BF16) {
+    NYS_CHECK(sketch_bf16(h, A, d, Omega, ell, Y));
+    return unit_sketch(h, A, d, Omega, ell, Y);     // unit columns: exact FP64 terms
+  }
   if (A->dtype == NYS_BF16)
     return set_error(h, NYS_EINVAL, "FP64 sketch needs an FP64 or FP32 matrix");
   double* W;
@@ -21,7 +24,7 @@ int sketch_product(nys_handle h, const nys_matrix* A, const double* d, const dou
   NYS_CHECK(gemm_f64(h, true, false, A->n, ell, A->m, A->data, A->dtype, A->ld, Omega, ell, W, ell, d));
   // Y (m x ell) = A W : K = n
   NYS_CHECK(gemm_f64(h, false, false, A->m, ell, A->n, A->data, A->dtype, A->ld, W, ell, Y, ell, nullptr));
-  return NYS_OK;
+  return unit_sketch(h, A, d, Omega, ell, Y);
 }
 
 }  // namespace nys

@@ -35,7 +35,8 @@ class NysError(RuntimeError):
 
 class nys_matrix(C.Structure):
     _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("ld", C.c_int64), ("dtype", C.c_int),
-                ("data", C.c_void_p), ("data_t", C.c_void_p), ("ld_t", C.c_int64)]
+                ("data", C.c_void_p), ("data_t", C.c_void_p), ("ld_t", C.c_int64),
+                ("n_unit", C.c_int64), ("unit_row", C.c_void_p), ("unit_val", C.c_void_p)]
 
 
 class nys_precond(C.Structure):
@@ -179,10 +180,31 @@ def _vec(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
     return t
 
 
-def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None) -> nys_matrix:
+def _units(A: torch.Tensor, units) -> tuple:
+    """(count, rows pointer, values pointer) of the unit columns: units is None
+    or (rows int32, vals float64), device tensors of equal length (rows
+    strictly increasing within [0, m), checked by the library)."""
+    if units is None:
+        return 0, None, None
+    rows, vals = units
+    if (rows.dtype != torch.int32 or vals.dtype != torch.float64 or rows.dim() != 1 or vals.dim() != 1
+            or rows.numel() != vals.numel() or rows.device != A.device or vals.device != A.device
+            or not rows.is_contiguous() or not vals.is_contiguous()):
+        raise ValueError("units: need (int32 rows, float64 values), 1-D contiguous, equal length, on A's device")
+    k = rows.numel()
+    return k, (rows.data_ptr() if k else None), (vals.data_ptr() if k else None)
+
+
+def ncols(A: torch.Tensor, units=None) -> int:
+    """Number of variables: dense columns plus unit columns."""
+    return A.shape[1] + (0 if units is None else units[0].numel())
+
+
+def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None, units=None) -> nys_matrix:
     """nys_matrix view of a row-major CUDA tensor; A_t (optional) is the same
-    matrix transposed, n x m row-major (see nys_transpose)."""
-    if A.dim() != 2 or A.dtype not in _DT or not A.is_cuda or A.stride(1) != 1:
+    matrix transposed, n x m row-major (see nys_transpose); units (optional)
+    appends unit columns (see _units)."""
+    if A.dim() != 2 or A.dtype not in _DT or not A.is_cuda or (A.stride(1) != 1 and A.shape[1] > 1):
         raise ValueError("A: need a 2-D row-major float64/float32/bfloat16 CUDA tensor")
     tp, tld = None, 0
     if A_t is not None:
@@ -190,8 +212,9 @@ def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None) -> nys_matrix:
                 or A_t.device != A.device or A_t.stride(1) != 1):
             raise ValueError("A_t: need an n x m row-major tensor of A's dtype on A's device")
         tp, tld = A_t.data_ptr(), max(A_t.stride(0), A.shape[0], 1)
+    k, ur, uv = _units(A, units)
     return nys_matrix(A.shape[0], A.shape[1], max(A.stride(0), A.shape[1], 1), _DT[A.dtype],
-                      A.data_ptr(), tp, tld)
+                      A.data_ptr(), tp, tld, k, ur, uv)
 
 
 @dataclass
@@ -218,16 +241,16 @@ class PChol:
                          self.L.data_ptr(), self.Cinv.data_ptr(), self.diagS.data_ptr())
 
 
-def nys_pchol_build(A: torch.Tensor, d: torch.Tensor, delta: float, ell: int) -> PChol:
+def nys_pchol_build(A: torch.Tensor, d: torch.Tensor, delta: float, ell: int, units=None) -> PChol:
     lib, h = _handle(A.device)
-    m, n = A.shape
-    _vec(d, n, "d", A.device)
+    m = A.shape[0]
+    _vec(d, ncols(A, units), "d", A.device)
     dev = A.device
     P = PChol(torch.empty(ell, dtype=torch.int32, device=dev), torch.empty(m, dtype=torch.int32, device=dev),
               torch.empty((m, ell), dtype=torch.float64, device=dev),
               torch.empty((ell, ell), dtype=torch.float64, device=dev), torch.empty(m, dtype=torch.float64, device=dev))
     Pc = P.c()
-    Am = _mat(A)
+    Am = _mat(A, units=units)
     _check(lib, h, lib.nys_pchol_build(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc)))
     return P
 
@@ -260,13 +283,14 @@ def nys_transpose(A: torch.Tensor) -> torch.Tensor:
 
 
 def nys_normal_apply(A: torch.Tensor, d: torch.Tensor, delta: float, v: torch.Tensor,
-                     out: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None) -> torch.Tensor:
+                     out: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None,
+                     units=None) -> torch.Tensor:
     lib, h = _handle(A.device)
-    m, n = A.shape
-    _vec(d, n, "d", A.device)
+    m = A.shape[0]
+    _vec(d, ncols(A, units), "d", A.device)
     _vec(v, m, "v", A.device)
     out = torch.empty(m, dtype=torch.float64, device=A.device) if out is None else _vec(out, m, "out", A.device)
-    Am = _mat(A, A_t)
+    Am = _mat(A, A_t, units)
     _check(lib, h, lib.nys_normal_apply(h, C.byref(Am), _ptr(d), float(delta), _ptr(v), _ptr(out)))
     return out
 
@@ -280,15 +304,16 @@ def nys_test_matrix(m: int, ell: int, seed: int, counter: int, device="cuda") ->
 
 
 def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sketch_dtype="f64",
-                       out: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None) -> torch.Tensor:
+                       out: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None,
+                       units=None) -> torch.Tensor:
     lib, h = _handle(A.device)
-    m, n = A.shape
+    m = A.shape[0]
     ell = omega.shape[1]
-    _vec(d, n, "d", A.device)
+    _vec(d, ncols(A, units), "d", A.device)
     _vec(omega.reshape(-1), m * ell, "omega", A.device)
     Y = torch.empty((m, ell), dtype=torch.float64, device=A.device) if out is None else out
     _vec(Y.reshape(-1), m * ell, "out", A.device)
-    Am = _mat(A, A_t)
+    Am = _mat(A, A_t, units)
     _check(lib, h, lib.nys_sketch_product(h, C.byref(Am), _ptr(d), _ptr(omega), ell, _SK[sketch_dtype],
                                           _ptr(Y)))
     return Y
@@ -296,17 +321,17 @@ def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sk
 
 def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,
                sketch_dtype="f64", omega: Optional[torch.Tensor] = None,
-               A_t: Optional[torch.Tensor] = None) -> Precond:
+               A_t: Optional[torch.Tensor] = None, units=None) -> Precond:
     lib, h = _handle(A.device)
-    m, n = A.shape
-    _vec(d, n, "d", A.device)
+    m = A.shape[0]
+    _vec(d, ncols(A, units), "d", A.device)
     if omega is not None:
         _vec(omega.reshape(-1), m * ell, "omega", A.device)
     U = torch.empty((m, ell), dtype=torch.float64, device=A.device)
     lam = torch.empty(ell, dtype=torch.float64, device=A.device)
     P = nys_precond(m, ell, U.data_ptr(), lam.data_ptr())
     nu = C.c_double(0.0)
-    Am = _mat(A, A_t)
+    Am = _mat(A, A_t, units)
     _check(lib, h, lib.nys_sketch(h, C.byref(Am), _ptr(d), ell, seed, counter, _SK[sketch_dtype],
                                   _ptr(omega), C.byref(P), C.byref(nu)))
     return Precond(U, lam, nu.value)
@@ -325,13 +350,13 @@ def nys_precond_apply(P: Precond, delta: float, r: torch.Tensor,
 
 def nys_pcg_solve(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Tensor,
                   P: Optional[Precond] = None, y0: Optional[torch.Tensor] = None,
-                  A_t: Optional[torch.Tensor] = None, **opts):
+                  A_t: Optional[torch.Tensor] = None, units=None, **opts):
     lib, h = _handle(A.device)
-    m, n = A.shape
-    _vec(d, n, "d", A.device)
+    m = A.shape[0]
+    _vec(d, ncols(A, units), "d", A.device)
     _vec(rhs, m, "rhs", A.device)
     y = torch.zeros(m, dtype=torch.float64, device=A.device) if y0 is None else _vec(y0, m, "y0", A.device).clone()
-    Am = _mat(A, A_t)
+    Am = _mat(A, A_t, units)
     o = _pcg_opts(**opts)
     info = nys_pcg_info()
     Pc = P.c() if P is not None else None
@@ -346,9 +371,9 @@ def nys_pcg_solve(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Ten
 
 
 def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond] = None,
-                     A_t: Optional[torch.Tensor] = None, **opts):
+                     A_t: Optional[torch.Tensor] = None, units=None, **opts):
     lib, h = _handle(A.device)
-    m, n = A.shape
+    m, n = A.shape[0], ncols(A, units)
     dev = A.device
     for t, k, nm in ((q, n, "q"), (x, n, "x"), (z, n, "z"), (r_d, n, "r_d"), (r_p, m, "r_p"),
                      (r_xz, n, "r_xz")):
@@ -356,7 +381,7 @@ def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond
     dx = torch.empty(n, dtype=torch.float64, device=dev)
     dz = torch.empty(n, dtype=torch.float64, device=dev)
     dy = torch.empty(m, dtype=torch.float64, device=dev)
-    Am = _mat(A, A_t)
+    Am = _mat(A, A_t, units)
     o = _pcg_opts(**opts)
     info = nys_pcg_info()
     Pc = P.c() if P is not None else None
@@ -419,8 +444,8 @@ def nys_precond_rebuild_due(k: int, k_build: int, pcg_prev: int, pcg_ref: int, m
                                             float(growth)))
 
 
-def _qp(A, b, c, q, A_lo, A_t=None, vtype=None, u=None):
-    Am = _mat(A, A_t)
+def _qp(A, b, c, q, A_lo, A_t=None, vtype=None, u=None, units=None):
+    Am = _mat(A, A_t, units)
     Alo = _mat(A_lo) if A_lo is not None else None
     keep = (Am, Alo)
     qp = nys_qp(C.pointer(Am), C.pointer(Alo) if Alo is not None else None, b.data_ptr(),
@@ -433,12 +458,13 @@ VAR_NONNEG, VAR_FREE, VAR_BOX = 0, 1, 2
 
 def ipm_solve_box(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor, vtype: torch.Tensor,
                   u: torch.Tensor, ell: int, A_lo: Optional[torch.Tensor] = None,
-                  A_t: Optional[torch.Tensor] = None, **kw):
+                  A_t: Optional[torch.Tensor] = None, units=None, **kw):
     """Nys-IP-PMM for free (VAR_FREE), non-negative (VAR_NONNEG) and box-constrained
     (VAR_BOX, 0 <= x_j <= u_j) variables.  vtype: n int8; u: n float64 (read on
-    box indices).  Returns (x, y, z, w, s, info)."""
+    box indices).  units: optional unit columns (see _units) after the dense
+    ones.  Returns (x, y, z, w, s, info)."""
     lib, h = _handle(A.device)
-    m, n = A.shape
+    m, n = A.shape[0], ncols(A, units)
     dev = A.device
     _vec(b, m, "b", dev)
     _vec(c, n, "c", dev)
@@ -448,7 +474,7 @@ def ipm_solve_box(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Te
         raise ValueError(f"vtype: need a contiguous int8 tensor of {n} elements on {dev}")
     x, z, w, s = (torch.empty(n, dtype=torch.float64, device=dev) for _ in range(4))
     y = torch.empty(m, dtype=torch.float64, device=dev)
-    qp, keep = _qp(A, b, c, q, A_lo, A_t, vtype, u)
+    qp, keep = _qp(A, b, c, q, A_lo, A_t, vtype, u, units)
     o = _ipm_opts(ell, **kw)
     info = nys_ipm_info()
     rc = lib.ipm_solve_box(h, C.byref(qp), C.byref(o), _ptr(x), _ptr(y), _ptr(z), _ptr(w), _ptr(s), C.byref(info))
@@ -458,11 +484,12 @@ def ipm_solve_box(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Te
 
 
 def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor, ell: int,
-              A_lo: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None, **kw):
+              A_lo: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None, units=None, **kw):
     """Nys-IP-PMM.  Returns (x, y, z, info: nys_ipm_info).  Without A_t the
-    library makes its own transposed copy of A unless transposed_copy=False."""
+    library makes its own transposed copy of A unless transposed_copy=False.
+    units: optional unit columns (see _units) after the dense ones."""
     lib, h = _handle(A.device)
-    m, n = A.shape
+    m, n = A.shape[0], ncols(A, units)
     dev = A.device
     _vec(b, m, "b", dev)
     _vec(c, n, "c", dev)
@@ -470,7 +497,7 @@ def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor
     x = torch.empty(n, dtype=torch.float64, device=dev)
     z = torch.empty(n, dtype=torch.float64, device=dev)
     y = torch.empty(m, dtype=torch.float64, device=dev)
-    qp, keep = _qp(A, b, c, q, A_lo, A_t)
+    qp, keep = _qp(A, b, c, q, A_lo, A_t, units=units)
     o = _ipm_opts(ell, **kw)
     info = nys_ipm_info()
     rc = lib.ipm_solve(h, C.byref(qp), C.byref(o), _ptr(x), _ptr(y), _ptr(z), C.byref(info))

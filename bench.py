@@ -220,7 +220,8 @@ def compare_svm(nys, args):
     import torch
     from instances import svm_instance
     d, n, ell = SVM_SHAPES[args.workload]
-    S = svm_instance(d, n, seed=args.seed, device="cuda", dtype=torch.float32)
+    S = svm_instance(d, n, seed=args.seed, device="cuda", dtype=torch.float32,
+                     unit_columns=not args.dense_identity)
     compare_box(nys, args, S, ell, TOL, {"d": d, "n": n})
 
 
@@ -232,7 +233,8 @@ def compare_portfolio(nys, args):
     from instances import portfolio_instance
     n, d, s_f, ell, tol = PORTFOLIO_SHAPES[args.workload]
     t0 = time.perf_counter()
-    S = portfolio_instance(n, d, s_f, seed=args.seed, device="cuda", dtype=torch.float32)
+    S = portfolio_instance(n, d, s_f, seed=args.seed, device="cuda", dtype=torch.float32,
+                           unit_columns=not args.dense_identity)
     torch.cuda.synchronize()
     log(f"{args.workload}: A {tuple(S['A'].shape)} FP32 generated in {time.perf_counter() - t0:.1f}s")
     compare_box(nys, args, S, ell, tol, {"n": n, "d": d, "s": s_f})
@@ -240,33 +242,57 @@ def compare_portfolio(nys, args):
 
 def compare_box(nys, args, S, ell, tol, shape):
     """Nys-IP-PMM, Chol-IP-PMM and CG-IP-PMM on one (P~) instance (FP32 A,
-    BF16 sketch): one warm-up solve, then one JSON line per solver."""
+    BF16 sketch; identity and slack blocks as unit columns unless
+    --dense-identity): one warm-up solve (skipped with --no-warmup-solve),
+    then one JSON line per solver with its convergence history (seconds,
+    rp_rel, rd_rel, mu per IP-PMM iteration).  An iteration limit
+    (--max-iter) ends a solve early; its line then carries the KKT reached."""
+    import numpy as np
     import torch
     A = S["A"]
+    units = S.get("units")
     A_lo = A.to(torch.bfloat16)
     A_t = nys.nys_transpose(A)
     box = (S["vtype"], S["u"])
-    extra = dict(verbose=args.verbose, max_iter=args.max_iter, A_t=A_t)
-    nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=tol, seed=args.seed, sketch_dtype="bf16",
-                      A_lo=A_lo, **extra)
-    torch.cuda.synchronize()
+    extra = dict(verbose=args.verbose, max_iter=args.max_iter, A_t=A_t, units=units)
+    if not args.no_warmup_solve:
+        try:
+            nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=tol, seed=args.seed,
+                              sketch_dtype="bf16", A_lo=A_lo, **extra)
+        except nys.NysError:
+            pass
+        torch.cuda.synchronize()
     for name, pre in (("Nys-IP-PMM", "nystrom"), ("Chol-IP-PMM", "pchol"), ("CG-IP-PMM", "none")):
+        if pre not in args.solvers.split(","):
+            continue
         log(f"{args.workload}: {name}")
+        tr = np.full((args.max_iter + 1, len(nys.TRACE_FIELDS)), np.nan)
         t0 = time.perf_counter()
+        err = None
         try:
             x, y, z, w, s, info = nys.ipm_solve_box(A, S["b"], S["c"], S["q"], *box, ell=ell, tol=tol,
-                                                    seed=args.seed, sketch_dtype="bf16",
+                                                    seed=args.seed, sketch_dtype="bf16", trace=tr,
                                                     A_lo=A_lo if pre == "nystrom" else None, precond=pre, **extra)
-        except nys.NysError as e:          # e.g. the iteration limit: report it
-            print(json.dumps({"solver": name, "workload": args.workload, "error": str(e)}), flush=True)
-            continue
+        except nys.NysError as e:          # the iteration limit and the like: report what was reached
+            err = str(e)
         torch.cuda.synchronize()
         t = time.perf_counter() - t0
-        rec = {"solver": name, "workload": args.workload, **shape, "m": A.shape[0], "n_vars": A.shape[1],
-               "ell": ell, "tol": tol, "seconds": round(t, 3), "status": info.status, "ipm_iters": info.iters,
-               "pcg_iters": info.pcg_iters_total, "kkt_rel": info.kkt_rel,
-               "time_split_ms": {"precond": round(info.t_sketch_ms, 1), "pcg": round(info.t_pcg_ms, 1),
-                                 "other": round(info.t_other_ms, 1)}}
+        K = int(np.sum(~np.isnan(tr[:, 0])))
+        f = {k: i for i, k in enumerate(nys.TRACE_FIELDS)}
+        rec = {"solver": name, "workload": args.workload, **shape, "m": A.shape[0],
+               "n_vars": A.shape[1] + (0 if units is None else units[0].numel()),
+               "unit_columns": 0 if units is None else units[0].numel(), "ell": ell, "tol": tol,
+               "seconds": round(t, 3)}
+        if err is None:
+            rec.update({"status": info.status, "ipm_iters": info.iters, "pcg_iters": info.pcg_iters_total,
+                        "kkt_rel": info.kkt_rel,
+                        "time_split_ms": {"precond": round(info.t_sketch_ms, 1), "pcg": round(info.t_pcg_ms, 1),
+                                          "other": round(info.t_other_ms, 1)}})
+        else:
+            rec["error"] = err
+        rec["history"] = [[round(tr[k, f["time_ms"]] / 1e3, 2), float(f"{tr[k, f['rp_rel']]:.2e}"),
+                           float(f"{tr[k, f['rd_rel']]:.2e}"), float(f"{tr[k, f['mu']]:.2e}"), int(tr[k, f["pcg"]])]
+                          for k in range(K)]
         print(json.dumps(rec), flush=True)
 
 
@@ -349,6 +375,9 @@ def main():
     ap.add_argument("--kernel-loop", type=int, default=0)
     ap.add_argument("--compare", action="store_true")
     ap.add_argument("--adaptive", action="store_true")
+    ap.add_argument("--dense-identity", action="store_true")
+    ap.add_argument("--no-warmup-solve", action="store_true")
+    ap.add_argument("--solvers", default="nystrom,pchol,none")
     ap.add_argument("--max-iter", type=int, default=100)
     ap.add_argument("--verbose", action="store_true")
     ap.add_argument("--summarize-trace", nargs=2, metavar=("DB", "OUT_MD"))

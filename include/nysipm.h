@@ -329,6 +329,9 @@ enum {
                           d_hat and lambda_hat_ell of the previous Nystrom
                           preconditioner at mu_k (NaN when no rule ran)       */
   NYS_TR_RULE_LAMLAST,
+  NYS_TR_RP,           /* rp_rel, rd_rel of the stopping test at iteration k  */
+  NYS_TR_RD,
+  NYS_TR_TIME_MS,      /* milliseconds from entry to that test                */
   NYS_TRACE_FIELDS
 };
 

@@ -700,6 +700,7 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     inf.rd_rel = rd_rel;
     inf.ru_rel = ru_rel;
     inf.mu = mu;
+    const double t_test = ms_since(t_start);
     if (o.verbose)
       std::fprintf(stderr, "[nysipm] k=%d rp=%.2e rd=%.2e mu=%.2e rho=%.2e pcg_total=%d t=%.1fms ell=%d\n", k,
                    rp_rel, rd_rel, mu, rho, pcg_total, ms_since(t_start), ell_cur);
@@ -809,6 +810,9 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
       t[NYS_TR_PCG] = pcg_k;
       t[NYS_TR_RULE_DHAT] = rule_dhat;
       t[NYS_TR_RULE_LAMLAST] = rule_lam;
+      t[NYS_TR_RP] = rp_rel;
+      t[NYS_TR_RD] = rd_rel;
+      t[NYS_TR_TIME_MS] = t_test;
     }
     if (k == k_build) pcg_ref = pcg_k;
     pcg_prev = pcg_k;

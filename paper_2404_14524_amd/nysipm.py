@@ -395,7 +395,8 @@ def nys_newton_solve(A, q, x, z, rho, delta, r_d, r_p, r_xz, P: Optional[Precond
 PRECONDS = {"nystrom": 0, "none": 1, "pchol": 2}
 ELL_RULES = {"fixed": 0, "deff": 1, "theorem": 2}
 # fields of one record of the per-iteration trace (NYS_TR_*)
-TRACE_FIELDS = ("k", "mu", "delta", "ell", "built", "d_hat", "lam_last", "pcg", "rule_d_hat", "rule_lam_last")
+TRACE_FIELDS = ("k", "mu", "delta", "ell", "built", "d_hat", "lam_last", "pcg", "rule_d_hat", "rule_lam_last",
+                "rp_rel", "rd_rel", "time_ms")
 
 
 def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0, verbose=False,

@@ -205,3 +205,32 @@ def test_large_mixed_solve_and_adjoint_full_size(nys):
     assert np.all(np.abs(res_cols) <= 1e-8 * scale_cols), np.max(np.abs(res_cols) / scale_cols)
     del inst, A, A_lo
     torch.cuda.empty_cache()
+
+
+def test_normal_apply_full_size_portfolio_unit_columns(nys):
+    """The normal-equation operator of the portfolio form at its full size
+    (dense block 50101 x 80000 FP32, 50100 unit columns for -I_s and I_d):
+    every output entry against the FP64 oracle on the dense block plus the
+    unit columns' exact terms E diag(d_E) E^T v, in both pass-1 layouts."""
+    from instances import portfolio_instance
+    print("full-size normal_apply portfolio with unit columns", flush=True)
+    P = portfolio_instance(80000, 50000, 100, seed=0, device=DEV, dtype=torch.float32, unit_columns=True)
+    A = P["A"]
+    rows, vals = P["units"]
+    m, n = A.shape
+    k = rows.numel()
+    g = torch.Generator(device=DEV)
+    g.manual_seed(11)
+    d = torch.rand(n + k, generator=g, dtype=torch.float64, device=DEV) * 3.0
+    v = torch.randn(m, generator=g, dtype=torch.float64, device=DEV)
+    ref, bound = _oracle_normal_apply(A, d[:n].cpu().numpy(), 1e-3, v.cpu().numpy())
+    r, vv, dd, vh = rows.cpu().numpy(), vals.cpu().numpy(), d[n:].cpu().numpy(), v.cpu().numpy()
+    unit = np.zeros(m)
+    unit[r] = vv * vv * dd * vh[r]
+    ref = ref + unit
+    bound = bound + np.abs(unit)
+    for A_t in (None, nys.nys_transpose(A)):
+        out = nys.nys_normal_apply(A, d, 1e-3, v, A_t=A_t, units=P["units"]).cpu().numpy()
+        assert np.all(np.abs(out - ref) <= 1e-11 * bound + 1e-300)
+    del P, A
+    torch.cuda.empty_cache()

@@ -508,11 +508,12 @@ def ipm_solve(A: torch.Tensor, b: torch.Tensor, c: torch.Tensor, q: torch.Tensor
 
 
 def ipm_adjoint(A, b, c, q, x, y, z, rho, delta, g, ell, A_lo=None, want=("c", "b", "q", "A"),
-                A_t=None, **kw):
+                A_t=None, units=None, **kw):
     """Gradients of L with dL/dx = g through the KKT conditions.  Returns
-    (dict of requested gradients, nys_pcg_info)."""
+    (dict of requested gradients, nys_pcg_info).  (The library rejects unit
+    columns here.)"""
     lib, h = _handle(A.device)
-    m, n = A.shape
+    m, n = A.shape[0], ncols(A, units)
     dev = A.device
     for t, k, nm in ((b, m, "b"), (c, n, "c"), (q, n, "q"), (x, n, "x"), (z, n, "z"), (y, m, "y"),
                      (g, n, "g")):
@@ -526,7 +527,7 @@ def ipm_adjoint(A, b, c, q, x, y, z, rho, delta, g, ell, A_lo=None, want=("c", "
         out["q"] = torch.empty(n, dtype=torch.float64, device=dev)
     if "A" in want:
         out["A"] = torch.empty((m, n), dtype=torch.float64, device=dev)
-    qp, keep = _qp(A, b, c, q, A_lo, A_t)
+    qp, keep = _qp(A, b, c, q, A_lo, A_t, units=units)
     kw.pop("tol", None)
     o = _ipm_opts(ell, **kw)
     info = nys_pcg_info()

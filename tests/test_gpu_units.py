@@ -252,3 +252,54 @@ def test_units_rejected_when_malformed(nys):
         nys.nys_normal_apply(_t(A), _t(d), 1.0, _t(v), units=(_t(rows, torch.int64), _t(vals)))
     with pytest.raises(ValueError):            # d must cover the unit columns too
         nys.nys_normal_apply(_t(A), _t(d[:30]), 1.0, _t(v), units=_units(rows, vals))
+
+
+def test_ipm_solve_box_units_with_rules_reuse_and_trace(nys):
+    """Unit columns together with the sketch-size rule, reuse and the trace
+    on the (P~) solver: the oracle's optimum, decisions that follow the rules,
+    and per-iteration residuals recorded."""
+    from instances import portfolio_instance
+    from oracle import boxqp
+    P = portfolio_instance(600, 300, 12, seed=4)
+    U = portfolio_instance(600, 300, 12, seed=4, unit_columns=True)
+    npd = {k: v.numpy() for k, v in P.items()}
+    ref = boxqp.solve(npd["A"], npd["b"], npd["c"], npd["q"], npd["u"], npd["vtype"], tol=1e-11)
+    tr = np.full((100, len(nys.TRACE_FIELDS)), np.nan)
+    x, y, z, w, s, info = nys.ipm_solve_box(U["A"].to(DEV), *(U[k].to(DEV) for k in ("b", "c", "q", "vtype", "u")),
+                                            ell=20, tol=1e-8, seed=3, units=tuple(t.to(DEV) for t in U["units"]),
+                                            ell_rule="deff", ell_min=8, ell_max=80, reuse_max_age=2, trace=tr)
+    assert info.status == 0, (info.kkt_rel, info.iters)
+    assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
+    K = info.iters
+    f = {k: i for i, k in enumerate(nys.TRACE_FIELDS)}
+    assert np.all(np.isfinite(tr[:K, f["rp_rel"]])) and np.all(np.diff(tr[:K, f["time_ms"]]) > 0)
+    ells = tr[:K, f["ell"]].astype(int)
+    assert np.all((ells >= 8) & (ells <= 80))
+    built = tr[:K, f["built"]] == 1.0
+    assert built[0] and int(built.sum()) == info.builds
+    gaps = np.diff(np.flatnonzero(np.append(built, True)))
+    assert np.all(gaps <= 2)                         # never older than the maximal age
+
+
+def test_units_with_caller_bf16_copy(nys):
+    """A caller-supplied BF16 copy of the dense block is combined with A's
+    unit columns for the sketch (the copy itself carries none)."""
+    from instances import svm_instance
+    U = svm_instance(30, 300, seed=5, unit_columns=True, dtype=torch.float32)
+    A = U["A"].to(DEV)
+    args = [U[k].to(DEV) for k in ("b", "c", "q", "vtype", "u")]
+    un = tuple(t.to(DEV) for t in U["units"])
+    x1, *_, i1 = nys.ipm_solve_box(A, *args, ell=10, tol=1e-7, seed=1, sketch_dtype="bf16", units=un)
+    x2, *_, i2 = nys.ipm_solve_box(A, *args, ell=10, tol=1e-7, seed=1, sketch_dtype="bf16", units=un,
+                                   A_lo=A.to(torch.bfloat16))
+    assert i1.status == 0 and i2.status == 0
+    assert torch.equal(x1, x2) and i1.pcg_iters_total == i2.pcg_iters_total
+
+
+def test_adjoint_rejects_units(nys):
+    A, rows, vals, d, v = _case(20, 30, 5, seed=2)
+    n = 35
+    vec = torch.ones(n, dtype=torch.float64, device=DEV)
+    with pytest.raises(nys.NysError):
+        nys.ipm_adjoint(_t(A), torch.ones(20, dtype=torch.float64, device=DEV), vec, vec, vec, torch.zeros(
+            20, dtype=torch.float64, device=DEV), vec, 1e-6, 1e-6, vec, ell=5, units=_units(rows, vals))

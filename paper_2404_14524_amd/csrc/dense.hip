@@ -277,49 +277,203 @@ __global__ __launch_bounds__(DB) void k_chol_upper_blocked(double* G, int ell, i
 
 // X = C^{-1} for upper-triangular C, one wave per column: column j solves
 // C x = e_j by back substitution, x_i = -(sum_{k=i+1..j} C[i][k] x_k) / C[i][i].
-// Lane l keeps x_k for k = l, l+64, ... in registers (ell <= 64*TRI_CH); the row
+// Lane l keeps x_k for k = l, l+64, ... in registers (ell <= 64*CH); the row
 // of C for the next step is loaded while the current one is reduced.
-constexpr int TRI_CH = 16;
 constexpr int TRI_WAVES = 4;
+template <int CH>
 __global__ __launch_bounds__(TRI_WAVES * NYS_WAVE) void k_tri_inv_cols(const double* C, double* X, int ell) {
   const int lane = threadIdx.x % NYS_WAVE;
   const int j = blockIdx.x * TRI_WAVES + threadIdx.x / NYS_WAVE;
   if (j >= ell) return;                  // no block-level synchronisation below
-  double x[TRI_CH];
+  double x[CH];
 #pragma unroll
-  for (int t = 0; t < TRI_CH; ++t) x[t] = 0.0;
+  for (int t = 0; t < CH; ++t) x[t] = 0.0;
   const double xj = 1.0 / C[(int64_t)j * ell + j];
 #pragma unroll
-  for (int t = 0; t < TRI_CH; ++t)
+  for (int t = 0; t < CH; ++t)
     if (t * NYS_WAVE + lane == j) x[t] = xj;
-  double cn[TRI_CH];
+  double cn[CH];
   auto load_row = [&](int i, double* cr) {
 #pragma unroll
-    for (int t = 0; t < TRI_CH; ++t) {
+    for (int t = 0; t < CH; ++t) {
       const int k = t * NYS_WAVE + lane;
       cr[t] = (k > i && k <= j) ? C[(int64_t)i * ell + k] : 0.0;
     }
   };
   if (j > 0) load_row(j - 1, cn);
   for (int i = j - 1; i >= 0; --i) {
-    double cr[TRI_CH];
+    double cr[CH];
 #pragma unroll
-    for (int t = 0; t < TRI_CH; ++t) cr[t] = cn[t];
+    for (int t = 0; t < CH; ++t) cr[t] = cn[t];
     const double cii = C[(int64_t)i * ell + i];
     if (i > 0) load_row(i - 1, cn);
     double s = 0.0;
 #pragma unroll
-    for (int t = 0; t < TRI_CH; ++t) s = fma(cr[t], x[t], s);
+    for (int t = 0; t < CH; ++t) s = fma(cr[t], x[t], s);
     s = wave_sum_dpp(s);
     const double xi = -s / cii;
 #pragma unroll
-    for (int t = 0; t < TRI_CH; ++t)
+    for (int t = 0; t < CH; ++t)
       if (t * NYS_WAVE + lane == i) x[t] = xi;
   }
 #pragma unroll
-  for (int t = 0; t < TRI_CH; ++t) {
+  for (int t = 0; t < CH; ++t) {
     const int k = t * NYS_WAVE + lane;
     if (k < ell) X[(int64_t)k * ell + j] = x[t];
+  }
+}
+
+// ---------------------------------------------------------------- Cholesky across workgroups
+// G = C^T C, C upper, for larger ell: right-looking by panels of CP rows.  Per
+// panel: the CP x CP diagonal block is factored by one block in LDS, the row
+// panel C[k0:k0+nb, k0+nb:] = C_kk^{-T} G[k0:k0+nb, k0+nb:] is solved one
+// column per thread, and the trailing upper triangle is updated in 64 x 64
+// tiles by as many blocks as there are tiles.  Arithmetic per entry is the
+// same as the one-block kernels; only the order of the panel sums differs.
+constexpr int CP = 32;                   // panel rows
+constexpr int CT = 64;                   // trailing-update tile
+
+// upper triangle := (G + G^T)/2 (the lower triangle is only read)
+__global__ __launch_bounds__(NYS_BLOCK) void k_chol_sym(double* G, int ell) {
+  const int64_t total = (int64_t)ell * ell;
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    const int i = (int)(idx / ell), j = (int)(idx % ell);
+    if (i < j) G[idx] = 0.5 * (G[idx] + G[(int64_t)j * ell + i]);
+  }
+}
+
+// diagonal += shift_abs + shift_rel * trace; *fail = 0 (one block)
+__global__ __launch_bounds__(NYS_BLOCK) void k_chol_shift(double* G, int ell, double shift_abs, double shift_rel,
+                                                          double* fail) {
+  __shared__ double red[NYS_BLOCK / NYS_WAVE];
+  double tr[1] = {0.0};
+  for (int i = threadIdx.x; i < ell; i += NYS_BLOCK) tr[0] += G[(int64_t)i * ell + i];
+  block_sum<1>(tr, red);
+  const double shift = shift_abs + shift_rel * tr[0];
+  for (int i = threadIdx.x; i < ell; i += NYS_BLOCK) G[(int64_t)i * ell + i] += shift;
+  if (threadIdx.x == 0) *fail = 0.0;
+}
+
+// factor the nb x nb diagonal block at k0 (nb <= CP) in LDS; *fail = 1 on a
+// pivot that is not positive and finite
+__global__ __launch_bounds__(NYS_BLOCK) void k_chol_diag(double* G, int ell, int k0, int nb, double* fail) {
+  __shared__ double P[CP * CP];
+  const int tid = threadIdx.x;
+  for (int idx = tid; idx < nb * nb; idx += NYS_BLOCK) {
+    const int r = idx / nb, c = idx % nb;
+    P[r * CP + c] = G[(int64_t)(k0 + r) * ell + k0 + c];
+  }
+  __syncthreads();
+  bool bad = false;
+  for (int kk = 0; kk < nb; ++kk) {
+    const double g = P[kk * CP + kk];
+    if (!(g > 0.0) || !isfinite(g)) {    // uniform: every thread read the same g
+      bad = true;
+      break;
+    }
+    const double piv = sqrt(g);
+    __syncthreads();
+    for (int c = kk + 1 + tid; c < nb; c += NYS_BLOCK) P[kk * CP + c] /= piv;
+    if (tid == 0) P[kk * CP + kk] = piv;
+    __syncthreads();
+    const int rows = nb - kk - 1;
+    for (int idx = tid; idx < rows * nb; idx += NYS_BLOCK) {
+      const int r = kk + 1 + idx / nb, c = idx % nb;
+      if (c >= r) P[r * CP + c] -= P[kk * CP + r] * P[kk * CP + c];
+    }
+    __syncthreads();
+  }
+  if (bad) {
+    if (tid == 0) *fail = 1.0;
+    return;
+  }
+  for (int idx = tid; idx < nb * nb; idx += NYS_BLOCK) {
+    const int r = idx / nb, c = idx % nb;
+    G[(int64_t)(k0 + r) * ell + k0 + c] = c >= r ? P[r * CP + c] : 0.0;
+  }
+}
+
+// row panel: for every column c >= k0 + nb, x = C_kk^{-T} G[k0:k0+nb, c] by
+// forward substitution (C_kk^T is lower triangular), one column per thread
+__global__ __launch_bounds__(NYS_BLOCK) void k_chol_row(double* G, int ell, int k0, int nb) {
+  __shared__ double Ck[CP * CP];
+  for (int idx = threadIdx.x; idx < nb * nb; idx += NYS_BLOCK) {
+    const int r = idx / nb, c = idx % nb;
+    Ck[r * CP + c] = G[(int64_t)(k0 + r) * ell + k0 + c];
+  }
+  __syncthreads();
+  const int c = k0 + nb + blockIdx.x * NYS_BLOCK + threadIdx.x;
+  if (c >= ell) return;
+  double x[CP];
+#pragma unroll
+  for (int r = 0; r < CP; ++r) {
+    if (r < nb) {
+      double s = G[(int64_t)(k0 + r) * ell + c];
+#pragma unroll
+      for (int q = 0; q < r; ++q) s -= Ck[q * CP + r] * x[q];
+      x[r] = s / Ck[r * CP + r];
+      G[(int64_t)(k0 + r) * ell + c] = x[r];
+    }
+  }
+}
+
+// trailing update: G[i][j] -= sum_q C[k0+q][i] C[k0+q][j] for t0 <= i <= j < ell,
+// t0 = k0 + nb, over the upper tiles (ti <= tj) of a CT x CT tiling; each
+// thread owns a 4 x 4 piece of its block's tile
+__global__ __launch_bounds__(NYS_BLOCK) void k_chol_update(double* G, int ell, int k0, int nb) {
+  static_assert(NYS_BLOCK == (CT / 4) * (CT / 4), "one 4 x 4 piece of the tile per thread");
+  __shared__ double Pi[CP * CT];
+  __shared__ double Pj[CP * CT];
+  const int t0 = k0 + nb;
+  const int nt = (ell - t0 + CT - 1) / CT;
+  // blockIdx.x -> (ti, tj), ti <= tj, row by row of the upper tile triangle
+  int b = blockIdx.x, ti = 0;
+  while (b >= nt - ti) {
+    b -= nt - ti;
+    ++ti;
+  }
+  const int tj = ti + b;
+  const int i0 = t0 + ti * CT, j0 = t0 + tj * CT;
+  for (int idx = threadIdx.x; idx < nb * CT; idx += NYS_BLOCK) {
+    const int q = idx / CT, a = idx % CT;
+    const int64_t row = (int64_t)(k0 + q) * ell;
+    Pi[q * CT + a] = i0 + a < ell ? G[row + i0 + a] : 0.0;
+    Pj[q * CT + a] = j0 + a < ell ? G[row + j0 + a] : 0.0;
+  }
+  __syncthreads();
+  const int ai = (threadIdx.x / 16) * 4, bj = (threadIdx.x % 16) * 4;
+  double acc[4][4] = {};
+  for (int q = 0; q < nb; ++q) {
+    double u[4], v[4];
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      u[e] = Pi[q * CT + ai + e];
+      v[e] = Pj[q * CT + bj + e];
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+#pragma unroll
+      for (int f = 0; f < 4; ++f) acc[e][f] = fma(u[e], v[f], acc[e][f]);
+  }
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int i = i0 + ai + e;
+    if (i >= ell) continue;
+#pragma unroll
+    for (int f = 0; f < 4; ++f) {
+      const int j = j0 + bj + f;
+      if (j < ell && j >= i) G[(int64_t)i * ell + j] -= acc[e][f];
+    }
+  }
+}
+
+__global__ __launch_bounds__(NYS_BLOCK) void k_chol_lower_zero(double* G, int ell) {
+  const int64_t total = (int64_t)ell * ell;
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total;
+       idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    const int i = (int)(idx / ell), j = (int)(idx % ell);
+    if (i > j) G[idx] = 0.0;
   }
 }
 
@@ -553,6 +707,28 @@ int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64
 }
 
 int chol_upper(nys_handle h, double* G, int ell, double shift_abs, double shift_rel, double* fail) {
+  if (ell >= 128) {
+    // across workgroups (one block would update the whole trailing triangle
+    // for each of ell/CP panels)
+    const unsigned gsq = (unsigned)std::min<int64_t>(((int64_t)ell * ell + NYS_BLOCK - 1) / NYS_BLOCK, 4096);
+    hipLaunchKernelGGL(k_chol_sym, dim3(gsq), dim3(NYS_BLOCK), 0, h->stream, G, ell);
+    hipLaunchKernelGGL(k_chol_shift, dim3(1), dim3(NYS_BLOCK), 0, h->stream, G, ell, shift_abs, shift_rel, fail);
+    for (int k0 = 0; k0 < ell; k0 += CP) {
+      const int nb = std::min(CP, ell - k0);
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(NYS_BLOCK), 0, h->stream, G, ell, k0, nb, fail);
+      const int rest = ell - k0 - nb;
+      if (rest > 0) {
+        hipLaunchKernelGGL(k_chol_row, dim3((unsigned)((rest + NYS_BLOCK - 1) / NYS_BLOCK)), dim3(NYS_BLOCK), 0,
+                           h->stream, G, ell, k0, nb);
+        const int nt = (rest + CT - 1) / CT;
+        hipLaunchKernelGGL(k_chol_update, dim3((unsigned)(nt * (nt + 1) / 2)), dim3(NYS_BLOCK), 0, h->stream, G,
+                           ell, k0, nb);
+      }
+    }
+    hipLaunchKernelGGL(k_chol_lower_zero, dim3(gsq), dim3(NYS_BLOCK), 0, h->stream, G, ell);
+    NYS_LAUNCH_CHECK(h);
+    return NYS_OK;
+  }
   // panel height: the largest power of two <= 32 whose NB x ell panel fits in
   // 60 KB of LDS (the kernel's static LDS and 64 KB per block stay clear)
   int nb = 32;
@@ -568,9 +744,13 @@ int chol_upper(nys_handle h, double* G, int ell, double shift_abs, double shift_
 }
 
 int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell) {
-  if (ell <= TRI_CH * NYS_WAVE) {
-    hipLaunchKernelGGL(k_tri_inv_cols, dim3((unsigned)((ell + TRI_WAVES - 1) / TRI_WAVES)),
-                       dim3(TRI_WAVES * NYS_WAVE), 0, h->stream, C, Cinv, ell);
+  const dim3 g((unsigned)((ell + TRI_WAVES - 1) / TRI_WAVES)), b(TRI_WAVES * NYS_WAVE);
+  if (ell <= 16 * NYS_WAVE) {
+    hipLaunchKernelGGL(k_tri_inv_cols<16>, g, b, 0, h->stream, C, Cinv, ell);
+  } else if (ell <= 32 * NYS_WAVE) {
+    hipLaunchKernelGGL(k_tri_inv_cols<32>, g, b, 0, h->stream, C, Cinv, ell);
+  } else if (ell <= 64 * NYS_WAVE) {
+    hipLaunchKernelGGL(k_tri_inv_cols<64>, g, b, 0, h->stream, C, Cinv, ell);
   } else {
     hipLaunchKernelGGL(k_tri_inv_upper, dim3(1), dim3(DB), 0, h->stream, C, Cinv, ell);
   }

@@ -141,8 +141,12 @@ def _nhat(U, lam):
     return (U * lam) @ U.T
 
 
-@pytest.mark.parametrize("m,n,ell", [(120, 300, 10), (700, 2000, 64), (1500, 4000, 100)])
+@pytest.mark.parametrize("m,n,ell", [(120, 300, 10), (700, 2000, 64), (1500, 4000, 100), (1200, 3000, 300),
+                                     (1300, 3000, 1100), (1800, 3600, 1600)])
 def test_sketch_fp64_parity(nys, m, n, ell):
+    """Algorithm 1 in FP64 against the oracle; the larger sizes take the
+    multi-workgroup Cholesky (ell >= 128) and the register-chunked triangular
+    inverse beyond 1024 columns."""
     print(f"sketch {m}x{n} ell={ell}", flush=True)
     inst = make_instance("lowrank_5000x20000", seed=11, m=m, n=n, rank=max(ell // 2, 4))
     A = inst.A.double().numpy()
@@ -153,7 +157,8 @@ def test_sketch_fp64_parity(nys, m, n, ell):
     Omq = nystrom.orthonormalize(Om)
     Uo, lo, nuo = nystrom.nystrom(lambda V: A @ (d[:, None] * (A.T @ V)), Omq)
     Ug, lg = _np(P.U), _np(P.lam)
-    np.testing.assert_allclose(Ug.T @ Ug, np.eye(ell), atol=1e-12)
+    # orthogonality of Cholesky-QR-based bases: a few ell eps
+    np.testing.assert_allclose(Ug.T @ Ug, np.eye(ell), atol=max(1e-12, 10 * ell * np.finfo(float).eps))
     assert np.all(np.diff(lg) <= 0) and np.all(lg >= 0)
     scale = lo[0]
     np.testing.assert_allclose(lg, lo, rtol=1e-8, atol=1e-10 * scale)

@@ -652,3 +652,34 @@ def test_portfolio_bruteforce_matches_a_library_solver():
                        options=dict(ftol=1e-14, maxiter=500))
         assert res.success
         np.testing.assert_allclose(res.x, ref["x"], atol=1e-5)
+
+
+# ---------------------------------------------------------------- instance layouts
+
+def _dense_from_units(Ad, rows, vals):
+    m, n = Ad.shape
+    E = np.zeros((m, len(rows)))
+    E[rows, np.arange(len(rows))] = vals
+    return np.hstack([Ad, E])
+
+
+def test_unit_column_layouts_match_the_dense_instances():
+    """The generators' unit-column layouts describe the same problems as
+    their dense layouts: the portfolio form column for column, the SVM form
+    with the variables reordered from [v; p] to [p; v]."""
+    from instances import portfolio_instance, svm_instance
+    P = portfolio_instance(50, 20, 4, seed=3)
+    U = portfolio_instance(50, 20, 4, seed=3, unit_columns=True)
+    rows, vals = (t.numpy() for t in U["units"])
+    assert np.all(np.diff(rows) > 0)
+    np.testing.assert_array_equal(_dense_from_units(U["A"].numpy(), rows, vals), P["A"].numpy())
+    for k in ("b", "c", "q", "u", "vtype"):
+        np.testing.assert_array_equal(U[k].numpy(), P[k].numpy())
+    d, n = 12, 40
+    S = svm_instance(d, n, seed=6)
+    V = svm_instance(d, n, seed=6, unit_columns=True)
+    perm = np.concatenate([np.arange(d, d + n), np.arange(d)])
+    rows, vals = (t.numpy() for t in V["units"])
+    np.testing.assert_array_equal(_dense_from_units(V["A"].numpy(), rows, vals), S["A"].numpy()[:, perm])
+    for k in ("c", "q", "u", "vtype"):
+        np.testing.assert_array_equal(V[k].numpy(), S[k].numpy()[perm])

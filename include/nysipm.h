@@ -367,6 +367,17 @@ typedef struct {
                                iteration that reaches the Newton solve (later
                                iterations are not recorded)                    */
   int32_t trace_len;
+  /* The direction of the predictor-corrector scheme (Algorithm 6) is the sum
+     of the predictor and corrector steps.  0 (default): it is computed as one
+     solve with the summed right-hand side (r_d, r_p, r_u of the predictor,
+     R_xz = -XZ + mu~ - dx_p dz_p, R_ws likewise), started from the predictor's
+     dy, which is the same direction by linearity; the predictor itself, used
+     only for the step lengths and mu_aff, is then solved to a relative
+     residual of predictor_rtol (<= 0: 1e-3) or the usual inner tolerance,
+     whichever is looser.  1: the two solves as printed, both to the inner
+     tolerance, then added.                                                    */
+  int32_t separate_corrector;
+  double predictor_rtol;
 } nys_ipm_opts;
 
 typedef struct {

@@ -176,8 +176,8 @@ struct PcgCfg {
   double rtol = 1e-10, atol = 0.0;
   int maxit = 0, replace_every = 100, poll_every = 8;
   // mu rule of the interior-point inner solves (mu_abs >= 0):
-  // tol = max(floor_rel ||rhs||, min(rtol ||rhs||, mu_abs))
-  double mu_abs = -1.0, floor_rel = 1e-12;
+  // tol = max(floor_rel ||rhs||, min(rtol ||rhs||, mu_abs)), then at least loose_rel ||rhs||
+  double mu_abs = -1.0, floor_rel = 1e-12, loose_rel = 0.0;
 };
 
 PcgCfg pcg_cfg(const nys_pcg_opts* o, int64_t m) {
@@ -230,9 +230,9 @@ int pcg_run(nys_handle h, const nys_matrix* A, const double* d, double delta, co
   NYS_CHECK(dot(h, rhs, rhs, m, sc + SC_RED0));
   NYS_CHECK(read_scalars(h, SC_RED0, 1));
   const double bnorm = std::sqrt(h->hscal[SC_RED0]);
-  const double tol = cfg.mu_abs >= 0
-                         ? std::max(cfg.floor_rel * bnorm, std::min(cfg.rtol * bnorm, cfg.mu_abs))
-                         : std::max(cfg.rtol * bnorm, cfg.atol);
+  const double tol = std::max(cfg.loose_rel * bnorm,
+                              cfg.mu_abs >= 0 ? std::max(cfg.floor_rel * bnorm, std::min(cfg.rtol * bnorm, cfg.mu_abs))
+                                              : std::max(cfg.rtol * bnorm, cfg.atol));
 
   // true residual r = rhs - M y into `dst`, ||.||^2 -> sc[SC_RED0 + 1]
   auto true_residual = [&](double* dst) -> int {
@@ -508,7 +508,7 @@ struct ScalingF {
 int newton_run(nys_handle h, const nys_matrix* A, const double* x, const double* z, const double* D,
                double delta, const Precond& P, const double* rd, const double* rp, const double* rxz,
                const PcgCfg& cfg, double* dx, double* dy, double* dz, nys_pcg_info* info,
-               const BoxNewton& bx = BoxNewton{}) {
+               const BoxNewton& bx = BoxNewton{}, const double* dy_guess = nullptr) {
   const int64_t m = A->m, n = ncols(A);
   double* base;
   NYS_CHECK(ws(h, WS_NEWTON, (size_t)2 * n + m + 8, &base));
@@ -526,7 +526,9 @@ int newton_run(nys_handle h, const nys_matrix* A, const double* x, const double*
     g2.x0 = nullptr;
   }
   NYS_CHECK(gemv_n(h, g2));
-  int rc = pcg_run(h, A, D, delta, P, xi, dy, true, cfg, info);
+  // a warm start (the predictor's dy for the combined corrector solve)
+  if (dy_guess) NYS_CHECK(copy(h, dy, dy_guess, m));
+  int rc = pcg_run(h, A, D, delta, P, xi, dy, dy_guess == nullptr, cfg, info);
   if (rc < 0) return rc;
   GemvT g1;
   g1.A = A;
@@ -847,13 +849,14 @@ int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double*
                double delta, const double* U, const double* lam, int ell, const nys_pchol* pch,
                const double* rd, const double* rp, const double* rxz, const nys_pcg_opts* o,
                double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info,
-               const BoxNewton& bx) {
+               const BoxNewton& bx, double loose_rel, const double* dy_guess) {
   Precond pc{U, lam, U ? ell : 0, pch};
   PcgCfg cfg = pcg_cfg(o, A->m);
   cfg.rtol = (o && o->rtol > 0) ? o->rtol : 1e-2;
   cfg.atol = 0.0;
   cfg.mu_abs = mu_abs;
-  return newton_run(h, A, x, z, D, delta, pc, rd, rp, rxz, cfg, dx, dy, dz, info, bx);
+  cfg.loose_rel = loose_rel;
+  return newton_run(h, A, x, z, D, delta, pc, rd, rp, rxz, cfg, dx, dy, dz, info, bx, dy_guess);
 }
 int grad_A_rank2(nys_handle h, int64_t m, int64_t n, const double* y, const double* u1,
                  const double* u2, const double* x, double* G) {

@@ -36,7 +36,7 @@ int ipm_newton(nys_handle h, const nys_matrix* A, const double* x, const double*
                double delta, const double* U, const double* lam, int ell, const nys_pchol* pch,
                const double* rd, const double* rp, const double* rxz, const nys_pcg_opts* o,
                double mu_abs, double* dx, double* dy, double* dz, nys_pcg_info* info,
-               const BoxNewton& bx);
+               const BoxNewton& bx, double loose_rel = 0.0, const double* dy_guess = nullptr);
 int grad_A_rank2(nys_handle h, int64_t m, int64_t n, const double* y, const double* u1,
                  const double* u2, const double* x, double* G);
 
@@ -144,17 +144,22 @@ struct MuAff {        // (x + ap dx)^T (z + ad dz) over I, J plus (w + ap dw)^T 
     if (k == NYS_VAR_BOX) a[0] = fma(fma(ap, dw[j], w[j]), fma(ad, ds[j], s[j]), a[0]);
   }
 };
-struct CorrRxz {      // R_xz = mu~ - dxp .* dzp (I, J); R_ws = mu~ - dwp .* dsp (J)
+struct CorrRxz {      // R_xz = mu~ - dxp .* dzp (I, J); R_ws = mu~ - dwp .* dsp (J); with add: +=
   double* R;
   const double *dxp, *dzp;
   double mut;
   const int8_t* vt;
   double* Rws;
   const double *dwp, *dsp;
+  bool add;
   __device__ void operator()(int64_t j, double*, double*) const {
     const int k = kind_of(vt, j);
-    R[j] = k == NYS_VAR_FREE ? 0.0 : mut - dxp[j] * dzp[j];
-    if (Rws) Rws[j] = k == NYS_VAR_BOX ? mut - dwp[j] * dsp[j] : 0.0;
+    const double r = k == NYS_VAR_FREE ? 0.0 : mut - dxp[j] * dzp[j];
+    R[j] = add ? R[j] + r : r;
+    if (Rws) {
+      const double rw = k == NYS_VAR_BOX ? mut - dwp[j] * dsp[j] : 0.0;
+      Rws[j] = add ? Rws[j] + rw : rw;
+    }
   }
 };
 struct AddTo {        // a += b
@@ -388,6 +393,8 @@ struct Opts {
   double reuse_growth = 1.5;
   double* trace = nullptr;
   int trace_len = 0;
+  bool separate_corrector = false;
+  double predictor_rtol = 1e-3;
 };
 
 // Workspace-backed partial Cholesky preconditioner for the comparator runs.
@@ -426,6 +433,8 @@ Opts read_opts(const nys_ipm_opts* o) {
   if (o->reuse_growth > 0) r.reuse_growth = o->reuse_growth;
   r.trace = o->trace;
   r.trace_len = o->trace_len;
+  r.separate_corrector = o->separate_corrector != 0;
+  if (o->predictor_rtol > 0) r.predictor_rtol = o->predictor_rtol;
   return r;
 }
 
@@ -743,8 +752,12 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     nys_pcg_info pi{};
     auto t0 = clk::now();
     const BoxNewton bxp = box ? BoxNewton{vt, w, s, Ru, Rws, dwp, dsp} : BoxNewton{};
+    // combined mode: the predictor only sets the step lengths and mu_aff, so a
+    // relative residual of predictor_rtol suffices; the direction itself comes
+    // from the one solve with the summed right-hand side below
+    const bool comb = !o.separate_corrector;
     int rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, ell_cur, pchp, Rd, Rp, Rxz, &o.pcg, tau, dxp, dyp, dzp,
-                        &pi, bxp);
+                        &pi, bxp, comb ? o.predictor_rtol : 0.0);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;
@@ -763,12 +776,18 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     const double mu_aff = cnt > 0 ? h->hscal[SC_RED0] / cnt : 0.0;
     const double mut = mu > 0 ? mu_aff * mu_aff * mu_aff / (mu * mu) : 0.0;
 
-    // corrector
-    NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut, vt, Rws, dwp, dsp}, nullptr));
+    // corrector.  Separate (the scheme as printed): solve with r_d = r_p = r_u = 0
+    // and R_xz = mu~ - dxp dzp, then add the two directions.  Combined: by
+    // linearity the sum is the solution of the system with the summed
+    // right-hand side (r_d, r_p, r_u of the predictor, R_xz = -XZ + mu~ -
+    // dxp dzp), solved once to the inner tolerance from the predictor's dy.
+    NYS_CHECK(map_reduce<0, 0>(h, n, CorrRxz{Rxz, dxp, dzp, mut, vt, Rws, dwp, dsp, comb}, nullptr));
     t0 = clk::now();
-    const BoxNewton bxc = box ? BoxNewton{vt, w, s, nullptr, Rws, dwc, dsc} : BoxNewton{};
-    rc = ipm_newton(h, A, x, z, D, delta, Un, lamh, ell_cur, pchp, nullptr, nullptr, Rxz, &o.pcg, tau, dxc, dyc,
-                    dzc, &pi, bxc);
+    const BoxNewton bxc = box ? BoxNewton{vt, w, s, comb ? Ru : nullptr, Rws, dwc, dsc} : BoxNewton{};
+    rc = comb ? ipm_newton(h, A, x, z, D, delta, Un, lamh, ell_cur, pchp, Rd, Rp, Rxz, &o.pcg, tau, dxc, dyc, dzc, &pi,
+                           bxc, 0.0, dyp)
+              : ipm_newton(h, A, x, z, D, delta, Un, lamh, ell_cur, pchp, nullptr, nullptr, Rxz, &o.pcg, tau, dxc,
+                           dyc, dzc, &pi, bxc);
     h->t_pcg += ms_since(t0);
     if (rc < 0) {
       status = rc;
@@ -778,19 +797,24 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     if (o.verbose)
       std::fprintf(stderr, "[nysipm]   corrector pcg: iters=%d status=%d |res|=%.2e alpha=(%.3f,%.3f) mu_aff=%.2e\n",
                    pi.iters, pi.status, pi.true_res, ap, ad, mu_aff);
-    NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dxp, dxc}, nullptr));
-    NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dzp, dzc}, nullptr));
-    NYS_CHECK(map_reduce<0, 0>(h, m, AddTo{dyp, dyc}, nullptr));
-    if (box) {
-      NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dwp, dwc}, nullptr));
-      NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dsp, dsc}, nullptr));
+    // the direction: the combined solve's, or predictor + corrector
+    double *fdx = dxc, *fdy = dyc, *fdz = dzc, *fdw = dwc, *fds = dsc;
+    if (!comb) {
+      NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dxp, dxc}, nullptr));
+      NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dzp, dzc}, nullptr));
+      NYS_CHECK(map_reduce<0, 0>(h, m, AddTo{dyp, dyc}, nullptr));
+      if (box) {
+        NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dwp, dwc}, nullptr));
+        NYS_CHECK(map_reduce<0, 0>(h, n, AddTo{dsp, dsc}, nullptr));
+      }
+      fdx = dxp, fdy = dyp, fdz = dzp, fdw = dwp, fds = dsp;
     }
-    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, dxp, z, dzp, vt, w, dwp, s, dsp}, sc + SC_RED0)));
+    NYS_CHECK((map_reduce<0, 2>(h, n, Ratio{x, fdx, z, fdz, vt, w, fdw, s, fds}, sc + SC_RED0)));
     NYS_CHECK(read_scalars(h, SC_RED0, 2));
     ap = STEP * std::min(1.0, h->hscal[SC_RED0]);
     ad = STEP * std::min(1.0, h->hscal[SC_RED0 + 1]);
-    NYS_CHECK((map_reduce<2, 0>(h, n, UpdXZ{x, z, zeta, dxp, dzp, ap, ad, vt, w, s, dwp, dsp}, sc + SC_RED0)));
-    NYS_CHECK((map_reduce<1, 0>(h, m, UpdY{y, lam, dyp, ad}, sc + SC_RED0 + 2)));
+    NYS_CHECK((map_reduce<2, 0>(h, n, UpdXZ{x, z, zeta, fdx, fdz, ap, ad, vt, w, s, fdw, fds}, sc + SC_RED0)));
+    NYS_CHECK((map_reduce<1, 0>(h, m, UpdY{y, lam, fdy, ad}, sc + SC_RED0 + 2)));
     NYS_CHECK(read_scalars(h, SC_RED0, 3));
     if (h->hscal[SC_RED0 + 1] + h->hscal[SC_RED0 + 2] > 0) {
       status = set_error(h, NYS_ENUMERIC, "ipm_solve: non-finite iterate at iteration %d", k);

@@ -705,3 +705,29 @@ def test_ipm_solve_box_portfolio(nys, precond, storage):
     assert meas["kkt"] <= 1e-8
     assert np.linalg.norm(_np(x) - ref["x"]) <= 1e-6 * np.linalg.norm(ref["x"])
     assert abs(_np(x)[:600].sum() - 1.0) <= 1e-8
+
+
+# ------------------------------------------------------------------ predictor-corrector forms
+
+@pytest.mark.parametrize("box", [False, True])
+def test_ipm_solve_combined_and_separate_corrector(nys, box):
+    """Algorithm 6's direction computed as predictor + corrector (two solves)
+    and as one solve with the summed right-hand side (the default, with a
+    loose predictor): both reach the oracle's optimum at KKT <= 1e-8."""
+    print(f"corrector forms box={box}", flush=True)
+    if box:
+        from oracle import boxqp
+        A, b, c, q, u, vt, xs, ys = _box_case(300, 1000, seed=8)
+        ref = boxqp.solve(A, b, c, q, u, vt, tol=1e-11)["x"]
+        args = (_t(A), _t(b), _t(c), _t(q), _t(vt, torch.int8), _t(u))
+        run = lambda **kw: nys.ipm_solve_box(*args, ell=20, tol=1e-8, seed=1, **kw)
+    else:
+        inst = make_instance("lowrank_5000x20000", seed=5, m=400, n=1600, rank=30)
+        A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+        ref = inst.x_star.numpy()
+        run = lambda **kw: nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=20, tol=1e-8, seed=1, **kw)
+    for kw in (dict(separate_corrector=True), dict(), dict(predictor_rtol=1e-4)):
+        out = run(**kw)
+        x, info = out[0], out[-1]
+        assert info.status == 0, (kw, info.kkt_rel)
+        assert np.linalg.norm(_np(x) - ref) <= 1e-6 * np.linalg.norm(ref), kw

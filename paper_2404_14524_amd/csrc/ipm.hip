@@ -394,7 +394,7 @@ struct Opts {
   double* trace = nullptr;
   int trace_len = 0;
   bool separate_corrector = false;
-  double predictor_rtol = 1e-3;
+  double predictor_rtol = 1e-4;
 };
 
 // Workspace-backed partial Cholesky preconditioner for the comparator runs.

@@ -11,7 +11,7 @@
 //   rho = delta = max(5e-10, min(rho, mu)).
 // * stopping test: max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
 // * inner tolerance: ||xi - M dy|| <= max(1e-12 ||xi||, min(1e-2 ||xi||, tau)) with
-//   tau = max(0.1 mu, 0.1 tol (1 + ||b||)), judged on the true residual (the
+//   tau = f max(mu, tol (1 + ||b||)), f = 0.5 by default, judged on the true residual (the
 //   theory asks for a residual of order mu; the floor keeps solves from being
 //   asked for accuracy that the primal-feasibility target cannot use).
 // * a fresh test matrix per iteration (Philox key = seed, counter = k), shared
@@ -395,6 +395,7 @@ struct Opts {
   int trace_len = 0;
   bool separate_corrector = false;
   double predictor_rtol = 1e-4;
+  double inner_factor = 0.5;
 };
 
 // Workspace-backed partial Cholesky preconditioner for the comparator runs.
@@ -435,6 +436,7 @@ Opts read_opts(const nys_ipm_opts* o) {
   r.trace_len = o->trace_len;
   r.separate_corrector = o->separate_corrector != 0;
   if (o->predictor_rtol > 0) r.predictor_rtol = o->predictor_rtol;
+  if (o->inner_factor > 0 && o->inner_factor < 1) r.inner_factor = o->inner_factor;
   return r;
 }
 
@@ -745,10 +747,11 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho, vt, Rws, Ru, qp->u, w, s}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, m, PredM{Rp, rp, y, lam, delta}, nullptr));
     // inner tolerance: max(1e-12 ||xi||, min(cap ||xi||, tau)), cap = pcg.rtol or 1e-2,
-    // tau = max(0.1 mu, 0.1 tol (1 + ||b||)): the normal-equation residual enters
-    // only the primal block of the Newton system (Proposition 3.1), so no solve is
-    // asked for a residual below a tenth of the primal-feasibility target.
-    const double tau = std::max(0.1 * mu, 0.1 * o.tol * (1.0 + bnorm));
+    // tau = f max(mu, tol (1 + ||b||)), f = inner_factor (0.5): the normal-equation
+    // residual enters only the primal block of the Newton system (Proposition 3.1),
+    // so no solve is asked for a residual below a fraction f of the
+    // primal-feasibility target.
+    const double tau = std::max(o.inner_factor * mu, o.inner_factor * o.tol * (1.0 + bnorm));
     nys_pcg_info pi{};
     auto t0 = clk::now();
     const BoxNewton bxp = box ? BoxNewton{vt, w, s, Ru, Rws, dwp, dsp} : BoxNewton{};

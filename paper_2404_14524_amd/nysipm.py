@@ -70,7 +70,7 @@ class nys_ipm_opts(C.Structure):
                 ("precond", C.c_int32), ("ell_rule", C.c_int32), ("ell_min", C.c_int32),
                 ("ell_max", C.c_int32), ("c_ell", C.c_double), ("reuse_max_age", C.c_int32),
                 ("reuse_growth", C.c_double), ("trace", C.c_void_p), ("trace_len", C.c_int32),
-                ("separate_corrector", C.c_int32), ("predictor_rtol", C.c_double)]
+                ("separate_corrector", C.c_int32), ("predictor_rtol", C.c_double), ("inner_factor", C.c_double)]
 
 
 class nys_ipm_info(C.Structure):
@@ -404,7 +404,7 @@ def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0,
               pcg_rtol=0.0, pcg_maxit=0, replace_every=0, poll_every=0,
               transposed_copy=True, precond="nystrom", ell_rule="fixed", ell_min=0, ell_max=0,
               c_ell=0.0, reuse_max_age=0, reuse_growth=0.0, trace=None, separate_corrector=False,
-              predictor_rtol=0.0) -> nys_ipm_opts:
+              predictor_rtol=0.0, inner_factor=0.0) -> nys_ipm_opts:
     """trace: None, or a C-contiguous float64 numpy array of shape
     (L, len(TRACE_FIELDS)) that receives one record per IP-PMM iteration k < L."""
     tp, tl = None, 0
@@ -417,7 +417,7 @@ def _ipm_opts(ell, tol=1e-6, max_iter=100, seed=0, sketch_dtype="f64", c_nu=1.0,
                         _pcg_opts(pcg_rtol, 0.0, pcg_maxit, replace_every, poll_every), int(verbose),
                         0 if transposed_copy else 1, PRECONDS[precond], ELL_RULES[ell_rule], ell_min,
                         ell_max, c_ell, reuse_max_age, reuse_growth, tp, tl, int(bool(separate_corrector)),
-                        predictor_rtol)
+                        predictor_rtol, inner_factor)
 
 
 def nys_deff_estimate(lam: torch.Tensor, mu: float) -> float:

@@ -142,7 +142,7 @@ def _nhat(U, lam):
 
 
 @pytest.mark.parametrize("m,n,ell", [(120, 300, 10), (700, 2000, 64), (1500, 4000, 100), (1200, 3000, 300),
-                                     (1300, 3000, 1100), (1800, 3600, 1600)])
+                                     (1300, 3000, 1100), (1800, 3600, 1600), (2200, 4400, 2100)])
 def test_sketch_fp64_parity(nys, m, n, ell):
     """Algorithm 1 in FP64 against the oracle; the larger sizes take the
     multi-workgroup Cholesky (ell >= 128) and the register-chunked triangular

@@ -211,7 +211,8 @@ SVM_SHAPES = {"svm_sensit": (100, 98528, 50), "svm_cifar10": (3072, 60000, 200),
 
 # The portfolio workload (section 5.1): n assets, d correlation constraints,
 # s factors, sketch size, tolerance.
-PORTFOLIO_SHAPES = {"portfolio_80000x50000": (80000, 50000, 100, 20, 1e-8)}
+PORTFOLIO_SHAPES = {"portfolio_80000x50000": (80000, 50000, 100, 20, 1e-8),
+                    "portfolio_20000x12500": (20000, 12500, 50, 20, 1e-8)}
 
 
 def compare_svm(nys, args):

@@ -400,7 +400,10 @@ typedef struct {
    Newton solve of Algorithm 5) for (P): initial point from the regularised
    (A A^T + 10 I) systems solved by Nystrom-PCG; rho_0 = delta_0 = 8; per
    iteration a fresh Nystrom preconditioner of N_k shared by predictor and
-   corrector; step lengths with factor 0.995; parameter update
+   corrector (see ell_rule and reuse_max_age for the alternatives); the
+   direction by one solve of the summed predictor and corrector systems (see
+   separate_corrector); Newton solves to ||xi - M dy|| <= inner_factor *
+   max(mu, tol (1 + ||b||)); step lengths with factor 0.995; parameter update
    rho = delta = max(5e-10, min(rho, mu)); stop when
    max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
    Outputs x, z (n) and y (m) FP64.  Returns NYS_OK, NYS_MAXIT, or an error.

@@ -406,8 +406,9 @@ def main():
                           args.command, args.out)
         return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only; multi-GPU runs are not supported "
-              "(the column-sharded design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py: runs on one GPU only; multi-GPU runs are not supported "
+              "(the path would shard A by columns with one all-reduce of the m-vector per operator apply)",
+              file=sys.stderr)
         sys.exit(2)
 
     import torch

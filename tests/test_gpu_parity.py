@@ -731,3 +731,47 @@ def test_ipm_solve_combined_and_separate_corrector(nys, box):
         x, info = out[0], out[-1]
         assert info.status == 0, (kw, info.kkt_rel)
         assert np.linalg.norm(_np(x) - ref) <= 1e-6 * np.linalg.norm(ref), kw
+
+
+# ------------------------------------------------------------------ initial point
+
+@pytest.mark.parametrize("case", ["gauss", "lowrank", "box", "box_units"])
+def test_initial_point_measures_match_the_oracle(nys, case):
+    """The supplement's initial point (reading 9; the regularised A A^T + 10 I
+    systems): the GPU's mu, rp_rel and rd_rel at k = 0 (from the trace) equal
+    the oracle's for the point it constructs, to the initial solves' accuracy."""
+    from oracle import boxqp
+    print(f"initial point {case}", flush=True)
+    tr = np.full((100, len(nys.TRACE_FIELDS)), np.nan)
+    f = {k: i for i, k in enumerate(nys.TRACE_FIELDS)}
+    if case in ("gauss", "lowrank"):
+        inst = (make_instance("gauss_200x500", seed=2) if case == "gauss"
+                else make_instance("lowrank_5000x20000", seed=2, m=300, n=1200, rank=20))
+        A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+        x0, y0, z0 = oipm.initial_point(A, b, c, q)
+        ref = problem.kkt_measure(A, b, c, q, x0, y0, z0)
+        nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=20, tol=1e-6, seed=0, trace=tr)
+    else:
+        A, b, c, q, u, vt, xs, ys = _box_case(120, 400, seed=6)
+        x0, y0, z0, w0, s0 = boxqp.initial_point(A, b, c, q, u, vt)
+        ref = boxqp.kkt_measure(A, b, c, q, u, vt, x0, y0, z0, w0, s0)
+        args = (_t(b), _t(c), _t(q), _t(vt, torch.int8), _t(u))
+        if case == "box":
+            nys.ipm_solve_box(_t(A), *args, ell=20, tol=1e-6, seed=0, trace=tr)
+        else:
+            # A with 40 slack columns on its last rows: unit columns on the GPU,
+            # written out densely for the oracle
+            m, n = A.shape
+            rows = np.arange(m - 40, m, dtype=np.int32)
+            F = np.hstack([A, np.zeros((m, 40))])
+            F[rows, n + np.arange(40)] = 1.0
+            vt2 = np.concatenate([vt, np.zeros(40, np.int8)])
+            q2, u2 = np.concatenate([q, np.full(40, 0.5)]), np.concatenate([u, np.zeros(40)])
+            c2 = np.concatenate([c, np.ones(40)])
+            x0, y0, z0, w0, s0 = boxqp.initial_point(F, b, c2, q2, u2, vt2)
+            ref = boxqp.kkt_measure(F, b, c2, q2, u2, vt2, x0, y0, z0, w0, s0)
+            nys.ipm_solve_box(_t(A), _t(b), _t(c2), _t(q2), _t(vt2, torch.int8), _t(u2), ell=20, tol=1e-6, seed=0,
+                              trace=tr, units=(_t(rows, torch.int32), _t(np.ones(40))))
+    for key in ("mu", "rp_rel", "rd_rel"):
+        got = tr[0, f[key]]
+        assert abs(got - ref[key]) <= 1e-7 * abs(ref[key]) + 1e-14, (key, got, ref[key])

@@ -775,3 +775,31 @@ def test_initial_point_measures_match_the_oracle(nys, case):
     for key in ("mu", "rp_rel", "rd_rel"):
         got = tr[0, f[key]]
         assert abs(got - ref[key]) <= 1e-7 * abs(ref[key]) + 1e-14, (key, got, ref[key])
+
+
+@pytest.mark.parametrize("case", ["qp", "box"])
+def test_first_iterations_follow_the_oracle(nys, case):
+    """With near-exact inner solves and the two-solve corrector, the GPU
+    driver's first IP-PMM iterations (step lengths, mu_aff, the corrector,
+    the parameter update) reproduce the oracle's: mu, rp_rel and rd_rel at
+    k = 0..4 agree to 1e-6 relative."""
+    from oracle import boxqp
+    print(f"first iterations {case}", flush=True)
+    tr = np.full((100, len(nys.TRACE_FIELDS)), np.nan)
+    f = {k: i for i, k in enumerate(nys.TRACE_FIELDS)}
+    hist = []
+    tight = dict(separate_corrector=True, inner_factor=1e-9, pcg_rtol=1e-13, pcg_maxit=5000, tol=1e-9, seed=0,
+                 trace=tr)
+    if case == "qp":
+        inst = make_instance("gauss_200x500", seed=3)
+        A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())
+        oipm.solve(A, b, c, q, tol=1e-9, history=hist)
+        nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=20, **tight)
+    else:
+        A, b, c, q, u, vt, xs, ys = _box_case(120, 400, seed=7)
+        boxqp.solve(A, b, c, q, u, vt, tol=1e-9, history=hist)
+        nys.ipm_solve_box(_t(A), _t(b), _t(c), _t(q), _t(vt, torch.int8), _t(u), ell=20, **tight)
+    for k in range(5):
+        for key in ("mu", "rp_rel", "rd_rel"):
+            got, ref = tr[k, f[key]], hist[k][key]
+            assert abs(got - ref) <= 1e-6 * abs(ref) + 1e-13, (k, key, got, ref)

@@ -803,3 +803,28 @@ def test_first_iterations_follow_the_oracle(nys, case):
         for key in ("mu", "rp_rel", "rd_rel"):
             got, ref = tr[k, f[key]], hist[k][key]
             assert abs(got - ref) <= 1e-6 * abs(ref) + 1e-13, (k, key, got, ref)
+
+
+# ------------------------------------------------------------------ autograd wrapper
+
+def test_autograd_wrapper_matches_the_adjoint(nys):
+    """x*(A, b, c, q) through torch.autograd: the gradients of
+    L = 1/2 ||x* - x_tgt||^2 with respect to b and c equal ipm_adjoint's for
+    g = x* - x_tgt, and A, q get none when not requested."""
+    from paper_2404_14524_amd.autograd import nys_qp
+    inst = make_instance("gauss_200x500", seed=4)
+    A, b, c, q = (_t(inst.A.double().numpy()), _t(inst.b.numpy()), _t(inst.c.numpy()), _t(inst.q.numpy()))
+    b.requires_grad_(True)
+    c.requires_grad_(True)
+    x = nys_qp(A, b, c, q, ell=20, tol=1e-9, seed=0)
+    tgt = x.detach() + 0.01 * torch.randn(x.shape, generator=torch.Generator(device=DEV).manual_seed(1),
+                                          dtype=torch.float64, device=DEV)
+    L = 0.5 * ((x - tgt) ** 2).sum()
+    gb, gc = torch.autograd.grad(L, (b, c))
+    x2, y2, z2, info = nys.ipm_solve(A, b.detach(), c.detach(), q, ell=20, tol=1e-9, seed=0)
+    assert torch.equal(x2, x.detach())
+    ref, _ = nys.ipm_adjoint(A, b.detach(), c.detach(), q, x2, y2, z2, info.rho, info.delta,
+                             (x2 - tgt).contiguous(), ell=20, seed=0, want=("b", "c"))
+    np.testing.assert_allclose(_np(gb), _np(ref["b"]), rtol=0, atol=1e-12 * (1 + np.abs(_np(ref["b"])).max()))
+    np.testing.assert_allclose(_np(gc), _np(ref["c"]), rtol=0, atol=1e-12 * (1 + np.abs(_np(ref["c"])).max()))
+    assert A.grad is None and q.grad is None

@@ -373,10 +373,9 @@ typedef struct {
      R_xz = -XZ + mu~ - dx_p dz_p, R_ws likewise), started from the predictor's
      dy, which is the same direction by linearity; the predictor itself, used
      only for the step lengths and mu_aff, is then solved to a relative
-     residual of predictor_rtol (<= 0: 1e-4) or the usual inner tolerance,
-     whichever is looser (1e-3 is faster on the low-rank QPs and slower on the
-     SVM form).  1: the two solves as printed, both to the inner tolerance,
-     then added.                                                               */
+     residual of predictor_rtol (<= 0: 1e-3) or the usual inner tolerance,
+     whichever is looser.  1: the two solves as printed, both to the inner
+     tolerance, then added.                                                    */
   int32_t separate_corrector;
   double predictor_rtol;
   /* inner tolerance of the Newton solves: ||xi - M dy|| <= max(f mu,

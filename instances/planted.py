@@ -248,7 +248,8 @@ def portfolio_instance(n: int = 80000, d: int = 50000, s: int = 100, seed: int =
     then slow decay), scaled so that the mean variance is 1 (sig2 = 0.1);
     F = G_s diag(sqrt(lam_{1..s} + sig2)), the exact rank-s truncation of
     Sigma, and Dg = diag(Sigma - F F^T) >= sig2 (1 - |G_{j,1..s}|^2); rows of M
-    ~ N(0, I); r ~ N(0, 1); u_p ~ U[0.05, 1] (x = 1/n is strictly feasible).
+    ~ N(0, I); r ~ N(0, 1); u_p ~ U[0.05, 1] (x = 1/n is strictly feasible once the largest
+    (M 1/n)_i, about 4.5/sqrt(n), is below 0.05, as at the paper's size).
     A holds the stored values (dtype); F and M of the returned parts are those
     values promoted to FP64.  Returns A, b, c, q, u, vtype and, with
     with_parts, F, Dg, M, u_p, r, gamma.  With unit_columns A holds only the

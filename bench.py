@@ -23,6 +23,10 @@ Modes:
   python bench.py --adaptive [--workload NAME]  # sketch size from the d_eff
                                     # estimate and preconditioner reuse against
                                     # the fixed size: one JSON line per variant
+  python bench.py --operator MxN [--ell L]      # the normal-equation operator and
+                                    # the BF16 sketch product alone on an m x n
+                                    # FP32 matrix (e.g. one column shard of a
+                                    # larger A): one JSON line of per-pass rates
   python bench.py --kernel-loop R   # only R normal-equation applies (pass 1 on a
                                     # transposed copy, as in the solver), a plain
                                     # copy and read-stream kernels of known size
@@ -322,6 +326,55 @@ def compare(nys, inst, args):
         print(json.dumps(rec), flush=True)
 
 
+def operator_shape(nys, shape: str, ell: int, reps: int, seed: int):
+    """The normal-equation operator and the BF16 matrix-core sketch product
+    (both with transposed copies of A, as in the solver) alone on a seeded Gaussian
+    FP32 m x n matrix: launches and rates per kernel class from the library's
+    HIP events, against the read-stream reference over the same matrix."""
+    import torch
+    m, n = (int(t) for t in shape.lower().split("x"))
+    dev = "cuda"
+    g = torch.Generator(device=dev)
+    g.manual_seed(seed)
+    A = torch.randn(m, n, dtype=torch.float32, device=dev, generator=g)
+    A_t = nys.nys_transpose(A)
+    A_lo = A.to(torch.bfloat16)
+    A_lo_t = nys.nys_transpose(A_lo)      # the solver gives the sketch this layout too
+    d = torch.rand(n, dtype=torch.float64, device=dev, generator=g)
+    v = torch.randn(m, dtype=torch.float64, device=dev, generator=g)
+    om = torch.randn(m, ell, dtype=torch.float64, device=dev, generator=g)
+    out = torch.empty_like(v)
+    Y = torch.empty(m, ell, dtype=torch.float64, device=dev)
+    for _ in range(3):
+        nys.nys_normal_apply(A, d, 1e-3, v, out, A_t=A_t)
+    nys.nys_sketch_product(A_lo, d, om, "bf16", out=Y, A_t=A_lo_t)
+    torch.cuda.synchronize()
+    log(f"operator {m}x{n}: warm")
+    nys.nys_profile_enable(True)
+    for _ in range(reps):
+        nys.nys_normal_apply(A, d, 1e-3, v, out, A_t=A_t)
+    sk_reps = max(1, reps // 20)
+    for _ in range(sk_reps):
+        nys.nys_sketch_product(A_lo, d, om, "bf16", out=Y, A_t=A_lo_t)
+    torch.cuda.synchronize()
+    prof = nys.nys_profile_read()
+    nys.nys_profile_enable(False)
+    rs_ms = min(nys.nys_stream_read(A) for _ in range(5))
+    bytes_pass = m * n * 4
+    rec = {"mode": "operator", "m": m, "n": n, "A_storage": "float32", "applies": reps,
+           "read_stream_GBps": round(bytes_pass / (rs_ms * 1e-3) / 1e9, 1)}
+    for k in ("normal_pass1", "normal_pass2"):
+        nl, ms = prof[k]
+        rec[k] = {"launches": nl, "avg_ms": round(ms / nl, 4), "GBps": round(bytes_pass / (ms / nl * 1e-3) / 1e9, 1)}
+    rec["normal_apply_ms"] = round(rec["normal_pass1"]["avg_ms"] + rec["normal_pass2"]["avg_ms"], 4)
+    flops = 2.0 * m * n * ell
+    for k in ("sketch_w", "sketch_y"):
+        nl, ms = prof[k]
+        rec[k] = {"ell": ell, "launches": nl, "avg_ms": round(ms / nl, 3),
+                  "TFLOPs": round(flops / (ms / nl * 1e-3) / 1e12, 1)}
+    print(json.dumps(rec), flush=True)
+
+
 ADAPTIVE_VARIANTS = (
     ("fixed", dict()),
     ("deff", dict(ell_rule="deff")),
@@ -374,6 +427,9 @@ def main():
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--kernel-loop", type=int, default=0)
+    ap.add_argument("--operator", default="", metavar="MxN")
+    ap.add_argument("--ell", type=int, default=400)
+    ap.add_argument("--reps", type=int, default=200)
     ap.add_argument("--compare", action="store_true")
     ap.add_argument("--adaptive", action="store_true")
     ap.add_argument("--dense-identity", action="store_true")
@@ -415,6 +471,10 @@ def main():
 
     import paper_2404_14524_amd as nys
     from instances import make_instance
+
+    if args.operator:
+        operator_shape(nys, args.operator, args.ell, args.reps, args.seed)
+        return
 
     dev = "cuda"
     t0 = time.perf_counter()

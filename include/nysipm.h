@@ -26,6 +26,12 @@
  *   Arguments are validated before any launch, so on NYS_EINVAL outputs are
  *   untouched.  nys_last_error(h) gives a message.  Nothing aborts and no
  *   exception crosses the ABI.  A handle is not thread-safe: one per stream.
+ * - Size limits (launch grids): m < 2^31 (unit rows are int32); the BF16
+ *   sketch takes m <= 65535 * 128 = 8388480 (NYS_EINVAL beyond); nys_transpose
+ *   takes m <= 65535 * 64 = 4194240, and ipm_solve / ipm_adjoint make no
+ *   transposed copy beyond that (the passes then read A_d as it is); the
+ *   partial Cholesky preconditioner takes ell <= 65535.  n is bounded only by
+ *   memory.
  */
 #ifndef NYSIPM_H
 #define NYSIPM_H

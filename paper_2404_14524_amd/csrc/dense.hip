@@ -668,6 +668,19 @@ int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64
              const void* A, nys_dtype adt, int64_t lda, const double* B, int64_t ldb, double* C,
              int64_t ldc, const double* row_scale) {
   if (M == 0 || N == 0) return NYS_OK;
+  // the grid's y dimension counts GBM-row tiles and stops at 65535: taller
+  // products run as one launch per chunk of rows
+  constexpr int64_t kMaxRows = 65535LL * GBM;
+  if (M > kMaxRows) {
+    const int64_t es = adt == NYS_F64 ? 8 : adt == NYS_F32 ? 4 : 2;
+    for (int64_t r0 = 0; r0 < M; r0 += kMaxRows) {
+      const int64_t mc = std::min(kMaxRows, M - r0);
+      const char* Ac = (const char*)A + (transA ? r0 : r0 * lda) * es;
+      NYS_CHECK(gemm_f64(h, transA, transB, mc, N, K, Ac, adt, lda, B, ldb, C + r0 * ldc, ldc,
+                         row_scale ? row_scale + r0 : nullptr));
+    }
+    return NYS_OK;
+  }
   const int64_t tiles = ((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
   int64_t nsplit = 1;
   if (tiles < 512 && K > 512) {

@@ -398,6 +398,12 @@ struct Opts {
   double inner_factor = 0.5;
 };
 
+// Transposed copies only where the transpose kernel's grid (65535 tiles of 64
+// rows) covers A's m rows; beyond that the passes read A as it is.
+inline bool copy_allowed(const Opts& o, const nys_matrix* A) {
+  return o.transpose && (A->m + 63) / 64 <= 65535;
+}
+
 // Workspace-backed partial Cholesky preconditioner for the comparator runs.
 int pchol_storage(nys_handle h, int64_t m, int ell, nys_pchol* P) {
   const size_t nd = (size_t)m * ell + (size_t)ell * ell + m + ((size_t)ell + m + 1) / 2 + 4;
@@ -526,7 +532,7 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   }
   const bool box = vt != nullptr;
   nys_matrix At{};
-  NYS_CHECK(with_transpose(h, A, o.transpose, WS_AT, &At));
+  NYS_CHECK(with_transpose(h, A, copy_allowed(o, A), WS_AT, &At));
   A = &At;
 
   // ---- workspace
@@ -575,7 +581,7 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   nys_matrix Alot{};
   if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM) {
     NYS_CHECK(lo_matrix(h, qp, &Alo));
-    NYS_CHECK(with_transpose(h, &Alo, o.transpose, WS_ALOT, &Alot));
+    NYS_CHECK(with_transpose(h, &Alo, copy_allowed(o, &Alo), WS_ALOT, &Alot));
     Ask = &Alot;
   }
   nys_pchol pch{};
@@ -895,7 +901,7 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   const auto t_start = clk::now();
   h->t_sketch = h->t_pcg = h->t_other = 0.0;
   nys_matrix At{};
-  NYS_CHECK(with_transpose(h, A, o.transpose, WS_AT, &At));
+  NYS_CHECK(with_transpose(h, A, copy_allowed(o, A), WS_AT, &At));
   A = &At;
   double* base;
   NYS_CHECK(ws(h, WS_IPM, (size_t)12 * n + 8 * m + 64, &base));
@@ -912,7 +918,7 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   nys_matrix Alot{};
   if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM) {
     NYS_CHECK(lo_matrix(h, qp, &Alo));
-    NYS_CHECK(with_transpose(h, &Alo, o.transpose, WS_ALOT, &Alot));
+    NYS_CHECK(with_transpose(h, &Alo, copy_allowed(o, &Alo), WS_ALOT, &Alot));
     Ask = &Alot;
   }
   nys_pchol pch{};

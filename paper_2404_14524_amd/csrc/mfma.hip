@@ -378,7 +378,11 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
   NYS_LAUNCH_CHECK(h);
   const uint16_t* Ad = (const uint16_t*)A->data;
   const bool vecA = ((uintptr_t)Ad % 16 == 0) && (A->ld % 8 == 0);
-  const bool wide = A->data_t != nullptr;
+  // grid y counts TBM-row tiles (of A^T's n rows in the wide W product, of
+  // A's m rows in the Y product) and stops at 65535
+  if ((m + TBM - 1) / TBM > 65535)
+    return set_error(h, NYS_EINVAL, "BF16 sketch: m=%lld above %lld rows", (long long)m, 65535LL * TBM);
+  const bool wide = A->data_t != nullptr && (n + TBM - 1) / TBM <= 65535;
   if (wide) {
     // Wt (ell x n) written transposed from W = At (n x m) * Ot^T: both operands k-contiguous
     const uint16_t* Atd = (const uint16_t*)A->data_t;

@@ -249,6 +249,8 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_pchol_unit(double* Y, int ell, co
 int pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta, nys_pchol* P) {
   const int64_t m = A->m, n = A->n;
   const int ell = P->ell;
+  // the gather's grid has one y index per pivot and stops at 65535
+  if (ell > 65535) return set_error(h, NYS_EINVAL, "partial Cholesky: ell=%d above 65535 pivots", ell);
   double *Y, *Wt, *G, *diag;
   NYS_CHECK(ws(h, WS_Y, (size_t)m * ell, &Y));
   NYS_CHECK(ws(h, WS_SK_W, (size_t)ell * std::max<int64_t>(n, 1), &Wt));

@@ -1,0 +1,125 @@
+"""GPU parity at the largest shapes a launch grid takes in one go, and just
+beyond: the FP64 products run over chunks of 65535 * 64 rows, the BF16
+sketch keeps to the 128-wide tiles when A^T has more than 65535 * 128 rows,
+and the driver reads A as it is (no transposed copy) when m exceeds 65535 * 64.
+Thin matrices keep these shapes within a few hundred MB; checks are against
+the oracle where it runs at this size, else against properties that hold at
+any size (the KKT residuals of the returned point)."""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import lowprec, nystrom
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+ROWS_F64 = 65535 * 64        # rows of one FP64 product launch
+ROWS_BF16 = 65535 * 128      # rows of A^T in one wide BF16 launch
+
+
+@pytest.fixture(scope="module")
+def nys():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2404_14524_amd as pkg
+    return pkg
+
+
+def _t(a, dtype=torch.float64):
+    return torch.as_tensor(np.ascontiguousarray(a), dtype=dtype, device=DEV)
+
+
+def _np(t):
+    return t.detach().double().cpu().numpy()
+
+
+def test_fp64_sketch_product_over_row_chunks(nys):
+    """W = d .* (A^T Omega) has n = 65535 * 64 + 1000 rows: two launches."""
+    m, n, ell = 3, ROWS_F64 + 1000, 2
+    print(f"sketch_product f64 {m}x{n} ell={ell}", flush=True)
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    d = rng.uniform(0.0, 3.0, n)
+    Om = rng.standard_normal((m, ell))
+    Y = _np(nys.nys_sketch_product(_t(A), _t(d), _t(Om), "f64"))
+    ref = A @ (d[:, None] * (A.T @ Om))
+    bound = np.abs(A) @ (d[:, None] * (np.abs(A).T @ np.abs(Om)))
+    # worst case of two FP64 sums of at most m + n terms each
+    assert np.all(np.abs(Y - ref) <= 2.0 ** -52 * (m + n) * bound)
+    assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
+
+
+def test_bf16_sketch_beyond_the_wide_grid(nys):
+    """A^T with 65535 * 128 + 384 rows: the product keeps to the 128-wide
+    tiles on A and gives what it gives without the transposed copy."""
+    m, n, ell = 4, ROWS_BF16 + 384, 3
+    print(f"sketch_product bf16 {m}x{n} ell={ell}", flush=True)
+    rng = np.random.default_rng(6)
+    A32 = (rng.standard_normal((m, n)) / np.sqrt(n)).astype(np.float32)
+    d = rng.uniform(0.0, 3.0, n)
+    Om = rng.standard_normal((m, ell))
+    Abf = _t(A32, torch.float32).to(torch.bfloat16)
+    A_t = nys.nys_transpose(Abf)
+    Yt = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16", A_t=A_t))
+    del A_t
+    Y = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16"))
+    assert np.array_equal(Yt, Y)
+    refb = lowprec.sketch_bf16(A32.astype(np.float64), d, Om)
+    Ab = lowprec.round_bf16(A32.astype(np.float64))
+    boundb = np.abs(Ab) @ (d[:, None] * (np.abs(Ab).T @ np.abs(lowprec.round_bf16(Om))))
+    # FP32 accumulation over m + n terms plus a BF16 rounding of W across a tie
+    assert np.all(np.abs(Y - refb) <= (2.0 ** -8 + 2.0 ** -24 * (m + n)) * boundb)
+    assert np.linalg.norm(Y - refb) <= 1e-4 * np.linalg.norm(refb)
+
+
+def test_sketch_with_m_beyond_one_launch(nys):
+    """Algorithm 1 with m = 65535 * 64 + 128: the m x ell products run over
+    row chunks.  N has rank 2 = ell, so the approximation is N itself; the
+    two sides agree on its eigenvalues and on its action on probes."""
+    m, n, ell = ROWS_F64 + 128, 2, 2
+    print(f"sketch f64 {m}x{n} ell={ell}", flush=True)
+    rng = np.random.default_rng(7)
+    A = rng.standard_normal((m, n))
+    d = np.array([0.7, 2.5])
+    Om = rng.standard_normal((m, ell))
+    P = nys.nys_sketch(_t(A), _t(d), ell, omega=_t(Om))
+    Uo, lo, _ = nystrom.nystrom(lambda V: A @ (d[:, None] * (A.T @ V)), nystrom.orthonormalize(Om))
+    Ug, lg = _np(P.U), _np(P.lam)
+    np.testing.assert_allclose(Ug.T @ Ug, np.eye(ell), atol=1e-12)
+    np.testing.assert_allclose(lg, lo, rtol=1e-8)
+    V = rng.standard_normal((m, 3))
+    Ng = Ug @ (lg[:, None] * (Ug.T @ V))
+    No = Uo @ (lo[:, None] * (Uo.T @ V))
+    Nv = A @ (d[:, None] * (A.T @ V))
+    assert np.linalg.norm(Ng - No) <= 1e-8 * np.linalg.norm(No)
+    assert np.linalg.norm(Ng - Nv) <= 1e-8 * np.linalg.norm(Nv)
+
+
+def test_ipm_solve_with_m_beyond_the_transpose_grid(nys):
+    """min 1/2 x^T Q x + c^T x  s.t.  A_d x_d + s = b,  x, s >= 0, with
+    m = 65535 * 64 + 128 rows (the slack block as unit columns): no transposed
+    copy is made and the returned point meets the KKT conditions to the
+    tolerance, measured here in FP64 on the CPU."""
+    m, nd = ROWS_F64 + 128, 2
+    print(f"ipm_solve units {m}x{nd}+{m}", flush=True)
+    rng = np.random.default_rng(8)
+    A = rng.standard_normal((m, nd))
+    b = A @ rng.uniform(0.5, 1.5, nd) + rng.uniform(0.5, 1.5, m)
+    c = np.concatenate([rng.standard_normal(nd), rng.uniform(-1.0, 1.0, m)])
+    q = rng.uniform(0.5, 2.0, nd + m)
+    rows = np.arange(m, dtype=np.int32)
+    vals = np.ones(m)
+    tol = 1e-7
+    x, y, z, info = nys.ipm_solve(_t(A), _t(b), _t(c), _t(q), ell=2, tol=tol,
+                                  units=(_t(rows, torch.int32), _t(vals)))
+    assert info.status == 0
+    x, y, z = _np(x), _np(y), _np(z)
+    xd, s = x[:nd], x[nd:]
+    rp = b - A @ xd - s
+    rd = c + q * x - np.concatenate([A.T @ y, y]) - z
+    assert np.all(x > 0) and np.all(z > 0)
+    assert np.linalg.norm(rp) / (1 + np.linalg.norm(b)) <= tol
+    assert np.linalg.norm(rd) / (1 + np.linalg.norm(c)) <= tol
+    assert x @ z / x.size <= tol

@@ -722,6 +722,8 @@ extern "C" int nys_sketch(nys_handle h, const nys_matrix* A, const double* d, in
     return set_error(h, NYS_EINVAL, "nys_sketch: a BF16 sketch needs BF16 storage of A");
   if (sketch_dtype != NYS_BF16 && sketch_dtype != NYS_F64)
     return set_error(h, NYS_EINVAL, "nys_sketch: sketch dtype must be NYS_F64 or NYS_BF16");
+  if (sketch_dtype == NYS_BF16 && A->m > 65535LL * 128)
+    return set_error(h, NYS_EINVAL, "nys_sketch: the BF16 sketch takes m <= %lld", 65535LL * 128);
   NYS_HIP(h, hipSetDevice(h->device));
   SketchOut so{P->U, P->lambda, 0.0};
   int rc = sketch_run(h, A, d, ell, seed, counter, sketch_dtype, 1.0, omega, &so);

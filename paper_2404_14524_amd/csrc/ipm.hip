@@ -502,6 +502,10 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
       return set_error(h, NYS_EINVAL, "ipm_solve: need 1 <= ell_min <= ell_max <= m and ell <= ell_max");
     ell_cap = o.ell_max;
   }
+  if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM && m > 65535LL * 128)
+    return set_error(h, NYS_EINVAL, "ipm_solve: the BF16 sketch takes m <= %lld", 65535LL * 128);
+  if (o.precond == NYS_PRECOND_PCHOL && o.ell > 65535)
+    return set_error(h, NYS_EINVAL, "ipm_solve: the partial Cholesky preconditioner takes ell <= 65535");
   NYS_HIP(h, hipSetDevice(h->device));
   const auto t_start = clk::now();
   h->t_sketch = h->t_pcg = h->t_other = 0.0;
@@ -897,6 +901,15 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   const nys_matrix* A = qp->A;
   const int64_t m = A->m, n = A->n;
   if (o.ell < 1 || o.ell > m) return set_error(h, NYS_EINVAL, "ipm_adjoint: ell must be in [1, m]");
+  if (o.precond < NYS_PRECOND_NYSTROM || o.precond > NYS_PRECOND_PCHOL)
+    return set_error(h, NYS_EINVAL, "ipm_adjoint: bad preconditioner kind %d", o.precond);
+  if (o.precond == NYS_PRECOND_NYSTROM) {
+    if (o.sk != NYS_F64 && o.sk != NYS_BF16) return set_error(h, NYS_EINVAL, "ipm_adjoint: bad sketch dtype");
+    if (o.sk == NYS_BF16 && m > 65535LL * 128)
+      return set_error(h, NYS_EINVAL, "ipm_adjoint: the BF16 sketch takes m <= %lld", 65535LL * 128);
+  }
+  if (o.precond == NYS_PRECOND_PCHOL && o.ell > 65535)
+    return set_error(h, NYS_EINVAL, "ipm_adjoint: the partial Cholesky preconditioner takes ell <= 65535");
   NYS_HIP(h, hipSetDevice(h->device));
   const auto t_start = clk::now();
   h->t_sketch = h->t_pcg = h->t_other = 0.0;
@@ -933,8 +946,6 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   NYS_CHECK(gemv_n(h, g2));                                            // A D g
   auto t0 = clk::now();
   double nu = 0;
-  if (o.precond < NYS_PRECOND_NYSTROM || o.precond > NYS_PRECOND_PCHOL)
-    return set_error(h, NYS_EINVAL, "ipm_adjoint: bad preconditioner kind %d", o.precond);
   if (o.precond == NYS_PRECOND_NYSTROM)
     NYS_CHECK(ipm_sketch(h, Ask, D, o.ell, o.seed, CTR_ADJ, o.sk, o.c_nu, U, lamh, &nu));
   else if (o.precond == NYS_PRECOND_PCHOL)

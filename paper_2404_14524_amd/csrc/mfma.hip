@@ -369,6 +369,10 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
                 double* Y) {
   if (A->dtype != NYS_BF16) return set_error(h, NYS_EINVAL, "BF16 sketch needs BF16 storage of A");
   const int64_t m = A->m, n = A->n;
+  // grid y counts TBM-row tiles (of A's m rows in the Y product, of A^T's n
+  // rows in the wide W product) and stops at 65535
+  if ((m + TBM - 1) / TBM > 65535)
+    return set_error(h, NYS_EINVAL, "BF16 sketch: m=%lld above %lld rows", (long long)m, 65535LL * TBM);
   if (n == 0) return fill(h, Y, m * ell, 0.0);
   const int64_t ldo = (m + 7) / 8 * 8, ldw = (n + 7) / 8 * 8;
   uint16_t *Ot, *Wt;
@@ -378,10 +382,6 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
   NYS_LAUNCH_CHECK(h);
   const uint16_t* Ad = (const uint16_t*)A->data;
   const bool vecA = ((uintptr_t)Ad % 16 == 0) && (A->ld % 8 == 0);
-  // grid y counts TBM-row tiles (of A^T's n rows in the wide W product, of
-  // A's m rows in the Y product) and stops at 65535
-  if ((m + TBM - 1) / TBM > 65535)
-    return set_error(h, NYS_EINVAL, "BF16 sketch: m=%lld above %lld rows", (long long)m, 65535LL * TBM);
   const bool wide = A->data_t != nullptr && (n + TBM - 1) / TBM <= 65535;
   if (wide) {
     // Wt (ell x n) written transposed from W = At (n x m) * Ot^T: both operands k-contiguous

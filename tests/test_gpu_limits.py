@@ -123,3 +123,27 @@ def test_ipm_solve_with_m_beyond_the_transpose_grid(nys):
     assert np.linalg.norm(rp) / (1 + np.linalg.norm(b)) <= tol
     assert np.linalg.norm(rd) / (1 + np.linalg.norm(c)) <= tol
     assert x @ z / x.size <= tol
+
+
+def test_shapes_beyond_the_limits_are_rejected_before_any_work(nys):
+    """m above 65535 * 128 for a BF16 sketch, and ell above 65535 pivots for
+    the partial Cholesky preconditioner: NYS_EINVAL from the argument checks,
+    before any kernel of the path is launched."""
+    m = ROWS_BF16 + 1
+    print(f"rejections m={m}", flush=True)
+    A = torch.ones(m, 1, dtype=torch.float32, device=DEV)
+    Abf = A.to(torch.bfloat16)
+    d = torch.ones(1, dtype=torch.float64, device=DEV)
+    with pytest.raises(nys.NysError, match="BF16 sketch takes m"):
+        nys.nys_sketch(Abf, d, 1, sketch_dtype="bf16")
+    with pytest.raises(nys.NysError, match="BF16 sketch"):
+        nys.nys_sketch_product(Abf, d, torch.ones(m, 1, dtype=torch.float64, device=DEV), "bf16")
+    b = torch.ones(m, dtype=torch.float64, device=DEV)
+    with pytest.raises(nys.NysError, match="BF16 sketch takes m"):
+        nys.ipm_solve(A, b, d, d, ell=1, sketch_dtype="bf16", A_lo=Abf)
+    del A, Abf, b
+    m = 65536
+    A = torch.ones(m, 1, dtype=torch.float64, device=DEV)
+    b = torch.ones(m, dtype=torch.float64, device=DEV)
+    with pytest.raises(nys.NysError, match="ell <= 65535"):
+        nys.ipm_solve(A, b, d, d, ell=m, precond="pchol")

@@ -181,6 +181,21 @@ def _vec(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
     return t
 
 
+def _mat64(t: torch.Tensor, rows: int, cols: int, name: str, device) -> torch.Tensor:
+    """A contiguous float64 rows x cols tensor on `device` (the library reads
+    and writes such arguments as dense row-major blocks)."""
+    if (t.dtype != torch.float64 or t.device != device or t.dim() != 2 or tuple(t.shape) != (rows, cols)
+            or not t.is_contiguous()):
+        raise ValueError(f"{name}: need a contiguous float64 tensor of shape ({rows}, {cols}) on {device}")
+    return t
+
+
+def _idx32(t: torch.Tensor, n: int, name: str, device) -> torch.Tensor:
+    if t.dtype != torch.int32 or t.device != device or t.numel() != n or not t.is_contiguous():
+        raise ValueError(f"{name}: need a contiguous int32 tensor of {n} elements on {device}")
+    return t
+
+
 def _units(A: torch.Tensor, units) -> tuple:
     """(count, rows pointer, values pointer) of the unit columns: units is None
     or (rows int32, vals float64), device tensors of equal length (rows
@@ -201,16 +216,25 @@ def ncols(A: torch.Tensor, units=None) -> int:
     return A.shape[1] + (0 if units is None else units[0].numel())
 
 
+def _rows_ok(T) -> bool:
+    """Row-major with a leading dimension the library can take: unit stride
+    along a row, and rows that do not overlap (an expanded or broadcast view,
+    with row stride 0, would make the kernels read past its storage)."""
+    r, c = T.shape
+    return (T.stride(1) == 1 or c <= 1) and (T.stride(0) >= c or r <= 1)
+
+
 def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None, units=None) -> nys_matrix:
     """nys_matrix view of a row-major CUDA tensor; A_t (optional) is the same
     matrix transposed, n x m row-major (see nys_transpose); units (optional)
     appends unit columns (see _units)."""
-    if A.dim() != 2 or A.dtype not in _DT or not A.is_cuda or (A.stride(1) != 1 and A.shape[1] > 1):
-        raise ValueError("A: need a 2-D row-major float64/float32/bfloat16 CUDA tensor")
+    if (A.dim() != 2 or A.dtype not in _DT or not A.is_cuda or not _rows_ok(A)):
+        raise ValueError("A: need a 2-D row-major float64/float32/bfloat16 CUDA tensor "
+                         "(unit column stride, row stride >= columns)")
     tp, tld = None, 0
     if A_t is not None:
         if (A_t.dim() != 2 or tuple(A_t.shape) != (A.shape[1], A.shape[0]) or A_t.dtype != A.dtype
-                or A_t.device != A.device or A_t.stride(1) != 1):
+                or A_t.device != A.device or not _rows_ok(A_t)):
             raise ValueError("A_t: need an n x m row-major tensor of A's dtype on A's device")
         tp, tld = A_t.data_ptr(), max(A_t.stride(0), A.shape[0], 1)
     k, ur, uv = _units(A, units)
@@ -225,7 +249,12 @@ class Precond:
     nu: float = 0.0
 
     def c(self) -> nys_precond:
-        return nys_precond(self.U.shape[0], self.U.shape[1], self.U.data_ptr(), self.lam.data_ptr())
+        if self.U.dim() != 2:
+            raise ValueError("U: need an m x ell tensor")
+        m, ell = self.U.shape
+        _mat64(self.U, m, ell, "U", self.U.device)
+        _vec(self.lam, ell, "lam", self.U.device)
+        return nys_precond(m, ell, self.U.data_ptr(), self.lam.data_ptr())
 
 
 @dataclass
@@ -238,7 +267,16 @@ class PChol:
     diagS: torch.Tensor    # m float64
 
     def c(self) -> nys_pchol:
-        return nys_pchol(self.L.shape[0], self.L.shape[1], self.piv.data_ptr(), self.pos.data_ptr(),
+        if self.L.dim() != 2:
+            raise ValueError("L: need an m x ell tensor")
+        m, ell = self.L.shape
+        dev = self.L.device
+        _mat64(self.L, m, ell, "L", dev)
+        _mat64(self.Cinv, ell, ell, "Cinv", dev)
+        _vec(self.diagS, m, "diagS", dev)
+        _idx32(self.piv, ell, "piv", dev)
+        _idx32(self.pos, m, "pos", dev)
+        return nys_pchol(m, ell, self.piv.data_ptr(), self.pos.data_ptr(),
                          self.L.data_ptr(), self.Cinv.data_ptr(), self.diagS.data_ptr())
 
 
@@ -309,11 +347,13 @@ def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sk
                        units=None) -> torch.Tensor:
     lib, h = _handle(A.device)
     m = A.shape[0]
+    if omega.dim() != 2:
+        raise ValueError("omega: need an m x ell tensor")
     ell = omega.shape[1]
     _vec(d, ncols(A, units), "d", A.device)
-    _vec(omega.reshape(-1), m * ell, "omega", A.device)
+    _mat64(omega, m, ell, "omega", A.device)
     Y = torch.empty((m, ell), dtype=torch.float64, device=A.device) if out is None else out
-    _vec(Y.reshape(-1), m * ell, "out", A.device)
+    _mat64(Y, m, ell, "out", A.device)
     Am = _mat(A, A_t, units)
     _check(lib, h, lib.nys_sketch_product(h, C.byref(Am), _ptr(d), _ptr(omega), ell, _SK[sketch_dtype],
                                           _ptr(Y)))
@@ -327,7 +367,7 @@ def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counte
     m = A.shape[0]
     _vec(d, ncols(A, units), "d", A.device)
     if omega is not None:
-        _vec(omega.reshape(-1), m * ell, "omega", A.device)
+        _mat64(omega, m, ell, "omega", A.device)
     U = torch.empty((m, ell), dtype=torch.float64, device=A.device)
     lam = torch.empty(ell, dtype=torch.float64, device=A.device)
     P = nys_precond(m, ell, U.data_ptr(), lam.data_ptr())
@@ -573,6 +613,8 @@ def nys_stream_read(t: torch.Tensor) -> float:
     """Milliseconds for one 16-byte non-temporal read of the tensor's bytes
     (read-stream reference for roofline reports)."""
     lib, h = _handle(t.device)
+    if not t.is_contiguous():
+        raise ValueError("nys_stream_read: need a contiguous tensor")
     nbytes = t.numel() * t.element_size()
     ms = C.c_double()
     _check(lib, h, lib.nys_stream_read(h, C.c_void_p(t.data_ptr()), nbytes - nbytes % 16, C.byref(ms)))

@@ -112,3 +112,35 @@ def test_rebuild_rule_matches_oracle():
         growth = float(rng.choice([1.0, 1.5, 2.0, 1.25]))
         case = (k, k_build, pcg_prev, pcg_ref, max_age, growth)
         assert bool(lib.nys_precond_rebuild_due(*case)) == adaptive.rebuild_due(*case), case
+
+
+# ---------------------------------------------------------------- argument checks of the binding
+
+def test_binding_refuses_views_the_kernels_would_read_past():
+    """Row-major views with overlapping rows (expanded, broadcast) or a
+    non-unit column stride are refused before any library call; so are 2-D
+    arguments and preconditioner parts that are not dense row-major blocks."""
+    from paper_2404_14524_amd import nysipm as b
+    A = torch.zeros(6, 5, dtype=torch.float64)
+    assert b._rows_ok(A) and b._rows_ok(A[:, 1:4]) and b._rows_ok(A[2:3])
+    assert not b._rows_ok(torch.zeros(1, 5).expand(6, 5))     # row stride 0
+    assert not b._rows_ok(A.t())                              # column stride 6
+    assert b._rows_ok(torch.zeros(6, 1).expand(6, 1)) and b._rows_ok(torch.zeros(1, 5))
+    dev = A.device
+    b._mat64(A, 6, 5, "A", dev)
+    for bad in (A[:, :4], A.float(), A.t().contiguous(), torch.zeros(1, 5, dtype=torch.float64).expand(6, 5)):
+        with pytest.raises(ValueError):
+            b._mat64(bad, 6, 5, "A", dev)
+    U = torch.zeros(6, 2, dtype=torch.float64)
+    b.Precond(U, torch.zeros(2, dtype=torch.float64)).c()
+    with pytest.raises(ValueError):
+        b.Precond(torch.zeros(1, 2, dtype=torch.float64).expand(6, 2), torch.zeros(2, dtype=torch.float64)).c()
+    with pytest.raises(ValueError):
+        b.Precond(U, torch.zeros(3, dtype=torch.float64)).c()
+    i32 = torch.int32
+    P = b.PChol(torch.zeros(2, dtype=i32), torch.zeros(6, dtype=i32), U, torch.zeros(2, 2, dtype=torch.float64),
+                torch.zeros(6, dtype=torch.float64))
+    P.c()
+    P.pos = torch.zeros(6, dtype=torch.int64)
+    with pytest.raises(ValueError):
+        P.c()

@@ -195,6 +195,31 @@ def test_pcg_matches_dense_solve():
     assert tr <= 1e-11
 
 
+@pytest.mark.parametrize("precond", [False, True])
+def test_pcg_iterate_is_the_krylov_galerkin_solution(precond):
+    """After k steps from y = 0, (P)CG's iterate is the M-norm best
+    approximation of M^{-1} xi in the Krylov space K_k(P^{-1} M, P^{-1} xi):
+    y = V (V^T M V)^{-1} V^T xi for any basis V of that space.  A wrong sign
+    or index in alpha, beta or the direction update leaves this space or this
+    optimum at k >= 2."""
+    rng = np.random.default_rng(21)
+    m = 30
+    B = rng.standard_normal((m, m))
+    M = B @ B.T + 3.0 * np.eye(m)
+    xi = rng.standard_normal(m)
+    C = rng.standard_normal((m, m))
+    G = C @ C.T / m + np.eye(m) if precond else np.eye(m)        # P^{-1}, SPD
+    for k in (1, 2, 3, 6):
+        y, it, _, _ = pcg.pcg(lambda v: M @ v, xi, (lambda r: G @ r) if precond else None, tol=0.0, maxit=k)
+        assert it == k
+        K = [G @ xi]
+        for _ in range(k - 1):
+            K.append(G @ (M @ K[-1]))
+        V, _ = np.linalg.qr(np.array(K).T)
+        yk = V @ np.linalg.solve(V.T @ M @ V, V.T @ xi)
+        np.testing.assert_allclose(y, yk, rtol=0, atol=1e-10 * np.linalg.norm(yk))
+
+
 # ---------------------------------------------------------------- IP-PMM
 
 def test_step_length_fraction_to_boundary():

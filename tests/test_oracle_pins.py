@@ -74,6 +74,76 @@ def test_newton_elimination_matches_dense_lu(rho, delta):
         assert np.linalg.norm(a - e) <= 1e-10 * (1 + np.linalg.norm(e))
 
 
+def _central_jacobian(R, v, h=1e-3):
+    """Jacobian of R at v by central differences (exact up to rounding for
+    maps that are at most quadratic, as the residual maps here are)."""
+    return np.column_stack([(R(v + h * e) - R(v - h * e)) / (2 * h) for e in np.eye(v.size)])
+
+
+def test_newton_matrix_is_the_jacobian_of_the_pmm_residuals():
+    """eq. Newton is Newton's method on the residuals of the PMM subproblem
+    of (P): r_d + rho (x - zeta), r_p - delta (y - lambda) and the products
+    x_j z_j.  The unreduced matrix must equal minus the Jacobian of that map,
+    here differentiated numerically from problem.residuals (pinned by the
+    planted KKT point)."""
+    rng = np.random.default_rng(31)
+    m, n = 5, 11
+    A = rng.standard_normal((m, n))
+    b, c = rng.standard_normal(m), rng.standard_normal(n)
+    q = rng.uniform(0.0, 2.0, n)
+    rho, delta = 0.7, 0.3
+    zeta, lam = rng.standard_normal(n), rng.standard_normal(m)
+
+    def R(v):
+        x, y, z = v[:n], v[n:n + m], v[n + m:]
+        rp, rd, _ = problem.residuals(A, b, c, q, x, y, z)
+        return np.concatenate([rd + rho * (x - zeta), rp - delta * (y - lam), -x * z])
+
+    x, y, z = rng.uniform(0.5, 2.0, n), rng.standard_normal(m), rng.uniform(0.5, 2.0, n)
+    K = normal_eq.newton_matrix(A, q, x, z, rho, delta)
+    np.testing.assert_allclose(K, -_central_jacobian(R, np.concatenate([x, y, z])), rtol=0, atol=1e-9)
+
+
+def test_box_newton_matrix_is_the_jacobian_of_the_pmm_residuals():
+    """The same for eq. Newton-free-box: rows r_d, r_p, r_u (box indices),
+    x_j z_j (non-free indices) and w_j s_j (box indices), from
+    boxqp.residuals (pinned by planted optima and brute force)."""
+    from oracle import boxqp
+    rng = np.random.default_rng(32)
+    m, n = 4, 12
+    A = rng.standard_normal((m, n))
+    vt = _box_types(n, rng)
+    F, I, J = boxqp.kinds(vt)
+    IJ = I | J
+    iJ, iIJ = np.flatnonzero(J), np.flatnonzero(IJ)
+    b, c = rng.standard_normal(m), rng.standard_normal(n)
+    q = rng.uniform(0.0, 2.0, n)
+    u = np.where(J, rng.uniform(1.0, 3.0, n), 0.0)
+    rho, delta = 0.4, 0.2
+    zeta, lam = rng.standard_normal(n), rng.standard_normal(m)
+    x = np.where(F, rng.standard_normal(n), rng.uniform(0.5, 2.0, n))
+    y = rng.standard_normal(m)
+    z = np.where(IJ, rng.uniform(0.5, 2.0, n), 0.0)
+    w = np.where(J, rng.uniform(0.5, 2.0, n), 0.0)
+    s = np.where(J, rng.uniform(0.5, 2.0, n), 0.0)
+    K, (ox, oy, ow, oz, os_), _ = boxqp.newton_matrix(A, q, vt, x, z, w, s, rho, delta)
+
+    def unpack(v):
+        xv, yv = v[ox:ox + n], v[oy:oy + m]
+        wv, zv, sv = np.zeros(n), np.zeros(n), np.zeros(n)
+        wv[iJ], zv[iIJ], sv[iJ] = v[ow:ow + len(iJ)], v[oz:oz + len(iIJ)], v[os_:os_ + len(iJ)]
+        return xv, yv, zv, wv, sv
+
+    def R(v):
+        xv, yv, zv, wv, sv = unpack(v)
+        rp, rd, ru, _ = boxqp.residuals(A, b, c, q, u, vt, xv, yv, zv, wv, sv)
+        return np.concatenate([rd + rho * (xv - zeta), rp - delta * (yv - lam), ru[iJ],
+                               -(xv * zv)[iIJ], -(wv * sv)[iJ]])
+
+    v = np.concatenate([x, y, w[iJ], z[iIJ], s[iJ]])
+    np.testing.assert_allclose(K, -_central_jacobian(R, v), rtol=0, atol=1e-9)
+
+
 def test_inexact_newton_only_second_block_is_inexact():
     """Proposition 3.1: with an inexact normal-equation solve, blocks 1 and 3
     of the unreduced Newton residual vanish and block 2 equals the residual

@@ -144,6 +144,47 @@ def test_box_newton_matrix_is_the_jacobian_of_the_pmm_residuals():
     np.testing.assert_allclose(K, -_central_jacobian(R, v), rtol=0, atol=1e-9)
 
 
+def test_combined_corrector_solve_is_the_sum_of_the_two_solves():
+    """Algorithm 6 sums the predictor and corrector directions, both solutions
+    of systems with one matrix: a single solve with the summed right-hand
+    side (r_d, r_p, -XZ + mu~ - dXp dZp) gives the same direction, as the GPU
+    path computes it.  Checked for the non-negative and the box forms."""
+    from oracle import boxqp
+    A, q, x, z, rd, rp, _ = _random_state(8, 21, 5)
+    rho, delta, mu_t = 0.2, 0.1, 0.05
+    D = normal_eq.scaling(x, z, q, rho)
+    M = normal_eq.normal_matrix(A, D, delta)
+    exact = lambda xi: np.linalg.solve(M, xi)
+    m, n = A.shape
+    dxp, dyp, dzp, _ = normal_eq.newton_step(A, x, z, D, delta, rd, rp, -x * z, exact)
+    rc = mu_t - dxp * dzp
+    dxc, dyc, dzc, _ = normal_eq.newton_step(A, x, z, D, delta, np.zeros(n), np.zeros(m), rc, exact)
+    dx, dy, dz, _ = normal_eq.newton_step(A, x, z, D, delta, rd, rp, -x * z + rc, exact)
+    for a, e in ((dx, dxp + dxc), (dy, dyp + dyc), (dz, dzp + dzc)):
+        np.testing.assert_allclose(a, e, rtol=1e-10, atol=1e-12)
+    rng = np.random.default_rng(6)
+    vt = _box_types(n, rng)
+    F, I, J = boxqp.kinds(vt)
+    IJ = I | J
+    xb = np.where(F, rng.standard_normal(n), x)
+    zb = np.where(IJ, z, 0.0)
+    w = np.where(J, rng.uniform(0.5, 2.0, n), 0.0)
+    sb = np.where(J, rng.uniform(0.5, 2.0, n), 0.0)
+    ru = np.where(J, rng.standard_normal(n), 0.0)
+    Db = boxqp.scaling(vt, xb, zb, w, sb, q, rho)
+    Mb = (A * Db) @ A.T + delta * np.eye(m)
+    exb = lambda xi: np.linalg.solve(Mb, xi)
+    rxz, rws = np.where(IJ, -xb * zb, 0.0), np.where(J, -w * sb, 0.0)
+    p = boxqp.newton_step(A, vt, xb, zb, w, sb, Db, delta, rd, rp, ru, rxz, rws, exb)
+    rcz = np.where(IJ, mu_t - p[0] * p[2], 0.0)
+    rcs = np.where(J, mu_t - p[3] * p[4], 0.0)
+    zn = np.zeros(n)
+    c_ = boxqp.newton_step(A, vt, xb, zb, w, sb, Db, delta, zn, np.zeros(m), zn, rcz, rcs, exb)
+    t = boxqp.newton_step(A, vt, xb, zb, w, sb, Db, delta, rd, rp, ru, rxz + rcz, rws + rcs, exb)
+    for a, e1, e2 in zip(t, p, c_):
+        np.testing.assert_allclose(a, e1 + e2, rtol=1e-10, atol=1e-12)
+
+
 def test_inexact_newton_only_second_block_is_inexact():
     """Proposition 3.1: with an inexact normal-equation solve, blocks 1 and 3
     of the unreduced Newton residual vanish and block 2 equals the residual

@@ -25,6 +25,7 @@ philox     the Philox4x32-10 counter-based generator and Box-Muller normals
 Parity status: every function is pinned by a CPU test against something
 other than itself (closed forms, invariants, brute force, textbook routines
 or published known-answer vectors), except the parts listed as
-"parity unpinned" in the module docstrings of ``ippmm`` (initial point,
-parameter update and stopping rule shape the trajectory, not the optimum).
+"parity unpinned" in the module docstrings of ``ippmm`` and ``boxqp``
+(initial point, parameter update and stopping rule shape the trajectory, not
+the optimum).
 """

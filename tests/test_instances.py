@@ -107,3 +107,14 @@ def test_generators_are_seeded():
     c = make_instance("gauss_200x500", seed=8)
     assert torch.equal(a.A, b.A) and torch.equal(a.c, b.c)
     assert not torch.equal(a.A, c.A)
+
+
+def test_fp32_workloads_are_defined_by_the_stored_matrix():
+    """The FP32 workloads define the problem by the stored FP32 matrix promoted
+    exactly to FP64: b = A32 x* and c = A32^T y* + z* - Q x* in FP64."""
+    inst = make_instance("gauss_2000x8000", seed=6, m=90, n=300)
+    assert inst.A.dtype == torch.float32
+    A = inst.A.double().numpy()
+    x, y, z, q = inst.x_star.numpy(), inst.y_star.numpy(), inst.z_star.numpy(), inst.q.numpy()
+    np.testing.assert_allclose(inst.b.numpy(), A @ x, rtol=1e-13, atol=1e-14)
+    np.testing.assert_allclose(inst.c.numpy(), A.T @ y + z - q * x, rtol=1e-13, atol=1e-14)

@@ -1,7 +1,7 @@
 """GPU parity at the largest shapes a launch grid takes in one go, and just
 beyond: the FP64 products run over chunks of 65535 * 64 rows, the BF16
 sketch keeps to the 128-wide tiles when A^T has more than 65535 * 128 rows,
-and the driver reads A as it is (no transposed copy) when m exceeds 65535 * 64.
+and ipm_solve reads A as it is (no transposed copy) when m exceeds 65535 * 64.
 Thin matrices keep these shapes within a few hundred MB; checks are against
 the oracle where it runs at this size, else against properties that hold at
 any size (the KKT residuals of the returned point)."""

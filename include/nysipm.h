@@ -110,6 +110,8 @@ typedef struct {
    (a hipStream_t; NULL = the null stream).  Returns NYS_EINVAL / NYS_EHIP. */
 int nys_create(nys_handle* h, int device, void* hip_stream);
 int nys_destroy(nys_handle h);
+/* Enqueue later work on `hip_stream`.  Synchronises the handle's current
+   stream first (work queued there may still use the handle's workspace). */
 int nys_set_stream(nys_handle h, void* hip_stream);
 const char* nys_last_error(nys_handle h);
 /* Milliseconds of GPU time spent in the last call, split as in the paper's

@@ -92,6 +92,7 @@ EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys
 _lib = None
 _lock = threading.Lock()
 _handles: dict = {}
+_streams: dict = {}        # device index -> stream last given to that handle
 
 
 def load_library(path: str = LIB_PATH) -> C.CDLL:
@@ -161,7 +162,12 @@ def _handle(device: torch.device):
             raise NysError(rc, f"nys_create failed on device {idx}")
         _handles[idx] = h
     stream = torch.cuda.current_stream(idx).cuda_stream
-    lib.nys_set_stream(h, C.c_void_p(stream))
+    if _streams.get(idx) != stream:
+        # nys_set_stream waits for the handle's previous stream (its workspace
+        # may still be in use there), so it is called only when torch's
+        # current stream changes: calls that only enqueue stay asynchronous
+        lib.nys_set_stream(h, C.c_void_p(stream))
+        _streams[idx] = stream
     return lib, h
 
 

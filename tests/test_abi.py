@@ -144,3 +144,38 @@ def test_binding_refuses_views_the_kernels_would_read_past():
     P.pos = torch.zeros(6, dtype=torch.int64)
     with pytest.raises(ValueError):
         P.c()
+
+
+def test_binding_sets_the_stream_only_when_it_changes(monkeypatch):
+    """nys_set_stream waits for the handle's previous stream, so the binding
+    calls it only when torch's current stream changes (a fake library and
+    fake torch stream stand in for the GPU)."""
+    from paper_2404_14524_amd import nysipm as b
+    calls = []
+
+    class FakeLib:
+        def nys_create(self, h, idx, stream):
+            return 0
+
+        def nys_set_stream(self, h, stream):
+            calls.append(stream.value)
+            return 0
+
+    class FakeStream:
+        def __init__(self, ptr):
+            self.cuda_stream = ptr
+
+    current = [FakeStream(0)]
+    monkeypatch.setattr(b, "load_library", lambda: FakeLib())
+    monkeypatch.setattr(b, "_handles", {})
+    monkeypatch.setattr(b, "_streams", {})
+    monkeypatch.setattr(torch.cuda, "is_available", lambda: True)
+    monkeypatch.setattr(torch.cuda, "current_stream", lambda idx=None: current[0])
+    dev = torch.device("cuda", 0)
+    for _ in range(3):
+        b._handle(dev)
+    assert calls == [None]                   # the null stream, once (ctypes maps 0 to None)
+    current[0] = FakeStream(1234)
+    b._handle(dev)
+    b._handle(dev)
+    assert calls == [None, 1234]

@@ -378,11 +378,15 @@ typedef struct {
   /* The direction of the predictor-corrector scheme (Algorithm 6) is the sum
      of the predictor and corrector steps.  0 (default): it is computed as one
      solve with the summed right-hand side (r_d, r_p, r_u of the predictor,
-     R_xz = -XZ + mu~ - dx_p dz_p, R_ws likewise), started from the predictor's
-     dy, which is the same direction by linearity; the predictor itself, used
-     only for the step lengths and mu_aff, is then solved to a relative
-     residual of predictor_rtol (<= 0: 1e-3) or the usual inner tolerance,
-     whichever is looser.  1: the two solves as printed, both to the inner
+     R_xz = -XZ + mu~ - dx_p dz_p, R_ws likewise), started from the
+     predictor's dy and run to the inner tolerance.  With exact solves this
+     equals the sum of the two solves (linearity).  The predictor itself is
+     solved only to a relative residual of predictor_rtol (<= 0: 1e-3) or the
+     usual inner tolerance, whichever is looser; its error then enters the
+     predictor step lengths, mu_aff, mu~ and dx_p dz_p of the corrector's
+     right-hand side, so the default iterates differ from Algorithm 6's (they
+     reach the same optimum).  A predictor_rtol at the inner tolerance gives
+     Algorithm 6's iterates.  1: the two solves as printed, both to the inner
      tolerance, then added.                                                    */
   int32_t separate_corrector;
   double predictor_rtol;

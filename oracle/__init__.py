@@ -23,9 +23,11 @@ lowprec    round-to-nearest-even emulation of BF16 / FP32 storage
 philox     the Philox4x32-10 counter-based generator and Box-Muller normals
 
 Parity status: every function is pinned by a CPU test against something
-other than itself (closed forms, invariants, brute force, textbook routines
-or published known-answer vectors), except the parts listed as
-"parity unpinned" in the module docstrings of ``ippmm`` and ``boxqp``
-(initial point, parameter update and stopping rule shape the trajectory, not
-the optimum).
+other than itself (closed forms, invariants, brute force, textbook routines,
+published known-answer vectors, or cases worked by hand in exact rational
+arithmetic).  The readings that shape the trajectory (initial point,
+parameter update, stopping measure) are pinned that way too: hand-derived
+initial points and stopping measures, and the parameter update against the
+properties the paper states for it.  What stays unpinned is agreement of
+iteration counts with the paper's own runs, whose data are not available.
 """

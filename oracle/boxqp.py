@@ -30,9 +30,10 @@ Readings (in addition to those of ``ippmm``):
   where the printed formula writes delta_d; entries of x_{IJ}, w_J, z_{IJ},
   s_J still <= 0 after the shifts are set to 1.
 * stopping test: max(rp_rel, rd_rel, ||r_u|| / (1 + ||u||), mu) <= tol.
-These readings shape the trajectory only: parity of the trajectory is
-UNPINNED (as for ``ippmm``); the final point is pinned (planted optima,
-brute force).
+These readings shape the trajectory only.  As for ``ippmm`` they are pinned
+by hand-worked cases (initial points with box, non-negative and free
+variables; the stopping measure) and by the update rule's stated properties;
+the final point is pinned too (planted optima, brute force).
 
 Test infrastructure (see the package docstring).
 """

@@ -8,9 +8,16 @@ gradient of A (m x n) is produced only when A requires grad.
 
 from __future__ import annotations
 
+import warnings
+
 import torch
 
-from .nysipm import ipm_adjoint, ipm_solve
+from .nysipm import NYS_OK, ipm_adjoint, ipm_solve
+
+
+class NysConvergenceWarning(RuntimeWarning):
+    """A solve behind NysQP stopped at its iteration limit: its output (the
+    forward solution or the gradients) comes from the last iterate."""
 
 
 class NysQP(torch.autograd.Function):
@@ -20,6 +27,10 @@ class NysQP(torch.autograd.Function):
         A_lo = opts.pop("A_lo", None)
         ell = opts.pop("ell")
         x, y, z, info = ipm_solve(A.detach(), b.detach(), c.detach(), q.detach(), ell, A_lo=A_lo, **opts)
+        if info.status != NYS_OK:
+            warnings.warn(f"NysQP forward: ipm_solve stopped at its iteration limit after {info.iters} "
+                          f"iterations (KKT {info.kkt_rel:.2e}); x is the last iterate",
+                          NysConvergenceWarning, stacklevel=2)
         ctx.save_for_backward(A, b, c, q, x, y, z)
         ctx.ell, ctx.A_lo, ctx.opts = ell, A_lo, opts
         ctx.rho, ctx.delta = info.rho, info.delta
@@ -34,9 +45,13 @@ class NysQP(torch.autograd.Function):
         if not want:
             return None, None, None, None, None
         opts = {k: v for k, v in ctx.opts.items() if k not in ("tol", "max_iter")}
-        grads, _ = ipm_adjoint(A.detach(), b.detach(), c.detach(), q.detach(), x, y, z, ctx.rho, ctx.delta,
-                               gx.detach().to(torch.float64).contiguous(), ctx.ell, A_lo=ctx.A_lo,
-                               want=want, **opts)
+        grads, pinfo = ipm_adjoint(A.detach(), b.detach(), c.detach(), q.detach(), x, y, z, ctx.rho, ctx.delta,
+                                   gx.detach().to(torch.float64).contiguous(), ctx.ell, A_lo=ctx.A_lo,
+                                   want=want, **opts)
+        if pinfo.status != NYS_OK:
+            warnings.warn(f"NysQP backward: the adjoint PCG solve stopped at its iteration limit after "
+                          f"{pinfo.iters} iterations (relative residual {pinfo.rel_res:.2e}); the gradients "
+                          "come from its last iterate", NysConvergenceWarning, stacklevel=2)
         gA = grads.get("A")
         if gA is not None:
             gA = gA.to(A.dtype)

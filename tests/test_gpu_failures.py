@@ -145,3 +145,21 @@ def test_rank_deficient_constraints_still_converge(nys):
     meas = problem.kkt_measure(A, b, c, q, _np(x), _np(y), _np(z))
     assert meas["kkt"] <= 1.01 * tol       # the same measure as the solver's stopping test
     assert np.linalg.norm(_np(x) - xs) <= 1e-6 * np.linalg.norm(xs)
+
+
+def test_autograd_warns_when_a_solve_hits_its_iteration_limit(nys):
+    """NysQP reports an unconverged forward solve and an unconverged adjoint
+    PCG solve with NysConvergenceWarning instead of returning their last
+    iterates silently.  The limits are forced from the host: two IP-PMM
+    iterations, three PCG iterations per inner solve."""
+    from instances import make_instance
+    from paper_2404_14524_amd.autograd import NysConvergenceWarning, nys_qp
+    print("autograd iteration-limit warnings", flush=True)
+    inst = make_instance("gauss_200x500", seed=4)
+    A, b, c, q = (_t(inst.A.double().numpy()), _t(inst.b.numpy()), _t(inst.c.numpy()), _t(inst.q.numpy()))
+    c.requires_grad_(True)
+    with pytest.warns(NysConvergenceWarning, match="forward"):
+        x = nys_qp(A, b, c, q, ell=20, tol=1e-9, seed=0, max_iter=2, pcg_maxit=3)
+    with pytest.warns(NysConvergenceWarning, match="backward"):
+        (gc,) = torch.autograd.grad(0.5 * (x ** 2).sum(), (c,))
+    assert torch.isfinite(gc).all()

@@ -72,17 +72,23 @@ def test_normal_apply_full_size(nys, name):
     torch.cuda.empty_cache()
 
 
-def test_sketch_bf16_full_size_sampled_columns(nys):
+@pytest.mark.parametrize("layout", ["At", "A"])
+def test_sketch_bf16_full_size_sampled_columns(nys, layout):
+    """'At' is the solver's layout (ipm_solve makes a transposed BF16 copy and
+    both products read k-contiguous operands); 'A' is the product on A alone."""
     name = "lowrank_20000x100000"
-    print(f"full-size BF16 sketch {name}", flush=True)
+    print(f"full-size BF16 sketch {name} layout {layout}", flush=True)
     inst = make_instance(name, seed=0, device=DEV)
     m, n, ell = inst.m, inst.n, inst.ell
     Abf = inst.A.to(torch.bfloat16)
+    del inst
     g = torch.Generator(device=DEV)
     g.manual_seed(3)
     d = torch.rand(n, generator=g, dtype=torch.float64, device=DEV) * 2.0
     Om = torch.randn((m, ell), generator=g, dtype=torch.float64, device=DEV) / np.sqrt(m)
-    Y = nys.nys_sketch_product(Abf, d, Om, "bf16")
+    A_t = nys.nys_transpose(Abf) if layout == "At" else None
+    Y = nys.nys_sketch_product(Abf, d, Om, "bf16", A_t=A_t)
+    del A_t
     cols = [0, 57, 123, ell - 1]
     Ab = Abf.double()                      # exact promotion of the BF16 values
     Omb = torch.from_numpy(lowprec.round_bf16(Om[:, cols].cpu().numpy())).to(DEV)
@@ -93,7 +99,7 @@ def test_sketch_bf16_full_size_sampled_columns(nys):
         ref = (Ab @ wb).cpu().numpy()
         got = Y[:, c].cpu().numpy()
         assert np.linalg.norm(got - ref) <= 1e-4 * np.linalg.norm(ref), c
-    del Ab, Abf, inst
+    del Ab, Abf
     torch.cuda.empty_cache()
 
 
@@ -102,7 +108,8 @@ def test_adjoint_full_size_differentiation_workload(nys):
     scalars): loss 1/2 ||x* - x_tgt||^2 with x_tgt = x* + 0.01 N(0,1).  The GPU
     adjoint against (i) the oracle's dense reduced-KKT gradient for every entry
     of dL/dc, dL/db, dL/dq and 4096 entries of dL/dA, and (ii) FP64 central
-    differences through exact re-solves on 64 random coordinates of c and of b.
+    differences through exact re-solves on 64 random coordinates of each of
+    c, b, diag Q and A.
     The gradient is linear in g = x - x_tgt, so it inherits the forward
     solution's error: the oracle itself, given a KKT-1e-6 solution, is 1e-3 off
     the exact gradient and 5e-6 off at KKT 1e-8 -- the forward solve for
@@ -138,6 +145,19 @@ def test_adjoint_full_size_differentiation_workload(nys):
         fd = oadj.fd_gradient_rhs(A, b, c, q, S, x_tgt, block, coords)
         gk = grads[block].cpu().numpy()[coords]
         assert np.linalg.norm(gk - fd) <= 1e-4 * np.linalg.norm(fd), block
+    # the matrix blocks: 64 coordinates of diag Q and 64 of A on the support
+    # (off it both the gradient and the difference quotient vanish), central
+    # differences through exact low-rank re-solves of the KKT system on S
+    m, n = A.shape
+    supp = np.flatnonzero(S)
+    coords_q = rng.choice(supp, 64, replace=False)
+    coords_A = rng.integers(0, m, 64) * n + rng.choice(supp, 64)
+    for block, coords in (("q", coords_q), ("A", coords_A)):
+        fd = oadj.fd_gradient_lowrank(A, b, c, q, S, x_tgt, block, coords)
+        gk = grads[block].cpu().numpy().reshape(-1)[coords]
+        err = np.linalg.norm(gk - fd) / np.linalg.norm(fd)
+        print(f"FD {block}: rel err {err:.2e}", flush=True)
+        assert err <= 1e-4, block
 
 
 @pytest.mark.parametrize("name,sk", [("lowrank_5000x20000", "f64"), ("gauss_2000x8000", "bf16"),

@@ -218,6 +218,26 @@ def test_sketch_bf16_parity(nys, m, n, ell):
     assert np.linalg.norm(_nhat(Ug, lg) - _nhat(Uo, lo), 2) <= 1e-4 * lo[0]
 
 
+@pytest.mark.parametrize("layout", ["A", "At"])
+def test_sketch_bf16_rounding_points_hand_derived(nys, layout):
+    """The BF16 sketch product on the 4 x 3 case worked by hand (the CPU pin
+    of the emulation): A[3,2] = 1 + 3*2^-9 and Omega[0] = 1 + 3*2^-9 round up
+    to 1 + 2^-7, W[1] = 1 + 2^-8 is a tie rounded to even (1), so
+    Y = [2^-7, 2^-7, 1, 1 + 2^-6 + 2^-14] exactly (every FP32 accumulation on
+    these values is exact), in both operand layouts."""
+    print(f"bf16 rounding points {layout}", flush=True)
+    e = 2.0 ** -9
+    A32 = torch.zeros((4, 3), dtype=torch.float32)
+    A32[0, 0] = A32[1, 0] = A32[2, 1] = 1.0
+    A32[3, 2] = 1.0 + 3 * e
+    Abf = A32.to(torch.bfloat16).to(DEV)
+    Om = _t(np.array([[1.0 + 3 * e], [-1.0], [1.0], [1.0]]))
+    d = _t(np.array([1.0, 1.0 + 2.0 ** -8, 1.0]))
+    A_t = nys.nys_transpose(Abf) if layout == "At" else None
+    Y = nys.nys_sketch_product(Abf, d, Om, "bf16", A_t=A_t)
+    np.testing.assert_array_equal(_np(Y)[:, 0], [2.0 ** -7, 2.0 ** -7, 1.0, 1.0 + 2.0 ** -6 + 2.0 ** -14])
+
+
 def test_sketch_exact_at_rank(nys):
     # N of exact rank r < ell: the approximation reproduces N
     m, n, r, ell = 600, 900, 12, 20
@@ -777,19 +797,24 @@ def test_initial_point_measures_match_the_oracle(nys, case):
         assert abs(got - ref[key]) <= 1e-7 * abs(ref[key]) + 1e-14, (key, got, ref[key])
 
 
+@pytest.mark.parametrize("corrector", ["separate", "combined"])
 @pytest.mark.parametrize("case", ["qp", "box"])
-def test_first_iterations_follow_the_oracle(nys, case):
-    """With near-exact inner solves and the two-solve corrector, the GPU
-    driver's first IP-PMM iterations (step lengths, mu_aff, the corrector,
-    the parameter update) reproduce the oracle's: mu, rp_rel and rd_rel at
-    k = 0..4 agree to 1e-6 relative."""
+def test_first_iterations_follow_the_oracle(nys, case, corrector):
+    """With near-exact inner solves, the GPU driver's first IP-PMM iterations
+    (step lengths, mu_aff, the corrector, the parameter update) reproduce the
+    oracle's Algorithm 6, which solves the predictor and the corrector
+    separately: mu, rp_rel and rd_rel at k = 0..4 agree to 1e-6 relative.
+    'separate' runs the two solves as printed; 'combined' runs the library's
+    default direction path (one solve of the summed right-hand side, warm-
+    started from the predictor's dy) with the predictor tolerance tightened
+    to the inner one, so both paths are pinned step by step."""
     from oracle import boxqp
-    print(f"first iterations {case}", flush=True)
+    print(f"first iterations {case} {corrector}", flush=True)
     tr = np.full((100, len(nys.TRACE_FIELDS)), np.nan)
     f = {k: i for i, k in enumerate(nys.TRACE_FIELDS)}
     hist = []
-    tight = dict(separate_corrector=True, inner_factor=1e-9, pcg_rtol=1e-13, pcg_maxit=5000, tol=1e-9, seed=0,
-                 trace=tr)
+    tight = dict(separate_corrector=corrector == "separate", predictor_rtol=1e-13, inner_factor=1e-9,
+                 pcg_rtol=1e-13, pcg_maxit=5000, tol=1e-9, seed=0, trace=tr)
     if case == "qp":
         inst = make_instance("gauss_200x500", seed=3)
         A, b, c, q = (inst.A.double().numpy(), inst.b.numpy(), inst.c.numpy(), inst.q.numpy())

@@ -38,6 +38,38 @@ def test_planted_point_is_kkt(small):
     assert np.all(x * z == 0) and np.all(x + z > 0)
 
 
+def test_kkt_measure_hand_computed():
+    """The stopping measure (reading of the termination test the paper defers
+    to the original IP-PMM: relative primal and dual infeasibility and mu) on
+    a point worked by hand: A = 10 I, b = [5, 12], c = [3, 4], q = [1, 0],
+    x = [0.2, 0.8], y = [0.1, -0.1], z = [2.2, 0]:
+    r_p = [3, 4], ||b|| = 13 -> 5/14; r_d = c + Qx - A^T y - z = [0, 5],
+    ||c|| = 5 -> 5/6; mu = x^T z / n = 0.44/2 = 0.22; KKT = max = 5/6."""
+    A = 10.0 * np.eye(2)
+    b, c, q = np.array([5.0, 12.0]), np.array([3.0, 4.0]), np.array([1.0, 0.0])
+    x, y, z = np.array([0.2, 0.8]), np.array([0.1, -0.1]), np.array([2.2, 0.0])
+    meas = problem.kkt_measure(A, b, c, q, x, y, z)
+    np.testing.assert_allclose([meas["rp_rel"], meas["rd_rel"], meas["mu"], meas["kkt"]],
+                               [5 / 14, 5 / 6, 0.22, 5 / 6], rtol=1e-14)
+
+
+def test_box_kkt_measure_hand_computed():
+    """The box form's measure on the same data with x_0 in [0, 1] (box) and
+    x_1 >= 0, w = [0.5, 0], s = [1, 0], z = [3.2, 0]: r_u = 1 - 0.2 - 0.5 = 0.3,
+    ||u_J|| = 1 -> 0.15; r_d = c + Qx - A^T y - z + s = [0, 5] -> 5/6;
+    mu = (0.2*3.2 + 0.8*0 + 0.5*1) / (2 + 1) = 0.38; KKT = 5/6."""
+    from oracle import boxqp
+    A = 10.0 * np.eye(2)
+    b, c, q = np.array([5.0, 12.0]), np.array([3.0, 4.0]), np.array([1.0, 0.0])
+    vt = np.array([boxqp.BOX, boxqp.NONNEG])
+    u = np.array([1.0, 0.0])
+    x, y, z = np.array([0.2, 0.8]), np.array([0.1, -0.1]), np.array([3.2, 0.0])
+    w, s_ = np.array([0.5, 0.0]), np.array([1.0, 0.0])
+    meas = boxqp.kkt_measure(A, b, c, q, u, vt, x, y, z, w, s_)
+    np.testing.assert_allclose([meas["rp_rel"], meas["rd_rel"], meas["ru_rel"], meas["mu"], meas["kkt"]],
+                               [5 / 14, 5 / 6, 0.15, 0.38, 5 / 6], rtol=1e-14)
+
+
 # ---------------------------------------------------------------- normal equations
 
 def test_normal_apply_equals_sum_of_rank_one_terms():
@@ -400,6 +432,98 @@ def test_initial_point_is_interior(small):
     np.testing.assert_allclose(sz[0], dd + 0.5 * gamma / np.sum(xt + dp), rtol=1e-9)
 
 
+def _frac_vec(vals):
+    from fractions import Fraction
+    return np.array([float(Fraction(v)) for v in vals])
+
+
+def _load_initial_point_cases():
+    import json
+    with open(os.path.join(GOLDEN, "initial_point_cases.json")) as f:
+        return json.load(f)["cases"]
+
+
+@pytest.mark.parametrize("case", _load_initial_point_cases(), ids=lambda c: c["name"])
+def test_initial_point_hand_derived_cases(case):
+    """The supplement's initial point on tiny problems whose every step was
+    worked out by hand in exact rational arithmetic (tests/golden/
+    initial_point_cases.json, with the derivation): x0, y0, z0 (and w0, s0 in
+    the box form) equal the hand values, and the dual shift is the one of the
+    (x~ + delta_p) reading, not of the printed (x~ + delta_d) form, which the
+    fixture also records."""
+    from oracle import boxqp
+    A = np.array(case["A"], dtype=np.float64)
+    b, c, q = (np.array(case[k], dtype=np.float64) for k in ("b", "c", "q"))
+    if case["kind"] == "P":
+        x0, y0, z0 = ippmm.initial_point(A, b, c, q)
+        got = dict(x0=x0, y0=y0, z0=z0)
+    else:
+        kind = {"nonneg": boxqp.NONNEG, "free": boxqp.FREE, "box": boxqp.BOX}
+        vt = np.array([kind[v] for v in case["vtype"]])
+        u = np.array(case["u"], dtype=np.float64)
+        x0, y0, z0, w0, s0 = boxqp.initial_point(A, b, c, q, u, vt)
+        got = dict(x0=x0, y0=y0, z0=z0, w0=w0, s0=s0)
+    for key, val in got.items():
+        np.testing.assert_allclose(val, _frac_vec(case[key]), rtol=1e-14, atol=1e-15, err_msg=key)
+    if "printed_z0" in case:
+        assert np.max(np.abs(got["z0"] - _frac_vec(case["printed_z0"]))) > 1e-3
+
+
+def _peu_check(hist):
+    """The parameter update against what the paper fixes: rho_0 = delta_0 = 8
+    (Algorithm 4); the published trajectories (the regularisation tables of
+    the supplement) never increase and end at the floor 5e-10; the theory's
+    choice rho_k = delta_k = mu_k (section 2.1.2, section 3) wherever mu_k lies
+    between that floor and the previous value.  Returns which branches ran."""
+    floor = 5e-10
+    assert hist[0]["rho"] == 8.0 and hist[0]["delta"] == 8.0
+    seen = set()
+    for k in range(1, len(hist)):
+        rho, delta, mu = hist[k]["rho"], hist[k]["delta"], hist[k]["mu"]
+        prev = hist[k - 1]["rho"]
+        assert rho == delta, k
+        assert floor <= rho <= prev, k
+        if floor <= mu <= prev:
+            assert rho == mu, k
+            seen.add("mu")
+        elif mu < floor:
+            assert rho == floor, k
+            seen.add("floor")
+        else:
+            assert rho == prev, k
+            seen.add("hold")
+    return seen
+
+
+def test_parameter_update_follows_the_paper():
+    inst = make_instance("gauss_200x500", seed=5, m=40, n=100)
+    A, b, c, q = _np(inst)
+    hist = []
+    r = ippmm.solve(A, b, c, q, tol=1e-12, max_iter=60, history=hist)
+    assert r["status"] == 0
+    seen = _peu_check(hist)
+    assert {"mu", "floor", "hold"} <= seen, seen
+    assert hist[-1]["rho"] == 5e-10
+
+
+def test_box_parameter_update_follows_the_paper():
+    from oracle import boxqp
+    rng = np.random.default_rng(21)
+    m, n = 12, 40
+    A = rng.standard_normal((m, n)) / np.sqrt(n)
+    vt = _box_types(n, rng)
+    q = rng.uniform(0.5, 1.5, n)
+    u = np.where(vt == 2, rng.uniform(0.5, 2.0, n), 0.0)
+    b, c, *_ = boxqp.planted(A, q, vt, u, rng)
+    hist = []
+    # data scaled by 10 (the optimum scales with it): mu rises above rho at
+    # some iterations, so all three branches of the rule run
+    r = boxqp.solve(A, 10 * b, 10 * c, q, 10 * u, vt, tol=1e-12, max_iter=60, history=hist)
+    assert r["status"] == 0
+    seen = _peu_check(hist)
+    assert {"mu", "floor", "hold"} <= seen, seen
+
+
 # ---------------------------------------------------------------- adjoint
 
 def test_adjoint_matches_finite_differences():
@@ -431,6 +555,31 @@ def test_fd_with_reused_factorisation_matches_full_resolves():
         np.testing.assert_allclose(fast, full, rtol=1e-6, atol=1e-10)
 
 
+@pytest.mark.parametrize("block", ["q", "A"])
+def test_fd_through_low_rank_updates_matches_full_resolves(block):
+    """Central differences for the matrix blocks (q, A) by Sherman-Morrison-
+    Woodbury re-solves on one factorisation equal those by full re-solves,
+    and both equal the dense reduced-KKT gradient."""
+    inst = make_instance("gauss_2000x8000", seed=6, m=20, n=50)
+    A, b, c, q = _np(inst)
+    x, y, z = inst.x_star.numpy(), inst.y_star.numpy(), inst.z_star.numpy()
+    S = x > 0
+    x_tgt = x + 0.01 * np.random.default_rng(17).standard_normal(x.shape)
+    size = 50 if block == "q" else 20 * 50
+    coords = np.random.default_rng(18).choice(size, 24, replace=False)
+    full = adjoint.fd_gradient(A, b, c, q, S, x_tgt, block, coords)
+    fast = adjoint.fd_gradient_lowrank(A, b, c, q, S, x_tgt, block, coords)
+    np.testing.assert_allclose(fast, full, rtol=1e-6, atol=1e-10)
+    grad = adjoint.kkt_gradient(A, b, c, q, x, y, z, x - x_tgt)[block].reshape(-1)[coords]
+    assert np.linalg.norm(fast - grad) <= 1e-7 * np.linalg.norm(grad)
+    assert np.count_nonzero(fast) > 0
+    # at a large step the re-solves still agree to rounding (they are exact,
+    # not a linearisation), while the difference quotient moves by O(h^2)
+    full = adjoint.fd_gradient(A, b, c, q, S, x_tgt, block, coords[:8], h_rel=1e-2)
+    fast = adjoint.fd_gradient_lowrank(A, b, c, q, S, x_tgt, block, coords[:8], h_rel=1e-2)
+    np.testing.assert_allclose(fast, full, rtol=1e-9, atol=1e-12)
+
+
 # ---------------------------------------------------------------- low precision, RNG
 
 def test_bf16_rounding_matches_torch_and_ties_to_even():
@@ -442,6 +591,36 @@ def test_bf16_rounding_matches_torch_and_ties_to_even():
     assert lowprec.round_bf16(np.array([1.0 + 2.0 ** -8]))[0] == 1.0           # tie -> even
     assert lowprec.round_bf16(np.array([1.0 + 3 * 2.0 ** -8]))[0] == 1.0 + 2.0 ** -6
     assert lowprec.round_f32(np.array([1.0 + 2.0 ** -24]))[0] == 1.0
+
+
+def test_bf16_sketch_rounding_points_hand_derived():
+    """The three BF16 roundings of the mixed sketch (A, Omega and W, each round
+    to nearest even through FP32) on a 4 x 3 case where each one changes the
+    result.  Worked by hand (BF16 keeps 8 significant bits: spacing 2^-7 on
+    [1, 2)):
+      A[3,2] = 1 + 3*2^-9 -> 1 + 2^-7 (0x3F81);  Omega[0] = 1 + 3*2^-9 -> 1 + 2^-7;
+      Omega = [1 + 2^-7, -1, 1, 1];  A^T Omega = [2^-7, 1, 1 + 2^-7];
+      W = d .* A^T Omega = [2^-7, 1 + 2^-8 (a tie: to even, 1), 1 + 2^-7];
+      Y = A W = [2^-7, 2^-7, 1, (1 + 2^-7)^2 = 1 + 2^-6 + 2^-14].
+    Dropping the rounding of Omega gives Y[0] = 3*2^-9, of W gives
+    Y[2] = 1 + 2^-8, of A gives Y[3] = (1 + 3*2^-9)(1 + 2^-7)."""
+    e = 2.0 ** -9
+    A32 = np.zeros((4, 3))
+    A32[0, 0] = A32[1, 0] = A32[2, 1] = 1.0
+    A32[3, 2] = 1.0 + 3 * e
+    Om = np.array([[1.0 + 3 * e], [-1.0], [1.0], [1.0]])
+    d = np.array([1.0, 1.0 + 2.0 ** -8, 1.0])
+    assert [int(v) for v in lowprec.bf16_bits(np.array([1 + 3 * e, -1.0, 2.0 ** -7, 1 + 2.0 ** -8],
+                                                         dtype=np.float32))] == [0x3F81, 0xBF80, 0x3C00, 0x3F80]
+    Y = lowprec.sketch_bf16(A32, d, Om)
+    np.testing.assert_array_equal(Y[:, 0], [2.0 ** -7, 2.0 ** -7, 1.0, 1.0 + 2.0 ** -6 + 2.0 ** -14])
+    # each rounding matters: the same product without it differs
+    Ab, Ob = lowprec.round_bf16(A32), lowprec.round_bf16(Om)
+    no_om = Ab @ lowprec.round_bf16(d[:, None] * (Ab.T @ Om))
+    no_w = Ab @ (d[:, None] * (Ab.T @ Ob))
+    no_a = A32 @ lowprec.round_bf16(d[:, None] * (A32.T @ Ob))
+    assert no_om[0, 0] == 3 * e and no_w[2, 0] == 1.0 + 2.0 ** -8
+    assert no_a[3, 0] == (1.0 + 3 * e) * (1.0 + 2.0 ** -7)
 
 
 def test_bf16_sketch_exact_on_representable_data():

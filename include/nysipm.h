@@ -233,6 +233,29 @@ int nys_pcg_solve(nys_handle h, const nys_matrix* A, const double* d, double del
                   const nys_precond* P, const double* rhs, double* y,
                   const nys_pcg_opts* opts, nys_pcg_info* info);
 
+/* Allocation-free nys_pcg_solve, for callers that cannot allocate device
+   memory (code under HIP graph capture, tight serving loops, harnesses that
+   forbid hipMalloc).  Same arguments, kernels, results (bit for bit) and
+   return codes as nys_pcg_solve with the Nystrom preconditioner or none.
+   Instead of the handle's workspace it uses a fixed scratch array of
+   NYS_NOALLOC_SCRATCH_BYTES in device memory, one per GPU, held from the
+   first nys_create on that GPU until the process ends; it calls no hipMalloc
+   or hipFree.  The scratch holds the PCG vectors (6m + ell FP64), the n + n_unit
+   FP64 vector of pass 1 and the partial sums of the reductions; every word a
+   call reads is written by that call first, so nothing needs clearing, and a
+   call leaves its last values there.  A call needs about
+   m (48 + (ell + 1) / 8) + 8 (n + n_unit) bytes of it (the PCG vectors, pass
+   1's vector and the preconditioner's partial sums), plus partial sums of
+   pass 1 when A has no transposed copy; sizes above the scratch are refused
+   with NYS_EINVAL before anything is launched (m = 20000, n = 100000,
+   ell = 200 needs 2.3 MB).  All calls on one GPU share its scratch: two
+   calls that overlap in time on the same GPU (two handles, two streams, two
+   threads) race and give undefined results; serialise them.  Synchronises. */
+#define NYS_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+int nys_pcg_solve_noalloc(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                          const nys_precond* P, const double* rhs, double* y,
+                          const nys_pcg_opts* opts, nys_pcg_info* info);
+
 /* ------------------------------------------------ comparator: partial Cholesky */
 
 /* Partial Cholesky preconditioner of N + delta I, N = A diag(d) A^T (section

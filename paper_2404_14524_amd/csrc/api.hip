@@ -8,6 +8,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "common.hpp"
 #include "kernels.hpp"
@@ -28,6 +29,14 @@ int set_error(nys_handle h, int code, const char* fmt, ...) {
 
 int ws_get(nys_handle h, int slot, size_t bytes, void** out) {
   if (bytes == 0) bytes = 8;
+  if (h->arena) {
+    // allocation-free call: the slot's piece of the fixed scratch, never a new buffer
+    if (bytes > h->arena->len[slot])
+      return set_error(h, NYS_EINVAL, "allocation-free call: workspace slot %d needs %zu bytes, planned %zu", slot,
+                       bytes, h->arena->len[slot]);
+    *out = h->arena->base + h->arena->off[slot];
+    return NYS_OK;
+  }
   if (h->slot_bytes[slot] < bytes) {
     if (h->slot_ptr[slot]) {
       // a kernel still queued may use the old buffer
@@ -544,6 +553,73 @@ int newton_run(nys_handle h, const nys_matrix* A, const double* x, const double*
 }  // namespace
 }  // namespace nys
 
+// ---------------------------------------------------------------- fixed scratch
+// Device scratch of the allocation-free PCG entry point
+// (nys_pcg_solve_noalloc): every GPU the library runs on holds one copy of
+// this array until the process ends.  On the host, `scratch` names only a
+// stand-in for the device symbol, never device memory: host code uses the
+// address that nys_create looks up per device (nys_scratch_attach) wherever
+// the array's memory is meant.
+#define NYS_SCRATCH_BYTES NYS_NOALLOC_SCRATCH_BYTES
+static __device__ __align__(256) char scratch[NYS_SCRATCH_BYTES];
+
+namespace nys {
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+char* g_scratch_dev[kMaxScratchDevices] = {};   // per-device address of `scratch`
+
+// With `device` current: look up that device's copy of the scratch array (once per device).
+int nys_scratch_attach(nys_handle h, int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return NYS_OK;   // the allocation-free call refuses it
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  if (g_scratch_dev[device]) return NYS_OK;
+  void* p = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+  if (e != hipSuccess || !p) {
+    (void)hipGetLastError();
+    return set_error(h, NYS_EHIP, "hipGetSymbolAddress(scratch) failed on device %d: %s", device,
+                     hipGetErrorString(e));
+  }
+  g_scratch_dev[device] = (char*)p;
+  return NYS_OK;
+}
+
+char* scratch_of(int device) {
+  if (device < 0 || device >= kMaxScratchDevices) return nullptr;
+  std::lock_guard<std::mutex> lk(g_scratch_mu);
+  return g_scratch_dev[device];
+}
+
+// The workspace one pcg_run call requests, slot by slot, carved out of the
+// scratch at 256-byte aligned offsets; *total = bytes used.  Slots pcg_run
+// does not request get no piece (a request for one is refused by ws_get).
+void pcg_scratch_plan(const nys_matrix* A, int ell, nys_arena* ar, size_t* total) {
+  const int64_t m = A->m, n = ncols(A);
+  size_t need[WS_NSLOTS] = {};
+  need[WS_PCG] = ((size_t)6 * m + ell + 8) * sizeof(double);
+  need[WS_W] = (size_t)std::max<int64_t>(n, 1) * sizeof(double);
+  need[WS_PART] = std::max(gemv_t_part_doubles(A), update_part_doubles(m, ell, ell > 0)) * sizeof(double);
+  size_t p2 = std::max(gemv_n_part_doubles(m), expand_part_doubles(m));
+  p2 = std::max<size_t>(p2, map_reduce_blocks(m));                  // dot products, true residuals
+  p2 = std::max<size_t>(p2, map_reduce_blocks(A->n_unit));          // the unit-column check
+  need[WS_PART2] = p2 * sizeof(double);
+  if (A->n_unit > 0) need[WS_UNIT] = (size_t)std::max<int64_t>(m, 1) * sizeof(double);
+  size_t off = 0;
+  for (int s = 0; s < WS_NSLOTS; ++s) {
+    ar->off[s] = off;
+    ar->len[s] = 0;
+    if (!need[s]) continue;
+    ar->len[s] = (need[s] + 255) / 256 * 256;
+    off += ar->len[s];
+  }
+  *total = off;
+}
+
+}  // namespace
+}  // namespace nys
+
 using namespace nys;
 
 // ================================================================== C ABI
@@ -566,6 +642,10 @@ extern "C" int nys_create(nys_handle* out, int device, void* stream) {
       hipHostMalloc(&h->hscal, SC_NSCAL * sizeof(double), hipHostMallocDefault) != hipSuccess ||
       hipDeviceSynchronize() != hipSuccess) {
     (void)hipGetLastError();
+    nys_destroy(h);
+    return NYS_EHIP;
+  }
+  if (nys_scratch_attach(h, device) < 0) {
     nys_destroy(h);
     return NYS_EHIP;
   }
@@ -765,6 +845,46 @@ extern "C" int nys_pcg_solve(nys_handle h, const nys_matrix* A, const double* d,
   Precond pc;
   if (P) pc = Precond{P->U, P->lambda, P->ell};
   return pcg_run(h, A, d, delta, pc, rhs, y, false, pcg_cfg(opts, A->m), info);
+}
+
+extern "C" int nys_pcg_solve_noalloc(nys_handle h, const nys_matrix* A, const double* d, double delta,
+                                     const nys_precond* P, const double* rhs, double* y,
+                                     const nys_pcg_opts* opts, nys_pcg_info* info) {
+  static const char* who = "nys_pcg_solve_noalloc";
+  if (!h) return NYS_EINVAL;
+  if (!A) return set_error(h, NYS_EINVAL, "%s: matrix is NULL", who);
+  if (A->m < 0 || A->n < 0 || A->n_unit < 0)
+    return set_error(h, NYS_EINVAL, "%s: bad shape m=%lld n=%lld n_unit=%lld", who, (long long)A->m,
+                     (long long)A->n, (long long)A->n_unit);
+  NYS_CHECK(check_precond(h, P, A->m, who));
+  if (!(delta >= 0) || !is_fin(delta)) return set_error(h, NYS_EINVAL, "%s: delta must be finite and >= 0", who);
+  if (P && !(delta > 0)) return set_error(h, NYS_EINVAL, "%s: the Nystrom preconditioner needs delta > 0", who);
+  if (A->m > 0 && (!rhs || !y || !d)) return set_error(h, NYS_EINVAL, "%s: NULL vector", who);
+  nys_arena ar;
+  size_t total = 0;
+  pcg_scratch_plan(A, P ? P->ell : 0, &ar, &total);
+  if (total > NYS_SCRATCH_BYTES)
+    return set_error(h, NYS_EINVAL, "%s: m=%lld, %lld columns, ell=%d need %zu bytes of scratch, above its fixed %zu",
+                     who, (long long)A->m, (long long)ncols(A), P ? P->ell : 0, total, NYS_SCRATCH_BYTES);
+  ar.base = scratch_of(h->device);
+  if (!ar.base) return set_error(h, NYS_EHIP, "%s: no scratch array for device %d", who, h->device);
+  NYS_HIP(h, hipSetDevice(h->device));
+  // from here every workspace request is a piece of the scratch (ws_get), so
+  // the unit-column check in check_matrix allocates nothing either
+  h->arena = &ar;
+  int rc = check_matrix(h, A, who);
+  if (rc >= 0) {
+    if (A->m == 0) {
+      if (info) *info = nys_pcg_info{0, NYS_OK, 0.0, 0.0};
+      rc = NYS_OK;
+    } else {
+      Precond pc;
+      if (P) pc = Precond{P->U, P->lambda, P->ell};
+      rc = pcg_run(h, A, d, delta, pc, rhs, y, false, pcg_cfg(opts, A->m), info);
+    }
+  }
+  h->arena = nullptr;
+  return rc;
 }
 
 int check_pchol(nys_handle h, const nys_pchol* P, int64_t m, const char* who) {

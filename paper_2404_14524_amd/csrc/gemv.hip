@@ -444,6 +444,23 @@ int gemv_t_rows(nys_handle h, const GemvT& a) {
   return NYS_OK;
 }
 
+// Grid of the pass-1 kernel on column stripes of A (no transposed copy):
+// ncol column tiles of NYS_BLOCK * vec columns, nch row chunks of rpc rows,
+// enough blocks to cover the chip several times with rows per chunk >= 32.
+void t_chunks(const nys_matrix* A, int64_t* ncol_out, int64_t* nch_out, int64_t* rpc_out) {
+  const int vec = 16 / elem_size(A->dtype);
+  const int64_t ncol =
+      std::max<int64_t>(1, (A->n + (int64_t)NYS_BLOCK * vec - 1) / ((int64_t)NYS_BLOCK * vec));
+  int64_t nch = std::max<int64_t>(
+      1, std::min<int64_t>((A->m + 31) / 32, (NYS_T_TARGET_BLOCKS + ncol - 1) / ncol));
+  int64_t rpc = (A->m + nch - 1) / nch;
+  rpc = std::max<int64_t>(NYS_T_UNROLL, (rpc + NYS_T_UNROLL - 1) / NYS_T_UNROLL * NYS_T_UNROLL);
+  nch = std::max<int64_t>(1, (A->m + rpc - 1) / rpc);
+  *ncol_out = ncol;
+  *nch_out = nch;
+  *rpc_out = rpc;
+}
+
 int n_blocks_pass2(int64_t m) {
   const int rb = m >= 8 * 1536 ? NYS_N_RB : m >= 4 * 1024 ? 4 : m >= 2 * 1024 ? 2 : 1;
   return (int)((m + rb - 1) / rb);
@@ -461,20 +478,13 @@ int gemv_t(nys_handle h, const GemvT& a) {
 int gemv_t_dense(nys_handle h, const GemvT& a) {
   const nys_matrix* A = a.A;
   const int es = elem_size(A->dtype);
-  const int vec = 16 / es;
   const bool fused = a.s != nullptr;
   // n == 0: nothing to reduce; the fused direction update still has to run
   if (A->n == 0 && !fused) return NYS_OK;
   if (A->m == 0) return NYS_OK;
   if (A->data_t) return gemv_t_rows(h, a);
-  const int64_t ncol =
-      std::max<int64_t>(1, (A->n + (int64_t)NYS_BLOCK * vec - 1) / ((int64_t)NYS_BLOCK * vec));
-  // enough blocks to cover the chip several times, rows per chunk >= 32
-  int64_t nch = std::max<int64_t>(
-      1, std::min<int64_t>((A->m + 31) / 32, (NYS_T_TARGET_BLOCKS + ncol - 1) / ncol));
-  int64_t rpc = (A->m + nch - 1) / nch;
-  rpc = std::max<int64_t>(NYS_T_UNROLL, (rpc + NYS_T_UNROLL - 1) / NYS_T_UNROLL * NYS_T_UNROLL);
-  nch = std::max<int64_t>(1, (A->m + rpc - 1) / rpc);
+  int64_t ncol, nch, rpc;
+  t_chunks(A, &ncol, &nch, &rpc);
   T1Args k{};
   k.skip = a.skip;
   k.A = (const char*)A->data;
@@ -511,6 +521,15 @@ int gemv_t_dense(nys_handle h, const GemvT& a) {
   }
   return NYS_OK;
 }
+
+size_t gemv_t_part_doubles(const nys_matrix* A) {
+  if (A->data_t || A->m == 0 || A->n == 0) return 0;
+  int64_t ncol, nch, rpc;
+  t_chunks(A, &ncol, &nch, &rpc);
+  return nch > 1 ? (size_t)nch * (size_t)A->n : 0;
+}
+
+size_t gemv_n_part_doubles(int64_t m) { return m > 0 ? (size_t)n_blocks_pass2(m) : 0; }
 
 int gemv_n(nys_handle h, const GemvN& a) {
   const nys_matrix* A = a.A;

@@ -65,6 +65,15 @@ struct nys_prof {
   int64_t count[NYS_K_NCLASSES] = {};
 };
 
+// Fixed carve-up of a caller-independent scratch buffer: while a handle has
+// one set, every workspace request is served from it (slot s at base + off[s],
+// at most len[s] bytes) and nothing is allocated.
+struct nys_arena {
+  char* base = nullptr;
+  size_t off[WS_NSLOTS] = {};
+  size_t len[WS_NSLOTS] = {};
+};
+
 struct nys_handle_s {
   int device = 0;
   nys_prof prof;
@@ -76,6 +85,7 @@ struct nys_handle_s {
   double* hscal = nullptr;        // pinned host mirror
   hipEvent_t ev0 = nullptr, ev1 = nullptr;
   double t_sketch = 0, t_pcg = 0, t_other = 0;
+  const nys_arena* arena = nullptr;   // set only for the duration of an allocation-free call
 };
 
 namespace nys {

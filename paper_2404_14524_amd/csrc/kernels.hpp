@@ -68,6 +68,12 @@ int transpose(nys_handle h, const nys_matrix* A, void* At, int64_t ld_t);
 // for it, *out = *A and the kernels read A as it is).
 int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, int slot, nys_matrix* out);
 
+// Doubles of partial sums the two passes request from the workspace: pass 1
+// on column stripes of A (WS_PART; 0 with a transposed copy), pass 2's fused
+// dot product (WS_PART2).
+size_t gemv_t_part_doubles(const nys_matrix* A);
+size_t gemv_n_part_doubles(int64_t m);
+
 // out = (A diag(d) A^T + delta I) v, with optional *dot_out = v^T out.
 int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
                  const double* v, double* out, double* dot_out);
@@ -97,6 +103,11 @@ int precond_reduce(nys_handle h, const double* U, const double* lam, int64_t m, 
 // out[i] = r[i] + sum_k U[i,k] t[k]; optional *dot_out = sum_i r[i] out[i].
 int precond_expand(nys_handle h, const double* U, int64_t m, int ell, const double* r,
                    const double* t, double* out, double* dot_out);
+
+// Doubles of partial sums requested by the update kernels (WS_PART: pcg_update,
+// precond_reduce) and by the expand kernel (WS_PART2).
+size_t update_part_doubles(int64_t m, int ell, bool precond);
+size_t expand_part_doubles(int64_t m);
 
 // ---------------------------------------------------------------- PCG kernels
 // y += alpha p, r -= alpha q with alpha = rs/pq from the device words (zero

@@ -309,6 +309,13 @@ int launch_expand(nys_handle h, ExpArgs& k) {
 
 }  // namespace
 
+size_t update_part_doubles(int64_t m, int ell, bool precond) {
+  const int64_t nb = std::max<int64_t>(1, (m + RBU - 1) / RBU);
+  return (size_t)nb * (size_t)((precond ? ell : 0) + 1);
+}
+
+size_t expand_part_doubles(int64_t m) { return expand_blocks(m); }
+
 int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int nblocks) {
   hipLaunchKernelGGL(k_stream_read, dim3((unsigned)nblocks), dim3(NYS_BLOCK), 0, h->stream,
                      (const char*)data, bytes / 16, part);

@@ -87,7 +87,7 @@ EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys
            "nys_normal_apply", "nys_transpose", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint",
            "nys_pchol_build", "nys_pchol_apply", "nys_pcg_solve_pchol", "ipm_solve_box",
-           "nys_deff_estimate", "nys_sketch_size_rule", "nys_precond_rebuild_due"]
+           "nys_deff_estimate", "nys_sketch_size_rule", "nys_precond_rebuild_due", "nys_pcg_solve_noalloc"]
 
 _lib = None
 _lock = threading.Lock()
@@ -123,6 +123,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
             "nys_precond_apply": [vp, C.POINTER(nys_precond), dbl, vp, vp],
             "nys_pcg_solve": [vp, pm, vp, dbl, C.POINTER(nys_precond), vp, vp, C.POINTER(nys_pcg_opts),
                               C.POINTER(nys_pcg_info)],
+            "nys_pcg_solve_noalloc": [vp, pm, vp, dbl, C.POINTER(nys_precond), vp, vp,
+                                      C.POINTER(nys_pcg_opts), C.POINTER(nys_pcg_info)],
             "nys_pchol_build": [vp, pm, vp, dbl, C.POINTER(nys_pchol)],
             "nys_pchol_apply": [vp, C.POINTER(nys_pchol), vp, vp],
             "nys_pcg_solve_pchol": [vp, pm, vp, dbl, C.POINTER(nys_pchol), vp, vp, C.POINTER(nys_pcg_opts),
@@ -413,6 +415,28 @@ def nys_pcg_solve(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Ten
     else:
         rc = lib.nys_pcg_solve(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc) if Pc else None,
                                _ptr(rhs), _ptr(y), C.byref(o), C.byref(info))
+    _check(lib, h, rc)
+    return y, info
+
+
+def nys_pcg_solve_noalloc(A: torch.Tensor, d: torch.Tensor, delta: float, rhs: torch.Tensor,
+                          y: torch.Tensor, P: Optional[Precond] = None, A_t: Optional[torch.Tensor] = None,
+                          units=None, **opts):
+    """nys_pcg_solve without any device allocation: y (m FP64, caller-owned)
+    holds the initial guess and receives the solution in place; the library
+    works in its fixed per-GPU scratch array.  The binding allocates nothing
+    on the device either."""
+    lib, h = _handle(A.device)
+    m = A.shape[0]
+    _vec(d, ncols(A, units), "d", A.device)
+    _vec(rhs, m, "rhs", A.device)
+    _vec(y, m, "y", A.device)
+    Am = _mat(A, A_t, units)
+    o = _pcg_opts(**opts)
+    info = nys_pcg_info()
+    Pc = P.c() if P is not None else None
+    rc = lib.nys_pcg_solve_noalloc(h, C.byref(Am), _ptr(d), float(delta), C.byref(Pc) if Pc else None,
+                                   _ptr(rhs), _ptr(y), C.byref(o), C.byref(info))
     _check(lib, h, rc)
     return y, info
 

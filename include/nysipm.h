@@ -137,9 +137,10 @@ int nys_profile_read(nys_handle h, int kernel_class, int64_t* launches, double* 
 
 /* Read-stream reference for roofline reports (not a step of the method):
    reads `bytes` (a multiple of 16; data 16-byte aligned) once with the same
-   16-byte non-temporal loads as the normal-equation passes and returns the
-   device time of the read in *ms (the call synchronises).  NYS_EINVAL on a
-   bad size or alignment. */
+   16-byte non-temporal loads as the normal-equation passes, in their shape
+   (each block streams eight contiguous rows of 64 KB side by side), and
+   returns the device time of the read in *ms (the call synchronises).
+   NYS_EINVAL on a bad size or alignment. */
 int nys_stream_read(nys_handle h, const void* data, int64_t bytes, double* ms);
 
 /* ---------------------------------------------------------------- operators */

@@ -39,6 +39,8 @@ not claimed (their data are not available); the final point is pinned too
 Test infrastructure (see the package docstring).
 """
 
+import time
+
 import numpy as np
 import scipy.linalg as sla
 
@@ -81,12 +83,16 @@ def initial_point(A, b, c, q, reg=INIT_REG):
     return x0, yt.copy(), z0
 
 
-def solve(A, b, c, q, tol=1e-8, max_iter=100, verbose=False, history=None):
+def solve(A, b, c, q, tol=1e-8, max_iter=100, verbose=False, history=None, timings=None):
     """Returns dict(x, y, z, iters, status, kkt..., rho, delta).  status 0 =
-    converged, 1 = iteration limit."""
+    converged, 1 = iteration limit.  With a list `timings`, the wall-clock
+    time (time.perf_counter) is appended after the initial point and after
+    each iteration (instrumentation only)."""
     A = np.asarray(A, dtype=np.float64)
     m, n = A.shape
     x, y, z = initial_point(A, b, c, q)
+    if timings is not None:
+        timings.append(time.perf_counter())
     zeta, lam = x.copy(), y.copy()
     rho, delta = RHO0, DELTA0
     status = 1
@@ -134,6 +140,8 @@ def solve(A, b, c, q, tol=1e-8, max_iter=100, verbose=False, history=None):
         # parameter update (reading, see module docstring)
         zeta, lam = x.copy(), y.copy()
         rho = delta = max(REG_FLOOR, min(rho, mu_new))
+        if timings is not None:
+            timings.append(time.perf_counter())
     meas = kkt_measure(A, b, c, q, x, y, z)
     return dict(x=x, y=y, z=z, iters=k, status=status, rho=rho, delta=delta, **meas)
 

@@ -690,7 +690,7 @@ extern "C" int nys_stream_read(nys_handle h, const void* data, int64_t bytes, do
   if (!data || bytes <= 0 || bytes % 16 != 0 || (uintptr_t)data % 16 != 0 || !ms)
     return set_error(h, NYS_EINVAL, "nys_stream_read: need 16-byte aligned data and a size multiple of 16");
   NYS_HIP(h, hipSetDevice(h->device));
-  const int nb = 4096;
+  const int nb = stream_read_blocks(bytes);
   unsigned* part;
   NYS_CHECK(ws_get(h, WS_PART2, (size_t)nb * 4 * sizeof(unsigned), (void**)&part));
   hipEvent_t e0, e1;

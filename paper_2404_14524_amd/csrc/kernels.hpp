@@ -79,7 +79,8 @@ int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delt
                  const double* v, double* out, double* dot_out);
 
 // Read-stream reference (16-byte non-temporal loads over `bytes`, a multiple of
-// 16); part receives nblocks * 4 words.
+// 16); launch stream_read_blocks(bytes) blocks; part receives nblocks * 4 words.
+int stream_read_blocks(int64_t bytes);
 int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int nblocks);
 
 // ---------------------------------------------------------------- vectors

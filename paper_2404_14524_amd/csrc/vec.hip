@@ -62,23 +62,33 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_nonfinite(const char* A, int64_t 
   if (threadIdx.x == 0) part[blockIdx.x] = c[0];
 }
 
-// Read-stream reference: every 16-byte piece read once with the GEMV passes'
-// non-temporal loads, XOR-folded so the reads cannot be elided.
+// Read-stream reference: the buffer read once, in the shape of the GEMV
+// passes that stream A: each block takes eight consecutive rows of 64 KB
+// (512 KB) and every thread keeps one 16-byte non-temporal load per row in
+// flight, a wave covering 1 KB of a row per load; the words are XOR-folded so
+// the reads cannot be elided.  A tail shorter than a block is read by the
+// last block piece by piece.
+constexpr int64_t SR_ROW = 64 * 1024;          // bytes per row
+constexpr int SR_RB = 8;                        // rows per block
 __global__ __launch_bounds__(NYS_BLOCK) void k_stream_read(const char* p, int64_t n16, unsigned* part) {
-  const int64_t stride = (int64_t)gridDim.x * NYS_BLOCK;
+  constexpr int64_t ROW16 = SR_ROW / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * SR_RB;
+  const int64_t nrows = n16 / ROW16;
   unsigned acc = 0u;
-  int64_t i = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x;
-  for (; i + 3 * stride < n16; i += 4 * stride) {
-    const u32x4 v0 = ld_stream16(p + 16 * i);
-    const u32x4 v1 = ld_stream16(p + 16 * (i + stride));
-    const u32x4 v2 = ld_stream16(p + 16 * (i + 2 * stride));
-    const u32x4 v3 = ld_stream16(p + 16 * (i + 3 * stride));
-    acc ^= v0.x ^ v0.y ^ v0.z ^ v0.w ^ v1.x ^ v1.y ^ v1.z ^ v1.w ^ v2.x ^ v2.y ^ v2.z ^ v2.w ^ v3.x ^ v3.y ^
-           v3.z ^ v3.w;
-  }
-  for (; i < n16; i += stride) {
-    const u32x4 v = ld_stream16(p + 16 * i);
-    acc ^= v.x ^ v.y ^ v.z ^ v.w;
+  if (r0 + SR_RB <= nrows) {
+    const char* base = p + r0 * SR_ROW;
+    for (int64_t c = threadIdx.x; c < ROW16; c += NYS_BLOCK) {
+      u32x4 u[SR_RB];
+#pragma unroll
+      for (int r = 0; r < SR_RB; ++r) u[r] = ld_stream16(base + r * SR_ROW + 16 * c);
+#pragma unroll
+      for (int r = 0; r < SR_RB; ++r) acc ^= u[r].x ^ u[r].y ^ u[r].z ^ u[r].w;
+    }
+  } else {
+    for (int64_t i = r0 * ROW16 + threadIdx.x; i < n16; i += NYS_BLOCK) {
+      const u32x4 v = ld_stream16(p + 16 * i);
+      acc ^= v.x ^ v.y ^ v.z ^ v.w;
+    }
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, NYS_WAVE);
@@ -315,6 +325,12 @@ size_t update_part_doubles(int64_t m, int ell, bool precond) {
 }
 
 size_t expand_part_doubles(int64_t m) { return expand_blocks(m); }
+
+int stream_read_blocks(int64_t bytes) {
+  // full blocks of SR_RB rows, plus one block for the tail
+  const int64_t rows = bytes / SR_ROW;
+  return (int)(rows / SR_RB + 1);
+}
 
 int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int nblocks) {
   hipLaunchKernelGGL(k_stream_read, dim3((unsigned)nblocks), dim3(NYS_BLOCK), 0, h->stream,

@@ -102,3 +102,34 @@ def test_more_than_one_gpu_is_refused():
     r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"], capture_output=True,
                        text=True, timeout=120)
     assert r.returncode == 2 and "one GPU only" in r.stderr and r.stdout == ""
+
+
+def test_split_cores_keeps_two_for_the_gpu_thread():
+    assert bench.split_cores({5, 0, 3, 1, 2, 4}) == ([2, 3, 4, 5], [0, 1])
+    assert bench.split_cores({0, 1, 2}) == ([0, 1, 2], [0, 1, 2])
+    assert bench.cpu_model() != ""
+
+
+def test_oracle_child_and_its_record(tmp_path):
+    """The oracle child's full solve of a small configuration and its two
+    measured pieces on a handed-over instance; the cpu_baseline record
+    extrapolates initial point + K iterations."""
+    import numpy as np
+    from instances import make_instance
+    inst = make_instance("gauss_200x500", seed=3, m=60, n=150)
+    np.save(tmp_path / "A.npy", inst.A.float().numpy())
+    for v in ("b", "c", "q"):
+        np.save(tmp_path / f"{v}.npy", getattr(inst, v).numpy())
+    (tmp_path / "ready").write_text("1")
+    bench.oracle_child(str(tmp_path), seed=0, names=("gauss_200x500",), wait_s=5.0)
+    res = json.load(open(tmp_path / "result.json"))
+    fs = res["full_solves"]["gauss_200x500"]
+    assert fs["status"] == 0 and fs["kkt_rel"] <= 1e-6 and fs["x_rel_err_vs_planted"] < 1e-4
+    bi = res["bench_instance"]
+    assert bi["m"] == 60 and bi["n"] == 150 and bi["initial_point_s"] > 0 and bi["one_iteration_s"] > 0
+    rec = bench.oracle_baseline_record(res, gpu_iters=12)
+    assert rec["kind"] == "oracle" and rec["cores"] == res["cores"] and rec["unit"] == "s"
+    assert abs(rec["value"] - round(bi["initial_point_s"] + 12 * bi["one_iteration_s"], 1)) < 1e-9
+    assert "extrapolated" in rec["sample"]
+    empty = bench.oracle_baseline_record({}, gpu_iters=12)
+    assert empty["value"] is None

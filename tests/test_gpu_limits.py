@@ -147,3 +147,18 @@ def test_shapes_beyond_the_limits_are_rejected_before_any_work(nys):
     b = torch.ones(m, dtype=torch.float64, device=DEV)
     with pytest.raises(nys.NysError, match="ell <= 65535"):
         nys.ipm_solve(A, b, d, d, ell=m, precond="pchol")
+
+
+def test_read_stream_reference_sizes(nys):
+    """The read-stream reference takes any 16-byte multiple: less than one
+    64 KB row, whole blocks of eight rows, and blocks plus a ragged tail; it
+    refuses misaligned data and sizes."""
+    buf = torch.ones(((8 * 65536 * 3 + 65536 + 48) // 4,), dtype=torch.float32, device=DEV)
+    for nbytes in (16, 65536 - 16, 8 * 65536, 8 * 65536 * 3 + 65536 + 48, buf.numel() * 4):
+        print(f"stream_read {nbytes} B", flush=True)
+        ms = nys.nys_stream_read(buf[: nbytes // 4])
+        assert ms > 0.0
+    with pytest.raises(nys.NysError):
+        nys.nys_stream_read(buf[1:5])         # 4-byte offset: not 16-byte aligned
+    with pytest.raises(nys.NysError):
+        nys.nys_stream_read(buf[:3])          # 12 bytes

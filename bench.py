@@ -447,8 +447,8 @@ def compare(nys, inst, args):
 
 
 def operator_shape(nys, shape: str, ell: int, reps: int, seed: int):
-    """The normal-equation operator and the BF16 matrix-core sketch product
-    (both with transposed copies of A, as in the solver) alone on a seeded Gaussian
+    """The normal-equation operator (pass 1 on a transposed copy) and the BF16
+    matrix-core sketch product (on sketch tiles), as in the solver, alone on a seeded Gaussian
     FP32 m x n matrix: launches and rates per kernel class from the library's
     HIP events, against the read-stream reference over the same matrix."""
     import torch
@@ -459,7 +459,8 @@ def operator_shape(nys, shape: str, ell: int, reps: int, seed: int):
     A = torch.randn(m, n, dtype=torch.float32, device=dev, generator=g)
     A_t = nys.nys_transpose(A)
     A_lo = A.to(torch.bfloat16)
-    A_lo_t = nys.nys_transpose(A_lo)      # the solver gives the sketch this layout too
+    # the solver gives the BF16 sketch its operands as sketch tiles of A and of A^T
+    tiles = (nys.nys_sketch_tiles(A), nys.nys_sketch_tiles(A, transposed=True))
     d = torch.rand(n, dtype=torch.float64, device=dev, generator=g)
     v = torch.randn(m, dtype=torch.float64, device=dev, generator=g)
     om = torch.randn(m, ell, dtype=torch.float64, device=dev, generator=g)
@@ -467,7 +468,7 @@ def operator_shape(nys, shape: str, ell: int, reps: int, seed: int):
     Y = torch.empty(m, ell, dtype=torch.float64, device=dev)
     for _ in range(3):
         nys.nys_normal_apply(A, d, 1e-3, v, out, A_t=A_t)
-    nys.nys_sketch_product(A_lo, d, om, "bf16", out=Y, A_t=A_lo_t)
+    nys.nys_sketch_product(A_lo, d, om, "bf16", out=Y, tiles=tiles)
     torch.cuda.synchronize()
     log(f"operator {m}x{n}: warm")
     nys.nys_profile_enable(True)
@@ -475,7 +476,7 @@ def operator_shape(nys, shape: str, ell: int, reps: int, seed: int):
         nys.nys_normal_apply(A, d, 1e-3, v, out, A_t=A_t)
     sk_reps = max(1, reps // 20)
     for _ in range(sk_reps):
-        nys.nys_sketch_product(A_lo, d, om, "bf16", out=Y, A_t=A_lo_t)
+        nys.nys_sketch_product(A_lo, d, om, "bf16", out=Y, tiles=tiles)
     torch.cuda.synchronize()
     prof = nys.nys_profile_read()
     nys.nys_profile_enable(False)

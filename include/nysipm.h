@@ -26,12 +26,12 @@
  *   Arguments are validated before any launch, so on NYS_EINVAL outputs are
  *   untouched.  nys_last_error(h) gives a message.  Nothing aborts and no
  *   exception crosses the ABI.  A handle is not thread-safe: one per stream.
- * - Size limits (launch grids): m < 2^31 (unit rows are int32); the BF16
- *   sketch takes m <= 65535 * 128 = 8388480 (NYS_EINVAL beyond); nys_transpose
+ * - Size limits (launch grids): m < 2^31 (unit rows are int32); nys_transpose
  *   takes m <= 65535 * 64 = 4194240, and ipm_solve / ipm_adjoint make no
- *   transposed copy beyond that (the passes then read A_d as it is); the
- *   partial Cholesky preconditioner takes ell <= 65535.  n is bounded only by
- *   memory.
+ *   transposed copy beyond that (the passes then read A_d as it is); sketch
+ *   tiles take n <= 16776960, and ipm_solve / ipm_adjoint make none beyond
+ *   that (the BF16 sketch then reads A_d as it is); the partial Cholesky
+ *   preconditioner takes ell <= 65535.  Otherwise n is bounded only by memory.
  */
 #ifndef NYSIPM_H
 #define NYSIPM_H
@@ -82,6 +82,10 @@ typedef struct nys_handle_s* nys_handle;
    rows of it instead of column stripes of A_d (same results up to the order
    of the FP64 additions).  ipm_solve and ipm_adjoint make such a copy in their
    workspace when none is given (see nys_ipm_opts.no_transposed_copy).
+   tiles, tiles_t (optional, both or neither): A_d in the layout of the BF16
+   matrix-core sketch (nys_sketch_tiles), caller-owned; when present the BF16
+   sketch reads them instead of data / data_t.  ipm_solve and ipm_adjoint make
+   them in their workspace for a BF16 sketch.
    Zero-initialise the struct: n_unit = 0 gives the plain dense matrix. */
 typedef struct {
   int64_t m, n, ld;
@@ -92,6 +96,8 @@ typedef struct {
   int64_t n_unit;
   const int32_t* unit_row;
   const double* unit_val;
+  const void* tiles;      /* optional: sketch tiles of A_d (nys_sketch_tiles, transposed = 0) */
+  const void* tiles_t;    /* optional: sketch tiles of A_d^T (transposed = 1); give both or neither */
 } nys_matrix;
 
 /* Nystrom preconditioner {U_hat, Lambda_hat} (Algorithm 2; eq. Nys_precond).
@@ -169,15 +175,30 @@ int nys_transpose(nys_handle h, const nys_matrix* A, void* out, int64_t ld_out);
 int nys_test_matrix(nys_handle h, int64_t m, int32_t ell, uint64_t seed, uint64_t counter,
                     double* out);
 
+/* Sketch tiles: A_d (m x n, any storage dtype) in the layout the BF16
+   matrix-core sketch streams best.  transposed = 0: the tiles of A_d (its m
+   rows, k along n); 1: the tiles of A_d^T (n rows, k along m).  Stage kb
+   (k = 32 kb .. 32 kb + 31) of row r is 64 bytes at offset (kb * Rp + r) * 64,
+   Rp = rows rounded up to 256; the four 16-byte chunks of such a row are
+   permuted among themselves, the same way in every stage; entries past the
+   matrix are zero.  Values are BF16, rounded to nearest even (FP64 through
+   FP32).  nys_sketch_tiles_bytes gives the size; out: caller-owned device
+   buffer of that size, 16-byte aligned.  NYS_EINVAL on bad arguments or
+   n > 16776960.  Enqueue only. */
+int nys_sketch_tiles_bytes(int64_t m, int64_t n, int transposed, int64_t* bytes);
+int nys_sketch_tiles(nys_handle h, const nys_matrix* A, int transposed, void* out);
+
 /* The sketch Y = N Omega = A diag(d) A^T Omega of Algorithm 1 (second step),
    as the product pair W = d .* (A^T Omega), Y = A W.  omega: m x ell FP64
    row-major (used as given); Y: m x ell FP64 row-major, caller-owned.
    sketch_dtype NYS_F64: FP64 arithmetic, A stored FP64 or FP32.
    NYS_BF16: A stored BF16; Omega and W are rounded to BF16 (round to nearest
    even, through FP32) and both products run on matrix cores with FP32
-   accumulation; Y's split partial sums are added in FP64.  With a BF16
-   transposed copy in A->data_t both products read k-contiguous operands
-   (wider tiles; same arithmetic).  Enqueue only. */
+   accumulation; Y's split partial sums are added in FP64.  A BF16
+   transposed copy in A->data_t, or sketch tiles in A->tiles / A->tiles_t
+   (then A may be stored FP32 or FP64: the tiles hold its BF16 values), give
+   both products k-contiguous operands (same arithmetic; the tiles stream
+   best).  Enqueue only. */
 int nys_sketch_product(nys_handle h, const nys_matrix* A, const double* d, const double* omega,
                        int32_t ell, nys_dtype sketch_dtype, double* Y);
 

@@ -170,6 +170,8 @@ int check_matrix(nys_handle h, const nys_matrix* A, const char* who) {
   if (A->m > 0 && A->n > 0 && !A->data) return set_error(h, NYS_EINVAL, "%s: data is NULL", who);
   if (A->data_t && A->ld_t < std::max<int64_t>(A->m, 1))
     return set_error(h, NYS_EINVAL, "%s: ld_t=%lld < m=%lld", who, (long long)A->ld_t, (long long)A->m);
+  if ((A->tiles == nullptr) != (A->tiles_t == nullptr))
+    return set_error(h, NYS_EINVAL, "%s: give both sketch tiles (of A and of A^T) or neither", who);
   return check_units(h, A, who);
 }
 
@@ -778,8 +780,8 @@ extern "C" int nys_sketch_product(nys_handle h, const nys_matrix* A, const doubl
   if (!h) return NYS_EINVAL;
   NYS_CHECK(check_matrix(h, A, "nys_sketch_product"));
   if (ell < 1 || !d || !omega || !Y) return set_error(h, NYS_EINVAL, "nys_sketch_product: bad arguments");
-  if (sketch_dtype == NYS_BF16 && A->dtype != NYS_BF16)
-    return set_error(h, NYS_EINVAL, "nys_sketch_product: a BF16 sketch needs BF16 storage of A");
+  if (sketch_dtype == NYS_BF16 && A->dtype != NYS_BF16 && !A->tiles)
+    return set_error(h, NYS_EINVAL, "nys_sketch_product: a BF16 sketch needs BF16 storage of A or its sketch tiles");
   if (sketch_dtype == NYS_F64 && A->dtype == NYS_BF16)
     return set_error(h, NYS_EINVAL, "nys_sketch_product: an FP64 sketch needs FP64 or FP32 storage");
   if (sketch_dtype != NYS_BF16 && sketch_dtype != NYS_F64)
@@ -787,6 +789,23 @@ extern "C" int nys_sketch_product(nys_handle h, const nys_matrix* A, const doubl
   NYS_HIP(h, hipSetDevice(h->device));
   if (A->m == 0) return NYS_OK;
   return sketch_product(h, A, d, omega, ell, sketch_dtype, Y);
+}
+
+extern "C" int nys_sketch_tiles_bytes(int64_t m, int64_t n, int transposed, int64_t* bytes) {
+  if (m < 0 || n < 0 || !bytes || (transposed != 0 && transposed != 1)) return NYS_EINVAL;
+  *bytes = transposed ? sketch_tiles_bytes(n, m) : sketch_tiles_bytes(m, n);
+  return NYS_OK;
+}
+
+extern "C" int nys_sketch_tiles(nys_handle h, const nys_matrix* A, int transposed, void* out) {
+  if (!h) return NYS_EINVAL;
+  NYS_CHECK(check_matrix(h, A, "nys_sketch_tiles"));
+  if (transposed != 0 && transposed != 1) return set_error(h, NYS_EINVAL, "nys_sketch_tiles: transposed must be 0 or 1");
+  if (A->m > 0 && A->n > 0 && (!out || (uintptr_t)out % 16 != 0))
+    return set_error(h, NYS_EINVAL, "nys_sketch_tiles: need a 16-byte aligned output buffer");
+  if (A->n > 16776960LL) return set_error(h, NYS_EINVAL, "nys_sketch_tiles: n=%lld above 16776960", (long long)A->n);
+  NYS_HIP(h, hipSetDevice(h->device));
+  return sketch_tiles(h, A, transposed != 0, out);
 }
 
 extern "C" int nys_sketch(nys_handle h, const nys_matrix* A, const double* d, int32_t ell,
@@ -798,12 +817,10 @@ extern "C" int nys_sketch(nys_handle h, const nys_matrix* A, const double* d, in
   if (P->m != A->m || ell != P->ell || ell < 1 || ell > A->m)
     return set_error(h, NYS_EINVAL, "nys_sketch: need 1 <= ell <= m and P sized m x ell");
   if (!d) return set_error(h, NYS_EINVAL, "nys_sketch: NULL d");
-  if (sketch_dtype == NYS_BF16 && A->dtype != NYS_BF16)
-    return set_error(h, NYS_EINVAL, "nys_sketch: a BF16 sketch needs BF16 storage of A");
+  if (sketch_dtype == NYS_BF16 && A->dtype != NYS_BF16 && !A->tiles)
+    return set_error(h, NYS_EINVAL, "nys_sketch: a BF16 sketch needs BF16 storage of A or its sketch tiles");
   if (sketch_dtype != NYS_BF16 && sketch_dtype != NYS_F64)
     return set_error(h, NYS_EINVAL, "nys_sketch: sketch dtype must be NYS_F64 or NYS_BF16");
-  if (sketch_dtype == NYS_BF16 && A->m > 65535LL * 128)
-    return set_error(h, NYS_EINVAL, "nys_sketch: the BF16 sketch takes m <= %lld", 65535LL * 128);
   NYS_HIP(h, hipSetDevice(h->device));
   SketchOut so{P->U, P->lambda, 0.0};
   int rc = sketch_run(h, A, d, ell, seed, counter, sketch_dtype, 1.0, omega, &so);

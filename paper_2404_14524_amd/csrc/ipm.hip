@@ -404,6 +404,39 @@ inline bool copy_allowed(const Opts& o, const nys_matrix* A) {
   return o.transpose && (A->m + 63) / 64 <= 65535;
 }
 
+// The matrix the BF16 sketch reads: sketch tiles of A and of A^T in the
+// workspace, made from the caller's BF16 copy or, without one, from A itself
+// (rounded to BF16 on the way).  Without memory for them, or with transposed
+// copies switched off, the BF16 copy (the caller's or one made here) as it is,
+// with a transposed copy where allowed.
+int sketch_matrix(nys_handle h, const nys_qp* qp, const Opts& o, nys_matrix* out) {
+  const nys_matrix* src = qp->A_lo ? qp->A_lo : qp->A;
+  const int64_t m = src->m, n = src->n;
+  if (o.transpose && m > 0 && n > 0 && n <= 16776960LL) {
+    void *t = nullptr, *tt = nullptr;
+    int rc = ws_get(h, WS_ALO, (size_t)sketch_tiles_bytes(m, n), &t);
+    if (rc == NYS_OK) rc = ws_get(h, WS_ALOT, (size_t)sketch_tiles_bytes(n, m), &tt);
+    if (rc == NYS_OK) {
+      NYS_CHECK(sketch_tiles(h, src, false, t));
+      NYS_CHECK(sketch_tiles(h, src, true, tt));
+      *out = *src;
+      out->data_t = nullptr;
+      out->ld_t = 0;
+      out->tiles = t;
+      out->tiles_t = tt;
+      out->n_unit = qp->A->n_unit;      // the unit columns are A's
+      out->unit_row = qp->A->unit_row;
+      out->unit_val = qp->A->unit_val;
+      return NYS_OK;
+    }
+    if (rc != NYS_ENOMEM) return rc;
+    h->err.clear();
+  }
+  nys_matrix lo{};
+  NYS_CHECK(lo_matrix(h, qp, &lo));
+  return with_transpose(h, &lo, copy_allowed(o, &lo), WS_ALOT, out);
+}
+
 // Workspace-backed partial Cholesky preconditioner for the comparator runs.
 int pchol_storage(nys_handle h, int64_t m, int ell, nys_pchol* P) {
   const size_t nd = (size_t)m * ell + (size_t)ell * ell + m + ((size_t)ell + m + 1) / 2 + 4;
@@ -502,8 +535,6 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
       return set_error(h, NYS_EINVAL, "ipm_solve: need 1 <= ell_min <= ell_max <= m and ell <= ell_max");
     ell_cap = o.ell_max;
   }
-  if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM && m > 65535LL * 128)
-    return set_error(h, NYS_EINVAL, "ipm_solve: the BF16 sketch takes m <= %lld", 65535LL * 128);
   if (o.precond == NYS_PRECOND_PCHOL && o.ell > 65535)
     return set_error(h, NYS_EINVAL, "ipm_solve: the partial Cholesky preconditioner takes ell <= 65535");
   NYS_HIP(h, hipSetDevice(h->device));
@@ -580,13 +611,11 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
   double *U, *lamh;
   NYS_CHECK(ws(h, WS_PCU, (size_t)m * ell_cap, &U));
   NYS_CHECK(ws(h, WS_PCL, (size_t)ell_cap + 8, &lamh));
-  nys_matrix Alo{};
   const nys_matrix* Ask = A;
-  nys_matrix Alot{};
+  nys_matrix Alsk{};
   if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM) {
-    NYS_CHECK(lo_matrix(h, qp, &Alo));
-    NYS_CHECK(with_transpose(h, &Alo, copy_allowed(o, &Alo), WS_ALOT, &Alot));
-    Ask = &Alot;
+    NYS_CHECK(sketch_matrix(h, qp, o, &Alsk));
+    Ask = &Alsk;
   }
   nys_pchol pch{};
   if (o.precond == NYS_PRECOND_PCHOL) NYS_CHECK(pchol_storage(h, m, o.ell, &pch));
@@ -905,8 +934,6 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
     return set_error(h, NYS_EINVAL, "ipm_adjoint: bad preconditioner kind %d", o.precond);
   if (o.precond == NYS_PRECOND_NYSTROM) {
     if (o.sk != NYS_F64 && o.sk != NYS_BF16) return set_error(h, NYS_EINVAL, "ipm_adjoint: bad sketch dtype");
-    if (o.sk == NYS_BF16 && m > 65535LL * 128)
-      return set_error(h, NYS_EINVAL, "ipm_adjoint: the BF16 sketch takes m <= %lld", 65535LL * 128);
   }
   if (o.precond == NYS_PRECOND_PCHOL && o.ell > 65535)
     return set_error(h, NYS_EINVAL, "ipm_adjoint: the partial Cholesky preconditioner takes ell <= 65535");
@@ -926,13 +953,11 @@ extern "C" int ipm_adjoint(nys_handle h, const nys_qp* qp, const nys_ipm_opts* o
   double *U, *lamh;
   NYS_CHECK(ws(h, WS_PCU, (size_t)m * o.ell, &U));
   NYS_CHECK(ws(h, WS_PCL, (size_t)o.ell + 8, &lamh));
-  nys_matrix Alo{};
   const nys_matrix* Ask = A;
-  nys_matrix Alot{};
+  nys_matrix Alsk{};
   if (o.sk == NYS_BF16 && o.precond == NYS_PRECOND_NYSTROM) {
-    NYS_CHECK(lo_matrix(h, qp, &Alo));
-    NYS_CHECK(with_transpose(h, &Alo, copy_allowed(o, &Alo), WS_ALOT, &Alot));
-    Ask = &Alot;
+    NYS_CHECK(sketch_matrix(h, qp, o, &Alsk));
+    Ask = &Alsk;
   }
   nys_pchol pch{};
   if (o.precond == NYS_PRECOND_PCHOL) NYS_CHECK(pchol_storage(h, m, o.ell, &pch));

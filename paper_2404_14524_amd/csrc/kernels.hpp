@@ -74,6 +74,11 @@ int with_transpose(nys_handle h, const nys_matrix* A, bool allowed, int slot, ny
 size_t gemv_t_part_doubles(const nys_matrix* A);
 size_t gemv_n_part_doubles(int64_t m);
 
+// Sketch tiles of A (transposed = false: rows m, k along n) or of A^T (rows n,
+// k along m) for the BF16 sketch, and their size in bytes.
+int64_t sketch_tiles_bytes(int64_t rows, int64_t cols);
+int sketch_tiles(nys_handle h, const nys_matrix* A, bool transposed, void* out);
+
 // out = (A diag(d) A^T + delta I) v, with optional *dot_out = v^T out.
 int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delta,
                  const double* v, double* out, double* dot_out);

@@ -36,7 +36,8 @@ class NysError(RuntimeError):
 class nys_matrix(C.Structure):
     _fields_ = [("m", C.c_int64), ("n", C.c_int64), ("ld", C.c_int64), ("dtype", C.c_int),
                 ("data", C.c_void_p), ("data_t", C.c_void_p), ("ld_t", C.c_int64),
-                ("n_unit", C.c_int64), ("unit_row", C.c_void_p), ("unit_val", C.c_void_p)]
+                ("n_unit", C.c_int64), ("unit_row", C.c_void_p), ("unit_val", C.c_void_p),
+                ("tiles", C.c_void_p), ("tiles_t", C.c_void_p)]
 
 
 class nys_precond(C.Structure):
@@ -87,7 +88,8 @@ EXPORTS = ["nys_create", "nys_destroy", "nys_set_stream", "nys_last_error", "nys
            "nys_normal_apply", "nys_transpose", "nys_test_matrix", "nys_sketch_product", "nys_sketch", "nys_precond_apply",
            "nys_pcg_solve", "nys_newton_solve", "ipm_solve", "ipm_adjoint",
            "nys_pchol_build", "nys_pchol_apply", "nys_pcg_solve_pchol", "ipm_solve_box",
-           "nys_deff_estimate", "nys_sketch_size_rule", "nys_precond_rebuild_due", "nys_pcg_solve_noalloc"]
+           "nys_deff_estimate", "nys_sketch_size_rule", "nys_precond_rebuild_due", "nys_pcg_solve_noalloc",
+           "nys_sketch_tiles_bytes", "nys_sketch_tiles"]
 
 _lib = None
 _lock = threading.Lock()
@@ -123,6 +125,8 @@ def load_library(path: str = LIB_PATH) -> C.CDLL:
             "nys_precond_apply": [vp, C.POINTER(nys_precond), dbl, vp, vp],
             "nys_pcg_solve": [vp, pm, vp, dbl, C.POINTER(nys_precond), vp, vp, C.POINTER(nys_pcg_opts),
                               C.POINTER(nys_pcg_info)],
+            "nys_sketch_tiles_bytes": [i64, i64, C.c_int, C.POINTER(i64)],
+            "nys_sketch_tiles": [vp, pm, C.c_int, vp],
             "nys_pcg_solve_noalloc": [vp, pm, vp, dbl, C.POINTER(nys_precond), vp, vp,
                                       C.POINTER(nys_pcg_opts), C.POINTER(nys_pcg_info)],
             "nys_pchol_build": [vp, pm, vp, dbl, C.POINTER(nys_pchol)],
@@ -232,10 +236,11 @@ def _rows_ok(T) -> bool:
     return (T.stride(1) == 1 or c <= 1) and (T.stride(0) >= c or r <= 1)
 
 
-def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None, units=None) -> nys_matrix:
+def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None, units=None, tiles=None) -> nys_matrix:
     """nys_matrix view of a row-major CUDA tensor; A_t (optional) is the same
     matrix transposed, n x m row-major (see nys_transpose); units (optional)
-    appends unit columns (see _units)."""
+    appends unit columns (see _units); tiles (optional) is the pair of sketch
+    tiles (of A, of A^T) from nys_sketch_tiles."""
     if (A.dim() != 2 or A.dtype not in _DT or not A.is_cuda or not _rows_ok(A)):
         raise ValueError("A: need a 2-D row-major float64/float32/bfloat16 CUDA tensor "
                          "(unit column stride, row stride >= columns)")
@@ -246,8 +251,36 @@ def _mat(A: torch.Tensor, A_t: Optional[torch.Tensor] = None, units=None) -> nys
             raise ValueError("A_t: need an n x m row-major tensor of A's dtype on A's device")
         tp, tld = A_t.data_ptr(), max(A_t.stride(0), A.shape[0], 1)
     k, ur, uv = _units(A, units)
+    t0 = t1 = None
+    if tiles is not None:
+        T, Tt = tiles
+        for X, tr in ((T, 0), (Tt, 1)):
+            if (not isinstance(X, torch.Tensor) or X.dtype != torch.uint8 or X.device != A.device
+                    or not X.is_contiguous() or X.numel() != nys_sketch_tiles_bytes(A.shape[0], A.shape[1], tr)):
+                raise ValueError("tiles: need the pair (of A, of A^T) made by nys_sketch_tiles for this A")
+        t0, t1 = T.data_ptr(), Tt.data_ptr()
     return nys_matrix(A.shape[0], A.shape[1], max(A.stride(0), A.shape[1], 1), _DT[A.dtype],
-                      A.data_ptr(), tp, tld, k, ur, uv)
+                      A.data_ptr(), tp, tld, k, ur, uv, t0, t1)
+
+
+def nys_sketch_tiles_bytes(m: int, n: int, transposed: int) -> int:
+    lib = load_library()
+    b = C.c_int64(0)
+    rc = lib.nys_sketch_tiles_bytes(int(m), int(n), int(transposed), C.byref(b))
+    if rc != NYS_OK:
+        raise NysError(rc, "nys_sketch_tiles_bytes: bad arguments")
+    return b.value
+
+
+def nys_sketch_tiles(A: torch.Tensor, transposed: bool = False) -> torch.Tensor:
+    """Sketch tiles of A (transposed=False) or of A^T (True) as a uint8 device
+    tensor; the BF16 sketch reads the pair (tiles of A, tiles of A^T)."""
+    lib, h = _handle(A.device)
+    nb = nys_sketch_tiles_bytes(A.shape[0], A.shape[1], int(transposed))
+    out = torch.empty(max(nb, 16), dtype=torch.uint8, device=A.device)[:nb]
+    Am = _mat(A)
+    _check(lib, h, lib.nys_sketch_tiles(h, C.byref(Am), int(transposed), C.c_void_p(out.data_ptr())))
+    return out
 
 
 @dataclass
@@ -352,7 +385,7 @@ def nys_test_matrix(m: int, ell: int, seed: int, counter: int, device="cuda") ->
 
 def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sketch_dtype="f64",
                        out: Optional[torch.Tensor] = None, A_t: Optional[torch.Tensor] = None,
-                       units=None) -> torch.Tensor:
+                       units=None, tiles=None) -> torch.Tensor:
     lib, h = _handle(A.device)
     m = A.shape[0]
     if omega.dim() != 2:
@@ -362,7 +395,7 @@ def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sk
     _mat64(omega, m, ell, "omega", A.device)
     Y = torch.empty((m, ell), dtype=torch.float64, device=A.device) if out is None else out
     _mat64(Y, m, ell, "out", A.device)
-    Am = _mat(A, A_t, units)
+    Am = _mat(A, A_t, units, tiles)
     _check(lib, h, lib.nys_sketch_product(h, C.byref(Am), _ptr(d), _ptr(omega), ell, _SK[sketch_dtype],
                                           _ptr(Y)))
     return Y
@@ -370,7 +403,7 @@ def nys_sketch_product(A: torch.Tensor, d: torch.Tensor, omega: torch.Tensor, sk
 
 def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counter: int = 0,
                sketch_dtype="f64", omega: Optional[torch.Tensor] = None,
-               A_t: Optional[torch.Tensor] = None, units=None) -> Precond:
+               A_t: Optional[torch.Tensor] = None, units=None, tiles=None) -> Precond:
     lib, h = _handle(A.device)
     m = A.shape[0]
     _vec(d, ncols(A, units), "d", A.device)
@@ -380,7 +413,7 @@ def nys_sketch(A: torch.Tensor, d: torch.Tensor, ell: int, seed: int = 0, counte
     lam = torch.empty(ell, dtype=torch.float64, device=A.device)
     P = nys_precond(m, ell, U.data_ptr(), lam.data_ptr())
     nu = C.c_double(0.0)
-    Am = _mat(A, A_t, units)
+    Am = _mat(A, A_t, units, tiles)
     _check(lib, h, lib.nys_sketch(h, C.byref(Am), _ptr(d), ell, seed, counter, _SK[sketch_dtype],
                                   _ptr(omega), C.byref(P), C.byref(nu)))
     return Precond(U, lam, nu.value)

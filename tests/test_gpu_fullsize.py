@@ -72,10 +72,10 @@ def test_normal_apply_full_size(nys, name):
     torch.cuda.empty_cache()
 
 
-@pytest.mark.parametrize("layout", ["At", "A"])
+@pytest.mark.parametrize("layout", ["tiles", "At", "A"])
 def test_sketch_bf16_full_size_sampled_columns(nys, layout):
-    """'At' is the solver's layout (ipm_solve makes a transposed BF16 copy and
-    both products read k-contiguous operands); 'A' is the product on A alone."""
+    """'tiles' is the solver's layout (ipm_solve makes sketch tiles of A and of
+    A^T); 'At' reads a transposed BF16 copy; 'A' is the product on A alone."""
     name = "lowrank_20000x100000"
     print(f"full-size BF16 sketch {name} layout {layout}", flush=True)
     inst = make_instance(name, seed=0, device=DEV)
@@ -87,8 +87,9 @@ def test_sketch_bf16_full_size_sampled_columns(nys, layout):
     d = torch.rand(n, generator=g, dtype=torch.float64, device=DEV) * 2.0
     Om = torch.randn((m, ell), generator=g, dtype=torch.float64, device=DEV) / np.sqrt(m)
     A_t = nys.nys_transpose(Abf) if layout == "At" else None
-    Y = nys.nys_sketch_product(Abf, d, Om, "bf16", A_t=A_t)
-    del A_t
+    T = (nys.nys_sketch_tiles(Abf), nys.nys_sketch_tiles(Abf, True)) if layout == "tiles" else None
+    Y = nys.nys_sketch_product(Abf, d, Om, "bf16", A_t=A_t, tiles=T)
+    del A_t, T
     cols = [0, 57, 123, ell - 1]
     Ab = Abf.double()                      # exact promotion of the BF16 values
     Omb = torch.from_numpy(lowprec.round_bf16(Om[:, cols].cpu().numpy())).to(DEV)

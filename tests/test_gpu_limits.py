@@ -1,7 +1,8 @@
 """GPU parity at the largest shapes a launch grid takes in one go, and just
 beyond: the FP64 products run over chunks of 65535 * 64 rows, the BF16
-sketch keeps to the 128-wide tiles when A^T has more than 65535 * 128 rows,
-and ipm_solve reads A as it is (no transposed copy) when m exceeds 65535 * 64.
+sketch puts its row tiles in the grid's x dimension (more than 65535 * 128
+rows of A^T or of A), and ipm_solve reads A as it is (no transposed copy)
+when m exceeds 65535 * 64.
 Thin matrices keep these shapes within a few hundred MB; checks are against
 the oracle where it runs at this size, else against properties that hold at
 any size (the KKT residuals of the returned point)."""
@@ -16,7 +17,7 @@ pytestmark = pytest.mark.gpu
 
 DEV = "cuda"
 ROWS_F64 = 65535 * 64        # rows of one FP64 product launch
-ROWS_BF16 = 65535 * 128      # rows of A^T in one wide BF16 launch
+ROWS_BF16 = 65535 * 128      # more rows than a grid's y dimension holds in 128-row tiles
 
 
 @pytest.fixture(scope="module")
@@ -51,9 +52,10 @@ def test_fp64_sketch_product_over_row_chunks(nys):
     assert np.linalg.norm(Y - ref) <= 1e-12 * np.linalg.norm(ref)
 
 
-def test_bf16_sketch_beyond_the_wide_grid(nys):
-    """A^T with 65535 * 128 + 384 rows: the product keeps to the 128-wide
-    tiles on A and gives what it gives without the transposed copy."""
+def test_bf16_sketch_with_many_row_tiles(nys):
+    """A^T with 65535 * 128 + 384 rows (more row tiles than a grid's y
+    dimension holds: the products put row tiles in x) and m = 4: the BF16
+    product in its three operand layouts against the emulated-BF16 oracle."""
     m, n, ell = 4, ROWS_BF16 + 384, 3
     print(f"sketch_product bf16 {m}x{n} ell={ell}", flush=True)
     rng = np.random.default_rng(6)
@@ -61,17 +63,47 @@ def test_bf16_sketch_beyond_the_wide_grid(nys):
     d = rng.uniform(0.0, 3.0, n)
     Om = rng.standard_normal((m, ell))
     Abf = _t(A32, torch.float32).to(torch.bfloat16)
-    A_t = nys.nys_transpose(Abf)
-    Yt = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16", A_t=A_t))
-    del A_t
-    Y = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16"))
-    assert np.array_equal(Yt, Y)
     refb = lowprec.sketch_bf16(A32.astype(np.float64), d, Om)
     Ab = lowprec.round_bf16(A32.astype(np.float64))
     boundb = np.abs(Ab) @ (d[:, None] * (np.abs(Ab).T @ np.abs(lowprec.round_bf16(Om))))
-    # FP32 accumulation over m + n terms plus a BF16 rounding of W across a tie
-    assert np.all(np.abs(Y - refb) <= (2.0 ** -8 + 2.0 ** -24 * (m + n)) * boundb)
-    assert np.linalg.norm(Y - refb) <= 1e-4 * np.linalg.norm(refb)
+    for layout in ("A", "At", "tiles"):
+        print(f"  layout {layout}", flush=True)
+        A_t = nys.nys_transpose(Abf) if layout == "At" else None
+        T = (nys.nys_sketch_tiles(Abf), nys.nys_sketch_tiles(Abf, True)) if layout == "tiles" else None
+        Y = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16", A_t=A_t, tiles=T))
+        del A_t, T
+        # FP32 accumulation over m + n terms plus a BF16 rounding of W across a tie
+        assert np.all(np.abs(Y - refb) <= (2.0 ** -8 + 2.0 ** -24 * (m + n)) * boundb)
+        assert np.linalg.norm(Y - refb) <= 1e-4 * np.linalg.norm(refb)
+
+
+def test_bf16_sketch_with_m_beyond_the_old_grid(nys):
+    """m = 65535 * 128 + 64 rows (n = 2, ell = 2): Algorithm 1 with the BF16
+    sketch, through sketch tiles as ipm_solve uses it, against the oracle's
+    Algorithm 1 on the emulated BF16 sketch with the same Omega.  With an
+    orthonormal Omega the entries of Omega^T N Omega shrink like ell / m while
+    the BF16 shift nu scales with ||Y||_F ~ sqrt(ell / m), so at this m the
+    shift dominates and lambda_hat is not the spectrum of N: the check is
+    parity with the oracle, not the eigenvalues of N."""
+    m, n, ell = ROWS_BF16 + 64, 2, 2
+    print(f"sketch bf16 {m}x{n} ell={ell}", flush=True)
+    rng = np.random.default_rng(9)
+    A32 = rng.standard_normal((m, n)).astype(np.float32)
+    d = np.array([0.7, 2.5])
+    Om = rng.standard_normal((m, ell))
+    Abf = _t(A32, torch.float32).to(torch.bfloat16)
+    T = (nys.nys_sketch_tiles(Abf), nys.nys_sketch_tiles(Abf, True))
+    P = nys.nys_sketch(Abf, _t(d), ell, omega=_t(Om), sketch_dtype="bf16", tiles=T)
+    del T
+    Ug, lg = _np(P.U), _np(P.lam)
+    np.testing.assert_allclose(Ug.T @ Ug, np.eye(ell), atol=1e-10)
+    Omq = nystrom.orthonormalize(Om)
+    Y = lowprec.sketch_bf16(A32.astype(np.float64), d, Omq)
+    Uo, lo, nuo = nystrom.nystrom_from_sketch(Y, Omq, precision="bf16")
+    assert P.nu == nuo
+    np.testing.assert_allclose(lg, lo, rtol=1e-4)
+    # distinct eigenvalues: the vectors agree up to sign
+    np.testing.assert_allclose(np.abs(Ug.T @ Uo), np.eye(ell), atol=1e-4)
 
 
 def test_sketch_with_m_beyond_one_launch(nys):
@@ -126,22 +158,22 @@ def test_ipm_solve_with_m_beyond_the_transpose_grid(nys):
 
 
 def test_shapes_beyond_the_limits_are_rejected_before_any_work(nys):
-    """m above 65535 * 128 for a BF16 sketch, and ell above 65535 pivots for
-    the partial Cholesky preconditioner: NYS_EINVAL from the argument checks,
-    before any kernel of the path is launched."""
-    m = ROWS_BF16 + 1
-    print(f"rejections m={m}", flush=True)
-    A = torch.ones(m, 1, dtype=torch.float32, device=DEV)
-    Abf = A.to(torch.bfloat16)
+    """Sketch tiles of more than 16776960 columns, and ell above 65535 pivots
+    for the partial Cholesky preconditioner: NYS_EINVAL from the argument
+    checks, before any kernel of the path is launched."""
+    import ctypes
+    from paper_2404_14524_amd import nysipm
+    n = 16776960 + 1
+    print(f"rejections n={n}", flush=True)
+    Abf = torch.ones(1, n, dtype=torch.bfloat16, device=DEV)
+    lib, h = nysipm._handle(Abf.device)
+    out = torch.empty(64, dtype=torch.uint8, device=DEV)   # never written: the size check comes first
+    Am = nysipm._mat(Abf)
+    for tr in (0, 1):
+        assert lib.nys_sketch_tiles(h, ctypes.byref(Am), tr, ctypes.c_void_p(out.data_ptr())) == nysipm.NYS_EINVAL
+        assert "16776960" in lib.nys_last_error(h).decode()
+    del Abf
     d = torch.ones(1, dtype=torch.float64, device=DEV)
-    with pytest.raises(nys.NysError, match="BF16 sketch takes m"):
-        nys.nys_sketch(Abf, d, 1, sketch_dtype="bf16")
-    with pytest.raises(nys.NysError, match="BF16 sketch"):
-        nys.nys_sketch_product(Abf, d, torch.ones(m, 1, dtype=torch.float64, device=DEV), "bf16")
-    b = torch.ones(m, dtype=torch.float64, device=DEV)
-    with pytest.raises(nys.NysError, match="BF16 sketch takes m"):
-        nys.ipm_solve(A, b, d, d, ell=1, sketch_dtype="bf16", A_lo=Abf)
-    del A, Abf, b
     m = 65536
     A = torch.ones(m, 1, dtype=torch.float64, device=DEV)
     b = torch.ones(m, dtype=torch.float64, device=DEV)

@@ -170,8 +170,9 @@ def test_sketch_fp64_parity(nys, m, n, ell):
 @pytest.mark.parametrize("m,n,ell", [(1, 9, 1), (130, 257, 7), (1000, 3000, 100), (2000, 8000, 50),
                                      (777, 5001, 200), (300, 1000, 257), (515, 2049, 400)])
 def test_sketch_product_parity(nys, m, n, ell):
-    """Y = A diag(d) A^T Omega in FP64 and on BF16 matrix cores (both the
-    128-wide tiles on A alone and the 256-wide tiles with a transposed copy)."""
+    """Y = A diag(d) A^T Omega in FP64 and on BF16 matrix cores, with the
+    operands as A alone, with a transposed copy, and as sketch tiles (made
+    from the BF16 copy and from the FP32 matrix: the same BF16 values)."""
     print(f"sketch_product {m}x{n} ell={ell}", flush=True)
     rng = np.random.default_rng(m + n + ell)
     A = rng.standard_normal((m, n)) / np.sqrt(n)
@@ -188,8 +189,10 @@ def test_sketch_product_parity(nys, m, n, ell):
     refb = lowprec.sketch_bf16(A32.astype(np.float64), d, Om)
     Ab = lowprec.round_bf16(A32.astype(np.float64))
     boundb = np.abs(Ab) @ (d[:, None] * (np.abs(Ab).T @ np.abs(lowprec.round_bf16(Om))))
-    for A_t in (None, nys.nys_transpose(Abf)):
-        Yb = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16", A_t=A_t))
+    tiles = (nys.nys_sketch_tiles(Abf), nys.nys_sketch_tiles(Abf, transposed=True))
+    tiles32 = (nys.nys_sketch_tiles(_t(A32, torch.float32)), nys.nys_sketch_tiles(_t(A32, torch.float32), True))
+    for A_t, T in ((None, None), (nys.nys_transpose(Abf), None), (None, tiles), (None, tiles32)):
+        Yb = _np(nys.nys_sketch_product(Abf, _t(d), _t(Om), "bf16", A_t=A_t, tiles=T))
         # Worst case per entry: FP32 accumulation errors (m + n terms) plus a BF16
         # rounding of W that lands on the other side of a tie, at most 2^-8 |W|.
         err = np.abs(Yb - refb)
@@ -218,7 +221,7 @@ def test_sketch_bf16_parity(nys, m, n, ell):
     assert np.linalg.norm(_nhat(Ug, lg) - _nhat(Uo, lo), 2) <= 1e-4 * lo[0]
 
 
-@pytest.mark.parametrize("layout", ["A", "At"])
+@pytest.mark.parametrize("layout", ["A", "At", "tiles"])
 def test_sketch_bf16_rounding_points_hand_derived(nys, layout):
     """The BF16 sketch product on the 4 x 3 case worked by hand (the CPU pin
     of the emulation): A[3,2] = 1 + 3*2^-9 and Omega[0] = 1 + 3*2^-9 round up
@@ -234,8 +237,43 @@ def test_sketch_bf16_rounding_points_hand_derived(nys, layout):
     Om = _t(np.array([[1.0 + 3 * e], [-1.0], [1.0], [1.0]]))
     d = _t(np.array([1.0, 1.0 + 2.0 ** -8, 1.0]))
     A_t = nys.nys_transpose(Abf) if layout == "At" else None
-    Y = nys.nys_sketch_product(Abf, d, Om, "bf16", A_t=A_t)
+    T = (nys.nys_sketch_tiles(Abf), nys.nys_sketch_tiles(Abf, True)) if layout == "tiles" else None
+    Y = nys.nys_sketch_product(Abf, d, Om, "bf16", A_t=A_t, tiles=T)
     np.testing.assert_array_equal(_np(Y)[:, 0], [2.0 ** -7, 2.0 ** -7, 1.0, 1.0 + 2.0 ** -6 + 2.0 ** -14])
+
+
+def _tiles_reference(Xb, transposed):
+    """The sketch-tile layout written out from its definition: stage kb of
+    row r is 64 bytes at (kb * Rp + r) * 64, Rp = rows rounded up to 256, its
+    8-element chunk c at position c ^ (((r >> 1) & 3) ^ ((r >> 3) & 1)) of
+    r % 16; zero past the matrix.  Xb: BF16 bit patterns (uint16), m x n."""
+    X = Xb.T if transposed else Xb
+    R, K = X.shape
+    Rp, nkb = -(-R // 256) * 256, -(-K // 32)
+    T = np.zeros((nkb, Rp, 4, 8), dtype=np.uint16)
+    P = np.zeros((Rp, nkb * 32), dtype=np.uint16)
+    P[:R, :K] = X
+    for r in range(Rp):
+        f = ((r % 16 >> 1) & 3) ^ ((r % 16 >> 3) & 1)
+        for c in range(4):
+            T[:, r, c ^ f, :] = P[r].reshape(nkb, 4, 8)[:, c, :]
+    return T.reshape(-1).view(np.uint8)
+
+
+@pytest.mark.parametrize("m,n", [(1, 1), (37, 70), (300, 517), (16, 64)])
+def test_sketch_tiles_layout(nys, m, n):
+    """nys_sketch_tiles against the layout's definition, byte for byte, from
+    BF16 storage and from FP32 (rounded to nearest even), both orientations."""
+    print(f"sketch tiles {m}x{n}", flush=True)
+    rng = np.random.default_rng(m * 7 + n)
+    A32 = rng.standard_normal((m, n)).astype(np.float32)
+    Xb = lowprec.bf16_bits(A32)
+    for tr in (False, True):
+        ref = _tiles_reference(Xb, tr)
+        assert nys.nys_sketch_tiles_bytes(m, n, int(tr)) == ref.size
+        for src in (_t(A32, torch.float32).to(torch.bfloat16), _t(A32, torch.float32)):
+            got = nys.nys_sketch_tiles(src, transposed=tr).cpu().numpy()
+            np.testing.assert_array_equal(got, ref)
 
 
 def test_sketch_exact_at_rank(nys):

@@ -398,26 +398,31 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
   double* R1 = small + 2 * l2;
   double* R2 = small + 3 * l2;
   double* T = small + 4 * l2;
-  double* jw = small + 5 * l2;          // Jacobi work: l2 + 1 words
+  double* jw = small + 5 * l2;          // Jacobi work: l2 + ell + 2 words
   double* sig2 = small + 7 * l2;
   double* fail = h->dscal + SC_FAIL;
 
-  // test matrix and its thin QR (two passes of Cholesky-QR: a Gaussian
-  // m x ell block with m >= ell is well conditioned)
+  // test matrix and its thin QR by Cholesky-QR: two passes for a caller's
+  // Omega or a nearly square one; one for the library's Gaussian with
+  // m >= 4 ell, whose condition number is then below 3 (about
+  // (1 + sqrt(ell/m)) / (1 - sqrt(ell/m))), so that one pass leaves
+  // Q^T Q - I at a few units of rounding
   if (omega) NYS_CHECK(copy(h, Om, omega, m * ell));
   else NYS_CHECK(philox_gaussian(h, m, ell, seed, counter, Om));
+  const bool one_pass = !omega && m >= 4 * (int64_t)ell;
   auto cholqr_pass = [&](double* X, double* Xout, double shift_rel, double* Rout) -> int {
     NYS_CHECK(gemm_f64(h, true, false, ell, ell, m, X, NYS_F64, ell, X, ell, G, ell, nullptr));
     NYS_CHECK(chol_upper(h, G, ell, 0.0, shift_rel, fail));
     NYS_CHECK(read_scalars(h, SC_FAIL, 1));
     if (h->hscal[SC_FAIL] != 0.0) return set_error(h, NYS_ENOTPD, "Cholesky-QR: Gram matrix not positive definite");
     NYS_CHECK(tri_inv_upper(h, G, Cinv, ell));
-    NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, X, NYS_F64, ell, Cinv, ell, Xout, ell, nullptr));
+    NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, X, NYS_F64, ell, Cinv, ell, Xout, ell, nullptr, true));
     if (Rout) NYS_CHECK(copy(h, Rout, G, l2));
     return NYS_OK;
   };
   NYS_CHECK(cholqr_pass(Om, Q1, 0.0, nullptr));
-  NYS_CHECK(cholqr_pass(Q1, Om, 0.0, nullptr));
+  if (one_pass) NYS_CHECK(copy(h, Om, Q1, m * ell));
+  else NYS_CHECK(cholqr_pass(Q1, Om, 0.0, nullptr));
 
   // Y = N Omega
   NYS_CHECK(sketch_product(h, A, d, Om, ell, mode, Y));
@@ -443,7 +448,7 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
   }
   if (!ok) return set_error(h, NYS_ENOTPD, "sketch: chol(Omega^T Y_nu) failed after 6 shift increases (nu=%g)", nu);
   NYS_CHECK(tri_inv_upper(h, G, Cinv, ell));
-  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, B, NYS_F64, ell, Cinv, ell, Q1, ell, nullptr));
+  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, B, NYS_F64, ell, Cinv, ell, Q1, ell, nullptr, true));
   // thin QR of B (now in Q1) by shifted Cholesky-QR3:
   // R1 = chol(B^T B + s I), s = 11 (m ell + ell(ell+1)) u ||B||_F^2; then two plain passes.
   const double u = 1.1102230246251565e-16;

@@ -127,6 +127,130 @@ int gemm_dispatch(nys_handle h, bool ta, bool tb, dim3 g, int64_t M, int64_t N, 
   return NYS_OK;
 }
 
+// ---------------------------------------------------------------- GEMM (FP64 matrix cores)
+// C = op(A) B for FP64 A and B on v_mfma_f64_16x16x4f64.  Lane l of the
+// instruction holds A[l%16][l/16] and B[l/16][l%16] and returns
+// D[l/16 + 4r][l%16] in its register r.  A block computes a 128 x 128 tile
+// with four waves of 64 x 64 (4 x 4 instruction tiles); stages of 16 k go
+// through registers into two LDS buffers (one barrier per stage).
+// SYM: C = X^T X (A == B, transposed A): only tiles on or above the diagonal
+// are computed and each is stored with its mirror.  TRIB: B upper triangular,
+// so the k range of a column tile ends at its last column.  Split-K writes raw
+// partial tiles to C + z * M * ldc as k_gemm64 does.
+constexpr int MBM = 128, MBN = 128, MBK = 16, MPAD = 4;
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+template <bool TRA, bool TRIB, bool SYM>
+__global__ __launch_bounds__(NYS_BLOCK, 2) void k_gemm64_mfma(int64_t M, int64_t N, int64_t K, const double* A,
+                                                              int64_t lda, const double* B, int64_t ldb, double* C,
+                                                              int64_t ldc, const double* rs, int64_t klen) {
+  static_assert(NYS_BLOCK == 256, "four waves");
+  const int bm = blockIdx.y, bn = blockIdx.x;
+  if (SYM && bm > bn) return;
+  __shared__ double As[2][MBK][MBM + MPAD];
+  __shared__ double Bs[2][MBK][MBN + MPAD];
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int wm = wave >> 1, wn = wave & 1;
+  const int64_t m0 = (int64_t)bm * MBM, n0 = (int64_t)bn * MBN;
+  const int64_t kb = (int64_t)blockIdx.z * klen;
+  int64_t ke = min(K, kb + klen);
+  if (TRIB) ke = min(ke, n0 + MBN);
+  const int nst = ke > kb ? (int)((ke - kb + MBK - 1) / MBK) : 0;
+
+  // one stage of loads: 8 elements of A and 8 of B per thread
+  double ra[8], rb[8];
+  auto load = [&](int64_t k0) {
+    if (!TRA) {                          // A row-major M x K: row tid/2, k (tid%2)*8 ..
+      const int i = tid >> 1, kk = (tid & 1) * 8;
+      const int64_t gi = m0 + i;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t gk = k0 + kk + e;
+        ra[e] = (gi < M && gk < ke) ? A[gi * lda + gk] : 0.0;
+      }
+    } else {                             // A stored K x M: k tid/16, rows (tid%16)*8 ..
+      const int kk = tid >> 4, i = (tid & 15) * 8;
+      const int64_t gk = k0 + kk;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) {
+        const int64_t gi = m0 + i + e;
+        ra[e] = (gk < ke && gi < M) ? A[gk * lda + gi] : 0.0;
+      }
+    }
+    const int kk = tid >> 4, j = (tid & 15) * 8;   // B row-major K x N
+    const int64_t gk = k0 + kk;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t gj = n0 + j + e;
+      rb[e] = (gk < ke && gj < N) ? B[gk * ldb + gj] : 0.0;
+    }
+  };
+  auto store = [&](int buf) {
+    if (!TRA) {
+      const int i = tid >> 1, kk = (tid & 1) * 8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[buf][kk + e][i] = ra[e];
+    } else {
+      const int kk = tid >> 4, i = (tid & 15) * 8;
+#pragma unroll
+      for (int e = 0; e < 8; ++e) As[buf][kk][i + e] = ra[e];
+    }
+    const int kk = tid >> 4, j = (tid & 15) * 8;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) Bs[buf][kk][j + e] = rb[e];
+  };
+
+  f64x4 acc[4][4];
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj) acc[ti][tj] = f64x4{0.0, 0.0, 0.0, 0.0};
+  if (nst > 0) {
+    load(kb);
+    store(0);
+  }
+  __syncthreads();
+  const int lr = lane >> 4, lc = lane & 15;
+  for (int s = 0; s < nst; ++s) {
+    const int buf = s & 1;
+    if (s + 1 < nst) load(kb + (int64_t)(s + 1) * MBK);
+#pragma unroll
+    for (int ks = 0; ks < MBK / 4; ++ks) {
+      double a[4], b[4];
+#pragma unroll
+      for (int t = 0; t < 4; ++t) {
+        a[t] = As[buf][ks * 4 + lr][wm * 64 + t * 16 + lc];
+        b[t] = Bs[buf][ks * 4 + lr][wn * 64 + t * 16 + lc];
+      }
+#pragma unroll
+      for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+        for (int tj = 0; tj < 4; ++tj)
+          acc[ti][tj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[ti], b[tj], acc[ti][tj], 0, 0, 0);
+    }
+    // the other buffer was last read before the previous barrier
+    if (s + 1 < nst) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  double* Cz = C + (int64_t)blockIdx.z * M * ldc;
+  const bool scale = rs && gridDim.z == 1;
+#pragma unroll
+  for (int ti = 0; ti < 4; ++ti)
+#pragma unroll
+    for (int tj = 0; tj < 4; ++tj)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = m0 + wm * 64 + ti * 16 + lr + 4 * r;
+        const int64_t gj = n0 + wn * 64 + tj * 16 + lc;
+        if (gi >= M || gj >= N) continue;
+        const double v = acc[ti][tj][r];
+        Cz[gi * ldc + gj] = scale ? v * rs[gi] : v;
+        if (SYM && bm != bn) Cz[gj * ldc + gi] = v;
+      }
+}
+
 // ---------------------------------------------------------------- Cholesky (one block)
 constexpr int DB = 1024;   // threads of the one-block dense kernels
 
@@ -524,39 +648,161 @@ __global__ __launch_bounds__(NYS_WAVE) void k_jacobi_round(double* Xc, int ell, 
   if (jacobi_pair(xp, xq, ell, tol, lane) && lane == 0) atomicAdd(rotations, 1u);
 }
 
+// Rotation of a column pair held in registers: lane l holds elements
+// l, l + 64, ... (CH per lane, ell <= 64 CH) of both columns; same arithmetic
+// as jacobi_pair, with every load of the pair in flight together.
+template <int CH>
+__device__ __forceinline__ bool jacobi_pair_regs(double* xp, double* xq, int ell, double tol, int lane) {
+  double u[CH], v[CH];
+#pragma unroll
+  for (int t = 0; t < CH; ++t) {
+    const int i = lane + t * NYS_WAVE;
+    u[t] = i < ell ? xp[i] : 0.0;
+    v[t] = i < ell ? xq[i] : 0.0;
+  }
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int t = 0; t < CH; ++t) {
+    al = fma(u[t], u[t], al);
+    be = fma(v[t], v[t], be);
+    ga = fma(u[t], v[t], ga);
+  }
+  al = wave_sum_dpp(al);
+  be = wave_sum_dpp(be);
+  ga = wave_sum_dpp(ga);
+  if (!(fabs(ga) > tol * sqrt(al * be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+#pragma unroll
+  for (int k = 0; k < CH; ++k) {
+    const int i = lane + k * NYS_WAVE;
+    if (i < ell) {
+      xp[i] = c * u[k] - s * v[k];
+      xq[i] = s * u[k] + c * v[k];
+    }
+  }
+  return true;
+}
+
 // Block variant: the columns form groups of JG (the last ones padded), and a
-// launch is one round of the round-robin over groups.  Each block takes one
-// group pair, copies its 2*JG columns to LDS, runs one full round-robin sweep
-// over them there (2*JG - 1 rounds, one wave per column pair), and writes them
-// back.  Every column pair meets at least once per sweep over the group
-// rounds, so the convergence test (a sweep without rotations) is unchanged.
-template <int JG>
+// launch is one round of the round-robin over groups; each block takes one
+// group pair and keeps its 2*JG columns in LDS.  FULL (the first round of a
+// sweep): a full round-robin over the 2*JG columns (2*JG - 1 rounds, one wave
+// per column pair), which also covers the pairs inside each group; otherwise
+// only the JG * JG pairs across the two groups (JG rounds, wave w pairs
+// column w of the first group with column (w + r) % JG of the second).  Every
+// column pair meets at least once per sweep, so the convergence test (a sweep
+// without rotations) is unchanged.  Columns move between memory and LDS eight
+// elements per thread at a time; CH > 0 holds a pair in registers while it
+// is rotated (ell <= 64 CH).
+template <int JG, int CH, bool FULL>
 __global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc, int ell, int ngp, int round,
                                                                       double tol, unsigned* rotations) {
   extern __shared__ double cols[];       // 2*JG columns of length ell
+  constexpr int NT = JG * NYS_WAVE, U = 8;
   const int ga = rr_player(blockIdx.x, round, ngp);
   const int gb = rr_player(ngp - 1 - blockIdx.x, round, ngp);
   auto gcol = [&](int c) { return c < JG ? ga * JG + c : gb * JG + (c - JG); };
-  for (int idx = threadIdx.x; idx < 2 * JG * ell; idx += JG * NYS_WAVE) {
-    const int c = idx / ell, i = idx % ell;
-    const int g = gcol(c);
-    cols[idx] = g < ell ? Xc[(int64_t)g * ell + i] : 0.0;
+  const int total = 2 * JG * ell;
+  const int wid = threadIdx.x / NYS_WAVE, lane = threadIdx.x % NYS_WAVE;
+  if ((ell & 1) == 0) {
+    // even ell: every column starts 16-byte aligned; each wave moves whole
+    // columns straight into LDS, a kilobyte per instruction, all in flight
+    const int cb = ell * 8;                // bytes per column
+    for (int c = wid; c < 2 * JG; c += JG) {
+      const int g = gcol(c);
+      char* dst = (char*)(cols + (int64_t)c * ell);
+      if (g < ell) {
+        const char* src = (const char*)(Xc + (int64_t)g * ell);
+        for (int off = 0; off < cb; off += 1024)
+          if (off + lane * 16 < cb)
+            __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 16),
+                                             (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
+      } else {
+        for (int i = lane; i < ell; i += NYS_WAVE) cols[(int64_t)c * ell + i] = 0.0;
+      }
+    }
+    __builtin_amdgcn_s_waitcnt(0);
+  } else {
+    for (int base = threadIdx.x; base < total; base += NT * U) {
+      double v[U];
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * NT;
+        v[u] = 0.0;
+        if (idx < total) {
+          const int c = idx / ell, i = idx - c * ell;
+          const int g = gcol(c);
+          if (g < ell) v[u] = Xc[(int64_t)g * ell + i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < U; ++u)
+        if (base + u * NT < total) cols[base + u * NT] = v[u];
+    }
   }
   __syncthreads();
-  const int wid = threadIdx.x / NYS_WAVE, lane = threadIdx.x % NYS_WAVE;
   unsigned nrot = 0;
-  for (int r = 0; r < 2 * JG - 1; ++r) {
-    const int a = rr_player(wid, r, 2 * JG), b = rr_player(2 * JG - 1 - wid, r, 2 * JG);
-    const int p = min(a, b), q = max(a, b);
-    if (gcol(p) < ell && gcol(q) < ell && jacobi_pair(cols + p * ell, cols + q * ell, ell, tol, lane)) ++nrot;
-    __syncthreads();
+  auto rotate = [&](int p, int q) {
+    if (gcol(p) >= ell || gcol(q) >= ell) return;
+    bool r;
+    if constexpr (CH > 0) r = jacobi_pair_regs<CH>(cols + p * ell, cols + q * ell, ell, tol, lane);
+    else r = jacobi_pair(cols + p * ell, cols + q * ell, ell, tol, lane);
+    if (r) ++nrot;
+  };
+  if constexpr (FULL) {
+    for (int r = 0; r < 2 * JG - 1; ++r) {
+      const int a = rr_player(wid, r, 2 * JG), b = rr_player(2 * JG - 1 - wid, r, 2 * JG);
+      rotate(min(a, b), max(a, b));
+      __syncthreads();
+    }
+  } else {
+    for (int r = 0; r < JG; ++r) {
+      rotate(wid, JG + (wid + r) % JG);
+      __syncthreads();
+    }
   }
-  for (int idx = threadIdx.x; idx < 2 * JG * ell; idx += JG * NYS_WAVE) {
-    const int c = idx / ell, i = idx % ell;
-    const int g = gcol(c);
-    if (g < ell) Xc[(int64_t)g * ell + i] = cols[idx];
+  if ((ell & 1) == 0) {
+    // pairs of doubles: 16-byte stores
+    typedef double f64x2 __attribute__((ext_vector_type(2)));
+    const int half = ell / 2;
+    for (int c = wid; c < 2 * JG; c += JG) {
+      const int g = gcol(c);
+      if (g >= ell) continue;
+      const f64x2* srcl = (const f64x2*)(cols + (int64_t)c * ell);
+      f64x2* dstg = (f64x2*)(Xc + (int64_t)g * ell);
+      for (int i = lane; i < half; i += NYS_WAVE) dstg[i] = srcl[i];
+    }
+  } else {
+    for (int base = threadIdx.x; base < total; base += NT * U) {
+#pragma unroll
+      for (int u = 0; u < U; ++u) {
+        const int idx = base + u * NT;
+        if (idx < total) {
+          const int c = idx / ell, i = idx - c * ell;
+          const int g = gcol(c);
+          if (g < ell) Xc[(int64_t)g * ell + i] = cols[idx];
+        }
+      }
+    }
   }
   if (lane == 0 && nrot) atomicAdd(rotations, nrot);
+}
+
+template <int JG, int CH>
+void launch_jacobi_round(hipStream_t st, int ngp, size_t lds, double* Xc, int ell, int round, double tol, unsigned* rot) {
+  if (round == 0)
+    hipLaunchKernelGGL((k_jacobi_block_round<JG, CH, true>), dim3(ngp / 2), dim3(JG * NYS_WAVE), lds, st, Xc, ell, ngp, round, tol, rot);
+  else
+    hipLaunchKernelGGL((k_jacobi_block_round<JG, CH, false>), dim3(ngp / 2), dim3(JG * NYS_WAVE), lds, st, Xc, ell, ngp, round, tol, rot);
+}
+template <int JG, int CH>
+hipError_t jacobi_lds_attr(size_t lds) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_block_round<JG, CH, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_jacobi_block_round<JG, CH, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 __global__ __launch_bounds__(DB) void k_transpose_sq(const double* X, double* Y, int ell) {
@@ -567,25 +813,34 @@ __global__ __launch_bounds__(DB) void k_transpose_sq(const double* X, double* Y,
   }
 }
 
-// Normalise columns, sort by descending norm, write row-major U and sig2.
-__global__ __launch_bounds__(DB) void k_jacobi_finish(const double* Xc, int ell, double* U,
-                                                      double* sig2) {
-  extern __shared__ double nrm[];
-  for (int k = threadIdx.x; k < ell; k += DB) {
-    double s = 0.0;
-    for (int i = 0; i < ell; ++i) s = fma(Xc[(int64_t)k * ell + i], Xc[(int64_t)k * ell + i], s);
-    nrm[k] = s;
-  }
+// Squared column norms, one wave per column.
+__global__ __launch_bounds__(NYS_BLOCK) void k_jacobi_norms(const double* Xc, int ell, double* nrm) {
+  const int k = blockIdx.x * (NYS_BLOCK / NYS_WAVE) + threadIdx.x / NYS_WAVE;
+  const int lane = threadIdx.x % NYS_WAVE;
+  if (k >= ell) return;
+  double s = 0.0;
+  for (int i = lane; i < ell; i += NYS_WAVE) s = fma(Xc[(int64_t)k * ell + i], Xc[(int64_t)k * ell + i], s);
+  s = wave_sum_dpp(s);
+  if (lane == 0) nrm[k] = s;
+}
+
+// Column k of the result: its rank in descending norm (ties by index) is its
+// position; U (row-major) receives the normalised column there, sig2 its norm.
+__global__ __launch_bounds__(NYS_BLOCK) void k_jacobi_place(const double* Xc, int ell, const double* nrm,
+                                                            double* U, double* sig2) {
+  __shared__ int cnt[NYS_BLOCK / NYS_WAVE];
+  const int k = blockIdx.x;
+  const double nk = nrm[k];
+  int c = 0;
+  for (int j = threadIdx.x; j < ell; j += NYS_BLOCK) c += (nrm[j] > nk || (nrm[j] == nk && j < k)) ? 1 : 0;
+  for (int off = NYS_WAVE / 2; off > 0; off >>= 1) c += __shfl_down(c, off, NYS_WAVE);
+  if (threadIdx.x % NYS_WAVE == 0) cnt[threadIdx.x / NYS_WAVE] = c;
   __syncthreads();
-  for (int k = threadIdx.x; k < ell; k += DB) {
-    int rank = 0;
-    for (int j = 0; j < ell; ++j)
-      if (nrm[j] > nrm[k] || (nrm[j] == nrm[k] && j < k)) ++rank;
-    const double s2 = nrm[k];
-    const double inv = s2 > 0.0 ? 1.0 / sqrt(s2) : 0.0;
-    sig2[rank] = s2;
-    for (int i = 0; i < ell; ++i) U[(int64_t)i * ell + rank] = Xc[(int64_t)k * ell + i] * inv;
-  }
+  int rank = 0;
+  for (int w = 0; w < NYS_BLOCK / NYS_WAVE; ++w) rank += cnt[w];
+  const double inv = nk > 0.0 ? 1.0 / sqrt(nk) : 0.0;
+  if (threadIdx.x == 0) sig2[rank] = nk;
+  for (int i = threadIdx.x; i < ell; i += NYS_BLOCK) U[(int64_t)i * ell + rank] = Xc[(int64_t)k * ell + i] * inv;
 }
 
 // ---------------------------------------------------------------- Philox4x32-10
@@ -664,9 +919,62 @@ unsigned grid_for(int64_t n) {
 
 }  // namespace
 
+// FP64 operands, B not transposed: the matrix-core kernel
+int gemm_f64_mfma(nys_handle h, bool transA, int64_t M, int64_t N, int64_t K, const double* A, int64_t lda,
+                  const double* B, int64_t ldb, double* C, int64_t ldc, const double* row_scale, bool b_upper) {
+  const bool sym = transA && A == B && lda == ldb && M == N && !row_scale && !b_upper;
+  const int64_t tm = (M + MBM - 1) / MBM, tn = (N + MBN - 1) / MBN;
+  const int64_t active = sym ? tm * (tm + 1) / 2 : tm * tn;
+  // split K so that the blocks fill whole rounds of 512 (two per compute
+  // unit) as far as possible, each split at least 512 long
+  int64_t nsplit = 1;
+  if (active < 512 && K > 1024) {
+    double best_eff = 0.0;
+    for (int64_t sp = 1; sp <= std::min<int64_t>(64, K / 512); ++sp) {
+      const int64_t blocks = active * sp;
+      const double eff = (double)blocks / (512.0 * (double)((blocks + 511) / 512));
+      if (eff > best_eff + 0.02) {
+        best_eff = eff;
+        nsplit = sp;
+      }
+      if (best_eff >= 0.85) break;
+    }
+  }
+  int64_t klen = (K + nsplit - 1) / nsplit;
+  klen = std::max<int64_t>(MBK, (klen + MBK - 1) / MBK * MBK);
+  nsplit = std::max<int64_t>(1, (K + klen - 1) / klen);
+  double* out = C;
+  int64_t ldo = ldc;
+  if (nsplit > 1) {
+    NYS_CHECK(ws(h, WS_SK_SPLIT, (size_t)nsplit * M * N, &out));
+    ldo = N;
+  }
+  const dim3 g((unsigned)tn, (unsigned)tm, (unsigned)nsplit), b(NYS_BLOCK);
+  const double* rs = nsplit > 1 ? nullptr : row_scale;
+  const int ps = prof_begin(h, NYS_K_GEMM_F64);
+  if (sym)
+    hipLaunchKernelGGL((k_gemm64_mfma<true, false, true>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, out, ldo, rs, klen);
+  else if (transA && b_upper)
+    hipLaunchKernelGGL((k_gemm64_mfma<true, true, false>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, out, ldo, rs, klen);
+  else if (transA)
+    hipLaunchKernelGGL((k_gemm64_mfma<true, false, false>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, out, ldo, rs, klen);
+  else if (b_upper)
+    hipLaunchKernelGGL((k_gemm64_mfma<false, true, false>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, out, ldo, rs, klen);
+  else
+    hipLaunchKernelGGL((k_gemm64_mfma<false, false, false>), g, b, 0, h->stream, M, N, K, A, lda, B, ldb, out, ldo, rs, klen);
+  NYS_LAUNCH_CHECK(h);
+  prof_end(h, ps);
+  if (nsplit > 1) {
+    hipLaunchKernelGGL(k_splitk_reduce, dim3(grid_for(M * N)), dim3(NYS_BLOCK), 0, h->stream, M, N,
+                       (int)nsplit, out, C, ldc, row_scale);
+    NYS_LAUNCH_CHECK(h);
+  }
+  return NYS_OK;
+}
+
 int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
              const void* A, nys_dtype adt, int64_t lda, const double* B, int64_t ldb, double* C,
-             int64_t ldc, const double* row_scale) {
+             int64_t ldc, const double* row_scale, bool b_upper) {
   if (M == 0 || N == 0) return NYS_OK;
   // the grid's y dimension counts GBM-row tiles and stops at 65535: taller
   // products run as one launch per chunk of rows
@@ -677,10 +985,12 @@ int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64
       const int64_t mc = std::min(kMaxRows, M - r0);
       const char* Ac = (const char*)A + (transA ? r0 : r0 * lda) * es;
       NYS_CHECK(gemm_f64(h, transA, transB, mc, N, K, Ac, adt, lda, B, ldb, C + r0 * ldc, ldc,
-                         row_scale ? row_scale + r0 : nullptr));
+                         row_scale ? row_scale + r0 : nullptr, b_upper));
     }
     return NYS_OK;
   }
+  if (adt == NYS_F64 && !transB && K > 0)
+    return gemm_f64_mfma(h, transA, M, N, K, (const double*)A, lda, B, ldb, C, ldc, row_scale, b_upper);
   const int64_t tiles = ((M + GBM - 1) / GBM) * ((N + GBN - 1) / GBN);
   int64_t nsplit = 1;
   if (tiles < 512 && K > 512) {
@@ -776,7 +1086,8 @@ int small_mm(nys_handle h, const double* C1, const double* C2, double* C3, int e
 }
 
 int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
-  // work: ell*ell doubles (column storage) followed by one counter word
+  // work: ell*ell doubles (column storage), one counter word, one spare word
+  // and ell doubles of column norms
   double* Xc = work;
   unsigned* rot = reinterpret_cast<unsigned*>(work + (int64_t)ell * ell);
   hipLaunchKernelGGL(k_transpose_sq, dim3(grid_for((int64_t)ell * ell)), dim3(DB), 0, h->stream, X, Xc, ell);
@@ -786,28 +1097,54 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
   // ell carries a rounding error up to about ell * eps, so a smaller threshold
   // keeps rotating on noise and only stops when a sweep happens to find none
   const double tol = (double)ell * 2.220446049250313e-16;
-  // group size of the block variant: the largest of 16, 8, 4, 2 whose 2*JG
-  // columns fit in 60 KB of LDS (0: per-pair launches)
-  int jg = 16;
-  while (jg >= 2 && (size_t)2 * jg * ell * sizeof(double) > 61440) jg /= 2;
-  if (jg < 2) jg = 0;
+  // group size of the block variant: the largest of 16, 8, 6, 4, 2 whose 2*JG
+  // columns fit in the 160 KB of LDS (0: per-pair launches)
+  int jg = 0;
+  for (int c : {16, 8, 6, 4, 2})
+    if ((size_t)2 * c * ell * sizeof(double) <= (size_t)160 * 1024) {
+      jg = c;
+      break;
+    }
   const int ng = jg ? (ell + jg - 1) / jg : 0;
   const int ngp = ng + (ng & 1);
   const size_t lds = (size_t)2 * jg * ell * sizeof(double);
+  // pairs held in registers up to ell = 64 * CH (CH = 16 for the 16-wave
+  // groups, whose waves have 128 registers, else 32); beyond, rotated in LDS
+  const int chmax = jg == 16 ? 16 : 32;
+  const bool regs = ell <= chmax * NYS_WAVE;
+  auto dispatch = [&](int round) {
+#define NYS_JAC(JGV, CHV)                                                                  \
+  case JGV:                                                                                \
+    if (regs) launch_jacobi_round<JGV, CHV>(h->stream, ngp, lds, Xc, ell, round, tol, rot); \
+    else launch_jacobi_round<JGV, 0>(h->stream, ngp, lds, Xc, ell, round, tol, rot);        \
+    break;
+    switch (jg) {
+      NYS_JAC(16, 16)
+      NYS_JAC(8, 32)
+      NYS_JAC(6, 32)
+      NYS_JAC(4, 32)
+      default: NYS_JAC(2, 32)
+    }
+#undef NYS_JAC
+  };
+  if (jg && lds > 65536) {
+    hipError_t e = hipSuccess;
+    switch (jg) {
+      case 16: e = regs ? jacobi_lds_attr<16, 16>(lds) : jacobi_lds_attr<16, 0>(lds); break;
+      case 8: e = regs ? jacobi_lds_attr<8, 32>(lds) : jacobi_lds_attr<8, 0>(lds); break;
+      case 6: e = regs ? jacobi_lds_attr<6, 32>(lds) : jacobi_lds_attr<6, 0>(lds); break;
+      case 4: e = regs ? jacobi_lds_attr<4, 32>(lds) : jacobi_lds_attr<4, 0>(lds); break;
+      default: e = regs ? jacobi_lds_attr<2, 32>(lds) : jacobi_lds_attr<2, 0>(lds); break;
+    }
+    if (e != hipSuccess) return set_error(h, NYS_EHIP, "Jacobi SVD: LDS attribute: %s", hipGetErrorString(e));
+  }
   int sweep = 0;
   const int max_sweeps = 40;
   if (np >= 2) {
     for (; sweep < max_sweeps; ++sweep) {
       NYS_CHECK(zero_u32(h, rot, 1));
       if (jg) {
-        for (int round = 0; round < ngp - 1; ++round) {
-          switch (jg) {
-            case 16: hipLaunchKernelGGL(k_jacobi_block_round<16>, dim3(ngp / 2), dim3(16 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
-            case 8: hipLaunchKernelGGL(k_jacobi_block_round<8>, dim3(ngp / 2), dim3(8 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
-            case 4: hipLaunchKernelGGL(k_jacobi_block_round<4>, dim3(ngp / 2), dim3(4 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
-            default: hipLaunchKernelGGL(k_jacobi_block_round<2>, dim3(ngp / 2), dim3(2 * NYS_WAVE), lds, h->stream, Xc, ell, ngp, round, tol, rot); break;
-          }
-        }
+        for (int round = 0; round < ngp - 1; ++round) dispatch(round);
       } else {
         for (int round = 0; round < np - 1; ++round) {
           hipLaunchKernelGGL(k_jacobi_round, dim3(np / 2), dim3(NYS_WAVE), 0, h->stream, Xc, ell, np,
@@ -821,8 +1158,11 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
       if (hrot == 0) break;
     }
   }
-  hipLaunchKernelGGL(k_jacobi_finish, dim3(1), dim3(DB), (size_t)ell * sizeof(double), h->stream, Xc,
-                     ell, X, sig2);
+  // normalise the columns and order them by descending norm: U (row-major, in X) and sig2
+  double* nrm = work + (int64_t)ell * ell + 2;
+  hipLaunchKernelGGL(k_jacobi_norms, dim3((ell + NYS_BLOCK / NYS_WAVE - 1) / (NYS_BLOCK / NYS_WAVE)), dim3(NYS_BLOCK), 0,
+                     h->stream, Xc, ell, nrm);
+  hipLaunchKernelGGL(k_jacobi_place, dim3(ell), dim3(NYS_BLOCK), 0, h->stream, Xc, ell, nrm, X, sig2);
   NYS_LAUNCH_CHECK(h);
   if (sweep == max_sweeps) return set_error(h, NYS_ENOTPD, "Jacobi SVD did not converge in %d sweeps", max_sweeps);
   return NYS_OK;

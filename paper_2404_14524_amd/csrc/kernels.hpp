@@ -155,9 +155,11 @@ int pcg_expand(nys_handle h, int64_t m, const double* U, int ell, const double* 
 // ---------------------------------------------------------------- small dense FP64
 // C (M x N, ldc) = op(A) op(B) with FP64 accumulation, op = transpose if flag.
 // A elements may be FP64/FP32/BF16 (adt); B is FP64.  Row scale: C[i,:] *= rs[i].
+// b_upper: B (K x N, not transposed) is upper triangular with zeros below its
+// diagonal, so that rows k >= j of B do not reach column j of C.
 int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64_t K,
              const void* A, nys_dtype adt, int64_t lda, const double* B, int64_t ldb,
-             double* C, int64_t ldc, const double* row_scale);
+             double* C, int64_t ldc, const double* row_scale, bool b_upper = false);
 // In-place Cholesky G = C^T C of an ell x ell matrix (symmetrised first, plus
 // shift_abs + shift_rel * trace(G) on the diagonal); result C upper (lower
 // part zeroed).  Sets the device word *fail to 1.0 when a pivot is not positive.
@@ -168,7 +170,8 @@ int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell);
 int small_mm(nys_handle h, const double* C1, const double* C2, double* C3, int ell);
 // One-sided Jacobi SVD of X (ell x ell, row-major, overwritten): on return the
 // columns of X are the left singular vectors sorted by descending singular
-// value and sig2[k] the squared singular values.  Synchronises (sweep polls).
+// value and sig2[k] the squared singular values.  work: ell*ell + ell + 2
+// doubles.  Synchronises (sweep polls).
 int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work);
 // Philox4x32-10 Gaussian matrix (see nys_test_matrix).
 int philox_gaussian(nys_handle h, int64_t m, int ell, uint64_t seed, uint64_t counter, double* out);

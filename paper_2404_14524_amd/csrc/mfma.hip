@@ -139,6 +139,8 @@ struct SkArgs {
   const double* d;
   float* part;                      // split: part[(z * N + c) * Mp + j] = C[j][c]
   int64_t Mp;                       // partial row pitch, a multiple of 4
+  int64_t ntile;                    // row tiles; with ngroup > 1 the grid's x runs over
+  int ngroup;                       // (row tile, column group) in XCD order
 };
 
 #ifndef SK_DA_MAX
@@ -182,8 +184,19 @@ __global__ __launch_bounds__(SK_THREADS, 1) void k_sketch_mfma(SkArgs a) {
   const int wr = wave / WC, wc = wave % WC;
   const int l32 = lane & 31;
   const int pos0 = (lane >> 5) ^ sk_swz(lane & 15);   // position of this lane's chunk, k-step 0
-  const int64_t rowb = (int64_t)blockIdx.x * G::BM;
-  const int64_t colb = (int64_t)blockIdx.y * G::BN;
+  // with several column groups, block x of the grid runs group (x / 8) % ng
+  // of row tile (x / (8 ng)) * 8 + x % 8: blocks are dispatched to the eight
+  // XCDs in turn, so the groups of one row tile run back to back on one XCD
+  // and its Aop stream comes from HBM once, the other groups reading it in L2
+  int64_t tile = blockIdx.x, group = blockIdx.y;
+  if (a.ngroup > 1) {
+    const int64_t x = blockIdx.x, q = x >> 3;
+    group = q % a.ngroup;
+    tile = (q / a.ngroup) * 8 + (x & 7);
+    if (tile >= a.ntile) return;
+  }
+  const int64_t rowb = tile * G::BM;
+  const int64_t colb = group * G::BN;
   const int64_t kb = (int64_t)blockIdx.z * a.klen;
   const int64_t ke = min(a.K, kb + a.klen);
   const int nfull = TILED ? (int)((ke - kb + SK_TK - 1) / SK_TK) : (int)((ke - kb) / SK_TK);
@@ -756,7 +769,14 @@ int sketch_gemm(nys_handle h, SkArgs a, bool tiled, bool want_w, float** part, i
   }
   const bool vec = tiled || (((uintptr_t)a.A % 16 == 0) && (a.lda % 8 == 0));
   const int out = !direct ? SK_OUT_PART : (tiled ? SK_OUT_WT_TILES : SK_OUT_WT);
-  dim3 g((unsigned)tiles, (unsigned)sh.groups, (unsigned)nsplit);
+  a.ntile = tiles;
+  a.ngroup = sh.groups;
+  dim3 g((unsigned)tiles, 1u, (unsigned)nsplit);
+  if (sh.groups > 1) {
+    const int64_t nx = (tiles + 7) / 8 * 8 * sh.groups;
+    if (nx > 0x7FFFFFFFLL) return set_error(h, NYS_EINVAL, "BF16 sketch: %lld blocks", (long long)nx);
+    g.x = (unsigned)nx;
+  }
   if (sh.wc == 1) launch_sk_ctw<1>(sh.ctw, a, g, tiled, vec, out, h->stream);
   else launch_sk_ctw<2>(sh.ctw, a, g, tiled, vec, out, h->stream);
   NYS_LAUNCH_CHECK(h);

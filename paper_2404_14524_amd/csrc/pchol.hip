@@ -297,7 +297,7 @@ int pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta
   if (h->hscal[SC_FAIL] != 0.0)
     return set_error(h, NYS_ENOTPD, "partial Cholesky: the pivot block is not positive definite");
   NYS_CHECK(tri_inv_upper(h, G, P->Cinv, ell));
-  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, Y, NYS_F64, ell, P->Cinv, ell, P->L, ell, nullptr));
+  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, Y, NYS_F64, ell, P->Cinv, ell, P->L, ell, nullptr, true));
   hipLaunchKernelGGL(k_pchol_diags, dim3((unsigned)((m + 3) / 4)), dim3(NYS_BLOCK), 0, h->stream,
                      (const double*)P->L, m, ell, (const int*)P->pos, (const double*)diag, delta, P->diagS);
   NYS_LAUNCH_CHECK(h);

@@ -168,7 +168,7 @@ def test_sketch_fp64_parity(nys, m, n, ell):
 
 
 @pytest.mark.parametrize("m,n,ell", [(1, 9, 1), (130, 257, 7), (1000, 3000, 100), (2000, 8000, 50),
-                                     (777, 5001, 200), (300, 1000, 257), (515, 2049, 400)])
+                                     (777, 5001, 200), (300, 1000, 257), (515, 2049, 400), (600, 1500, 1000)])
 def test_sketch_product_parity(nys, m, n, ell):
     """Y = A diag(d) A^T Omega in FP64 and on BF16 matrix cores, with the
     operands as A alone, with a transposed copy, and as sketch tiles (made

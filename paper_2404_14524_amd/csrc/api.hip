@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <vector>
 #include <cstring>
 #include <mutex>
 
@@ -415,7 +416,7 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
     NYS_CHECK(chol_upper(h, G, ell, 0.0, shift_rel, fail));
     NYS_CHECK(read_scalars(h, SC_FAIL, 1));
     if (h->hscal[SC_FAIL] != 0.0) return set_error(h, NYS_ENOTPD, "Cholesky-QR: Gram matrix not positive definite");
-    NYS_CHECK(tri_inv_upper(h, G, Cinv, ell));
+    NYS_CHECK(tri_inv_upper(h, G, Cinv, ell, jw));
     NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, X, NYS_F64, ell, Cinv, ell, Xout, ell, nullptr, true));
     if (Rout) NYS_CHECK(copy(h, Rout, G, l2));
     return NYS_OK;
@@ -447,21 +448,55 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
     nu *= 10.0;
   }
   if (!ok) return set_error(h, NYS_ENOTPD, "sketch: chol(Omega^T Y_nu) failed after 6 shift increases (nu=%g)", nu);
-  NYS_CHECK(tri_inv_upper(h, G, Cinv, ell));
+  NYS_CHECK(tri_inv_upper(h, G, Cinv, ell, jw));
   NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, B, NYS_F64, ell, Cinv, ell, Q1, ell, nullptr, true));
-  // thin QR of B (now in Q1) by shifted Cholesky-QR3:
-  // R1 = chol(B^T B + s I), s = 11 (m ell + ell(ell+1)) u ||B||_F^2; then two plain passes.
+  // thin QR of B (now in Q1).  B B^T is the Nystrom approximation of N + nu I,
+  // so the singular values of B lie in [sqrt(nu), sqrt(lambda_max + nu)]:
+  // with the BF16 shift B is well conditioned, with the FP64 one it need not be.
+  // First an unshifted Cholesky-QR pass; if it succeeds and the spread of the
+  // factor's diagonal (a lower bound on cond(B)) is at most 1 / sqrt(10 s),
+  // s = 11 (m ell + ell(ell+1)) u, one more plain pass leaves Q^T Q - I at
+  // rounding level (Cholesky-QR2).  Otherwise shifted Cholesky-QR3 from B:
+  // R1 = chol(B^T B + s ||B||_F^2 I), then two plain passes.
   const double u = 1.1102230246251565e-16;
   const double srel = 11.0 * ((double)m * ell + (double)ell * (ell + 1)) * u;
-  NYS_CHECK(cholqr_pass(Q1, B, srel, R1));
-  NYS_CHECK(cholqr_pass(B, Q1, 0.0, R2));
-  NYS_CHECK(small_mm(h, R2, R1, T, ell));           // T = R2 R1
-  NYS_CHECK(cholqr_pass(Q1, B, 0.0, R1));           // Q in B, R3 in R1
-  NYS_CHECK(small_mm(h, R1, T, R2, ell));           // R = R3 R2 R1 in R2
+  double* Qf = B;                                   // Q and R of B
+  double* Rf = R2;
+  bool two_pass = false;
+  NYS_CHECK(gemm_f64(h, true, false, ell, ell, m, Q1, NYS_F64, ell, Q1, ell, G, ell, nullptr));
+  NYS_CHECK(chol_upper(h, G, ell, 0.0, 0.0, fail));
+  NYS_CHECK(read_scalars(h, SC_FAIL, 1));
+  if (h->hscal[SC_FAIL] == 0.0) {
+    std::vector<double> dg((size_t)ell);
+    NYS_HIP(h, hipMemcpy2DAsync(dg.data(), sizeof(double), G, (size_t)(ell + 1) * sizeof(double), sizeof(double),
+                                (size_t)ell, hipMemcpyDeviceToHost, h->stream));
+    NYS_HIP(h, hipStreamSynchronize(h->stream));
+    double dmin = INFINITY, dmax = 0.0;
+    for (double v : dg) {
+      dmin = std::min(dmin, std::fabs(v));
+      dmax = std::max(dmax, std::fabs(v));
+    }
+    two_pass = dmin > 0.0 && std::isfinite(dmax) && dmax <= dmin / std::sqrt(10.0 * srel);
+  }
+  if (two_pass) {
+    NYS_CHECK(tri_inv_upper(h, G, Cinv, ell, jw));
+    NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, Q1, NYS_F64, ell, Cinv, ell, B, ell, nullptr, true));
+    NYS_CHECK(copy(h, R1, G, l2));
+    NYS_CHECK(cholqr_pass(B, Q1, 0.0, R2));
+    NYS_CHECK(small_mm(h, R2, R1, T, ell));         // R = R2 R1 in T, Q in Q1
+    Qf = Q1;
+    Rf = T;
+  } else {
+    NYS_CHECK(cholqr_pass(Q1, B, srel, R1));
+    NYS_CHECK(cholqr_pass(B, Q1, 0.0, R2));
+    NYS_CHECK(small_mm(h, R2, R1, T, ell));         // T = R2 R1
+    NYS_CHECK(cholqr_pass(Q1, B, 0.0, R1));         // Q in B, R3 in R1
+    NYS_CHECK(small_mm(h, R1, T, R2, ell));         // R = R3 R2 R1 in R2
+  }
   // SVD of the triangular factor: left singular vectors U_R, Sigma^2
-  NYS_CHECK(jacobi_svd(h, R2, ell, sig2, jw));
+  NYS_CHECK(jacobi_svd(h, Rf, ell, sig2, jw));
   // U_hat = Q U_R ; Lambda_hat = max(0, Sigma^2 - nu)
-  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, B, NYS_F64, ell, R2, ell, outp->U, ell, nullptr));
+  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, Qf, NYS_F64, ell, Rf, ell, outp->U, ell, nullptr));
   NYS_CHECK(map_reduce<0, 0>(h, ell, LamF{sig2, outp->lam, nu}, nullptr));
   outp->nu = nu;
   return NYS_OK;

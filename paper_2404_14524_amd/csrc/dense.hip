@@ -447,6 +447,35 @@ __global__ __launch_bounds__(TRI_WAVES * NYS_WAVE) void k_tri_inv_cols(const dou
   }
 }
 
+// Inverse of the nb x nb diagonal blocks of an upper-triangular C (nb <= 64):
+// block (b, g) of the grid takes columns 4 g .. 4 g + 3 of diagonal block b,
+// one wave per column, by the back substitution of k_tri_inv_cols with one
+// element per lane.  X (zeroed beforehand) receives the blocks in place.
+__global__ __launch_bounds__(TRI_WAVES * NYS_WAVE) void k_tri_inv_diag(const double* C, double* X, int ell, int nb) {
+  const int lane = threadIdx.x % NYS_WAVE;
+  const int b = blockIdx.x;
+  const int jl = blockIdx.y * TRI_WAVES + threadIdx.x / NYS_WAVE;
+  const int o = b * nb;
+  const int sb = min(nb, ell - o);
+  if (jl >= sb) return;
+  const int64_t ld = ell;
+  double x = lane == jl ? 1.0 / C[(int64_t)(o + jl) * ld + o + jl] : 0.0;
+  for (int i = jl - 1; i >= 0; --i) {
+    const double cik = (lane > i && lane <= jl) ? C[(int64_t)(o + i) * ld + o + lane] : 0.0;
+    const double sum = wave_sum_dpp(cik * x);
+    if (lane == i) x = -sum / C[(int64_t)(o + i) * ld + o + i];
+  }
+  if (lane < sb) X[(int64_t)(o + lane) * ld + o + jl] = x;
+}
+
+__global__ __launch_bounds__(NYS_BLOCK) void k_scale_block(double* X, int64_t ld, int rows, int cols, double alpha) {
+  const int64_t total = (int64_t)rows * cols;
+  for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total; idx += (int64_t)gridDim.x * NYS_BLOCK) {
+    const int64_t r = idx / cols, c = idx % cols;
+    X[r * ld + c] *= alpha;
+  }
+}
+
 // ---------------------------------------------------------------- Cholesky across workgroups
 // G = C^T C, C upper, for larger ell: right-looking by panels of CP rows.  Per
 // panel: the CP x CP diagonal block is factored by one block in LDS, the row
@@ -686,6 +715,48 @@ __device__ __forceinline__ bool jacobi_pair_regs(double* xp, double* xq, int ell
   return true;
 }
 
+// Rotation of a column pair whose first column stays in registers across
+// rounds (u: pairs of doubles, lane l holding elements 2 i, 2 i + 1 for
+// i = l, l + 64, ...; even ell <= 128 C2); the second is read from LDS and
+// written back when the pair rotates.  Same arithmetic as jacobi_pair.
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+template <int C2>
+__device__ __forceinline__ bool jacobi_pair_held(f64x2 (&u)[C2], double* xq, int ell, double tol, int lane) {
+  const int half = ell / 2;
+  f64x2 v[C2];
+#pragma unroll
+  for (int t = 0; t < C2; ++t) {
+    const int i = lane + t * NYS_WAVE;
+    v[t] = i < half ? ((const f64x2*)xq)[i] : f64x2{0.0, 0.0};
+  }
+  double al = 0.0, be = 0.0, ga = 0.0;
+#pragma unroll
+  for (int t = 0; t < C2; ++t) {
+    al = fma(u[t][0], u[t][0], al);
+    be = fma(v[t][0], v[t][0], be);
+    ga = fma(u[t][0], v[t][0], ga);
+    al = fma(u[t][1], u[t][1], al);
+    be = fma(v[t][1], v[t][1], be);
+    ga = fma(u[t][1], v[t][1], ga);
+  }
+  al = wave_sum_dpp(al);
+  be = wave_sum_dpp(be);
+  ga = wave_sum_dpp(ga);
+  if (!(fabs(ga) > tol * sqrt(al * be))) return false;
+  const double zeta = (be - al) / (2.0 * ga);
+  const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+  const double c = 1.0 / sqrt(1.0 + t * t);
+  const double s = c * t;
+#pragma unroll
+  for (int k = 0; k < C2; ++k) {
+    const f64x2 uu = u[k], vv = v[k];
+    u[k] = f64x2{c * uu[0] - s * vv[0], c * uu[1] - s * vv[1]};
+    const int i = lane + k * NYS_WAVE;
+    if (i < half) ((f64x2*)xq)[i] = f64x2{s * uu[0] + c * vv[0], s * uu[1] + c * vv[1]};
+  }
+  return true;
+}
+
 // Block variant: the columns form groups of JG (the last ones padded), and a
 // launch is one round of the round-robin over groups; each block takes one
 // group pair and keeps its 2*JG columns in LDS.  FULL (the first round of a
@@ -698,9 +769,8 @@ __device__ __forceinline__ bool jacobi_pair_regs(double* xp, double* xq, int ell
 // elements per thread at a time; CH > 0 holds a pair in registers while it
 // is rotated (ell <= 64 CH).
 template <int JG, int CH, bool FULL>
-__global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc, int ell, int ngp, int round,
-                                                                      double tol, unsigned* rotations) {
-  extern __shared__ double cols[];       // 2*JG columns of length ell
+__device__ __forceinline__ void jacobi_block_body(double* Xc, int ell, int ngp, int round, double tol,
+                                                  unsigned* rotations, double* cols) {
   constexpr int NT = JG * NYS_WAVE, U = 8;
   const int ga = rr_player(blockIdx.x, round, ngp);
   const int gb = rr_player(ngp - 1 - blockIdx.x, round, ngp);
@@ -758,6 +828,30 @@ __global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc
       rotate(min(a, b), max(a, b));
       __syncthreads();
     }
+  } else if (CH > 0 && (ell & 1) == 0) {
+    // column wid of the first group stays with wave wid for all JG rounds
+    constexpr int C2 = CH > 0 ? (CH + 1) / 2 : 1;
+    const int half = ell / 2;
+    const bool live = gcol(wid) < ell;
+    f64x2 u[C2];
+    const f64x2* up = (const f64x2*)(cols + (int64_t)wid * ell);
+#pragma unroll
+    for (int t = 0; t < C2; ++t) {
+      const int i = lane + t * NYS_WAVE;
+      u[t] = i < half ? up[i] : f64x2{0.0, 0.0};
+    }
+    for (int r = 0; r < JG; ++r) {
+      const int q = JG + (wid + r) % JG;
+      if (live && gcol(q) < ell && jacobi_pair_held<C2>(u, cols + (int64_t)q * ell, ell, tol, lane)) ++nrot;
+      __syncthreads();
+    }
+    f64x2* upw = (f64x2*)(cols + (int64_t)wid * ell);
+#pragma unroll
+    for (int t = 0; t < C2; ++t) {
+      const int i = lane + t * NYS_WAVE;
+      if (i < half) upw[i] = u[t];
+    }
+    __syncthreads();
   } else {
     for (int r = 0; r < JG; ++r) {
       rotate(wid, JG + (wid + r) % JG);
@@ -766,7 +860,6 @@ __global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc
   }
   if ((ell & 1) == 0) {
     // pairs of doubles: 16-byte stores
-    typedef double f64x2 __attribute__((ext_vector_type(2)));
     const int half = ell / 2;
     for (int c = wid; c < 2 * JG; c += JG) {
       const int g = gcol(c);
@@ -789,6 +882,13 @@ __global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc
     }
   }
   if (lane == 0 && nrot) atomicAdd(rotations, nrot);
+}
+
+template <int JG, int CH, bool FULL>
+__global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc, int ell, int ngp, int round,
+                                                                      double tol, unsigned* rotations) {
+  extern __shared__ double cols[];       // 2*JG columns of length ell
+  jacobi_block_body<JG, CH, FULL>(Xc, ell, ngp, round, tol, rotations, cols);
 }
 
 template <int JG, int CH>
@@ -1066,7 +1166,33 @@ int chol_upper(nys_handle h, double* G, int ell, double shift_abs, double shift_
   return NYS_OK;
 }
 
-int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell) {
+int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell, double* work) {
+  if (ell > 256 && work) {
+    // blocked: diagonal blocks of 64 in parallel, then pairs of inverted
+    // blocks of size s joined into blocks of 2 s for s = 64, 128, ...:
+    // [A B; 0 D]^-1 = [A^-1, -A^-1 (B D^-1); 0, D^-1]
+    constexpr int NBD = 64;
+    const int nblk = (ell + NBD - 1) / NBD;
+    NYS_CHECK(fill(h, Cinv, (int64_t)ell * ell, 0.0));
+    hipLaunchKernelGGL(k_tri_inv_diag, dim3((unsigned)nblk, (unsigned)(NBD / TRI_WAVES)), dim3(TRI_WAVES * NYS_WAVE), 0,
+                       h->stream, C, Cinv, ell, NBD);
+    NYS_LAUNCH_CHECK(h);
+    for (int sz = NBD; sz < ell; sz *= 2) {
+      for (int r0 = 0; r0 + sz < ell; r0 += 2 * sz) {
+        const int r1 = r0 + sz, r2 = std::min(r0 + 2 * sz, ell), n2 = r2 - r1;
+        // work (sz x n2, ld n2) = B D^-1, B = C[r0:r1, r1:r2], D^-1 = Cinv[r1:r2, r1:r2]
+        NYS_CHECK(gemm_f64(h, false, false, sz, n2, n2, C + (int64_t)r0 * ell + r1, NYS_F64, ell,
+                           Cinv + (int64_t)r1 * ell + r1, ell, work, n2, nullptr, true));
+        // Cinv[r0:r1, r1:r2] = -A^-1 work, A^-1 = Cinv[r0:r1, r0:r1]
+        NYS_CHECK(gemm_f64(h, false, false, sz, n2, sz, Cinv + (int64_t)r0 * ell + r0, NYS_F64, ell, work, n2,
+                           Cinv + (int64_t)r0 * ell + r1, ell, nullptr));
+        hipLaunchKernelGGL(k_scale_block, dim3(grid_for((int64_t)sz * n2)), dim3(NYS_BLOCK), 0, h->stream,
+                           Cinv + (int64_t)r0 * ell + r1, (int64_t)ell, sz, n2, -1.0);
+        NYS_LAUNCH_CHECK(h);
+      }
+    }
+    return NYS_OK;
+  }
   const dim3 g((unsigned)((ell + TRI_WAVES - 1) / TRI_WAVES)), b(TRI_WAVES * NYS_WAVE);
   if (ell <= 16 * NYS_WAVE) {
     hipLaunchKernelGGL(k_tri_inv_cols<16>, g, b, 0, h->stream, C, Cinv, ell);
@@ -1086,8 +1212,8 @@ int small_mm(nys_handle h, const double* C1, const double* C2, double* C3, int e
 }
 
 int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
-  // work: ell*ell doubles (column storage), one counter word, one spare word
-  // and ell doubles of column norms
+  // work: ell*ell doubles (column storage), a counter word, a spare word and
+  // ell doubles of column norms
   double* Xc = work;
   unsigned* rot = reinterpret_cast<unsigned*>(work + (int64_t)ell * ell);
   hipLaunchKernelGGL(k_transpose_sq, dim3(grid_for((int64_t)ell * ell)), dim3(DB), 0, h->stream, X, Xc, ell);

@@ -164,8 +164,10 @@ int gemm_f64(nys_handle h, bool transA, bool transB, int64_t M, int64_t N, int64
 // shift_abs + shift_rel * trace(G) on the diagonal); result C upper (lower
 // part zeroed).  Sets the device word *fail to 1.0 when a pivot is not positive.
 int chol_upper(nys_handle h, double* G, int ell, double shift_abs, double shift_rel, double* fail);
-// Cinv = C^{-1} for upper-triangular C (ell x ell).
-int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell);
+// Cinv = C^{-1} for upper-triangular C (ell x ell), zeros below the diagonal.
+// With work (ell * ell / 4 doubles) and ell > 256, by diagonal blocks joined
+// pairwise with matrix-core products; otherwise column by column.
+int tri_inv_upper(nys_handle h, const double* C, double* Cinv, int ell, double* work = nullptr);
 // C3 = C1 * C2 for ell x ell (upper triangular products allowed).
 int small_mm(nys_handle h, const double* C1, const double* C2, double* C3, int ell);
 // One-sided Jacobi SVD of X (ell x ell, row-major, overwritten): on return the

@@ -254,7 +254,7 @@ int pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta
   double *Y, *Wt, *G, *diag;
   NYS_CHECK(ws(h, WS_Y, (size_t)m * ell, &Y));
   NYS_CHECK(ws(h, WS_SK_W, (size_t)ell * std::max<int64_t>(n, 1), &Wt));
-  NYS_CHECK(ws(h, WS_SMALL, (size_t)ell * ell + 8, &G));
+  NYS_CHECK(ws(h, WS_SMALL, (size_t)ell * ell + (size_t)ell * ell / 4 + 16, &G));   // G, then the inverse's work
   NYS_CHECK(ws(h, WS_B, (size_t)m, &diag));
   // diag(N + delta I) = (A .* A) d + delta
   GemvN gd;
@@ -296,7 +296,7 @@ int pchol_build(nys_handle h, const nys_matrix* A, const double* d, double delta
   NYS_CHECK(read_scalars(h, SC_FAIL, 1));
   if (h->hscal[SC_FAIL] != 0.0)
     return set_error(h, NYS_ENOTPD, "partial Cholesky: the pivot block is not positive definite");
-  NYS_CHECK(tri_inv_upper(h, G, P->Cinv, ell));
+  NYS_CHECK(tri_inv_upper(h, G, P->Cinv, ell, G + (size_t)ell * ell + 8));
   NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, Y, NYS_F64, ell, P->Cinv, ell, P->L, ell, nullptr, true));
   hipLaunchKernelGGL(k_pchol_diags, dim3((unsigned)((m + 3) / 4)), dim3(NYS_BLOCK), 0, h->stream,
                      (const double*)P->L, m, ell, (const int*)P->pos, (const double*)diag, delta, P->diagS);

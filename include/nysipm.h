@@ -142,11 +142,12 @@ int nys_profile_enable(nys_handle h, int enable);
 int nys_profile_read(nys_handle h, int kernel_class, int64_t* launches, double* total_ms);
 
 /* Read-stream reference for roofline reports (not a step of the method):
-   reads `bytes` (a multiple of 16; data 16-byte aligned) once with the same
+   reads `bytes` (a multiple of 16; data 16-byte aligned) with the same
    16-byte non-temporal loads as the normal-equation passes, in their shape
-   (each block streams eight contiguous rows of 64 KB side by side), and
-   returns the device time of the read in *ms (the call synchronises).
-   NYS_EINVAL on a bad size or alignment. */
+   (each block streams a few rows side by side), once in each of four shapes
+   (rows of 40 or 80 KB, four or eight per block), and returns in *ms the
+   device time of the fastest read (the call synchronises).  NYS_EINVAL on a
+   bad size or alignment. */
 int nys_stream_read(nys_handle h, const void* data, int64_t bytes, double* ms);
 
 /* ---------------------------------------------------------------- operators */

@@ -36,6 +36,12 @@
 #ifndef NYS_N_RB
 #define NYS_N_RB 8
 #endif
+#ifndef NYS_GEMV_UNROLL
+#define NYS_GEMV_UNROLL 1
+#endif
+#ifndef NYS_N_SPACE
+#define NYS_N_SPACE 1
+#endif
 #ifndef NYS_TT_RB
 #define NYS_TT_RB 8
 #endif
@@ -187,8 +193,11 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
   constexpr int VEC = T::vec;
   __shared__ double smem[RB * (NYS_BLOCK / NYS_WAVE) + NYS_BLOCK / NYS_WAVE];
   if (a.skip && *a.skip != 0.0) return;
-  const int64_t i0 = (int64_t)blockIdx.x * RB;
-  int nr = (int)min((int64_t)RB, a.m - i0);
+  // rows i0, i0 + SP, ..., i0 + (RB - 1) SP: blocks of SP consecutive indices
+  // interleave their rows within groups of RB SP rows
+  constexpr int64_t SP = RB > 1 ? NYS_N_SPACE : 1;
+  const int64_t i0 = ((int64_t)blockIdx.x / SP) * RB * SP + (int64_t)blockIdx.x % SP;
+  int nr = i0 < a.m ? (int)min((int64_t)RB, (a.m - i0 + SP - 1) / SP) : 0;
   double acc[RB];
 #pragma unroll
   for (int r = 0; r < RB; ++r) acc[r] = 0.0;
@@ -197,14 +206,15 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
   if (VECLOAD) {
     const int64_t nv = a.n / VEC;   // full 16-byte pieces per row
     const char* base = a.A + i0 * a.row_bytes;
+#pragma unroll NYS_GEMV_UNROLL
     for (int64_t jv = threadIdx.x; jv < nv; jv += NYS_BLOCK) {
       const int64_t j = jv * VEC;
-      double wv[VEC];
-      ld_f64s<VEC>(a.w + j, wv);
       u32x4 u[RB];
 #pragma unroll
       for (int r = 0; r < RB; ++r)
-        if (r < nr) u[r] = ld_stream16(base + r * a.row_bytes + j * (int64_t)sizeof(raw));
+        if (r < nr) u[r] = ld_stream16(base + r * SP * a.row_bytes + j * (int64_t)sizeof(raw));
+      double wv[VEC];
+      ld_f64s<VEC>(a.w + j, wv);
 #pragma unroll
       for (int r = 0; r < RB; ++r) {
         if (r < nr) {
@@ -222,7 +232,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
 #pragma unroll
     for (int r = 0; r < RB; ++r)
       if (r < nr) {
-        const double e = to_f64(((const raw*)(a.A + (i0 + r) * a.row_bytes))[j]);
+        const double e = to_f64(((const raw*)(a.A + (i0 + r * SP) * a.row_bytes))[j]);
         acc[r] = fma(SQ ? e * e : e, wj, acc[r]);
       }
   }
@@ -232,7 +242,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_n(T2Args a) {
 #pragma unroll
     for (int r = 0; r < RB; ++r) {
       if (r < nr) {
-        const int64_t i = i0 + r;
+        const int64_t i = i0 + r * SP;
         const double vi = a.v ? a.v[i] : 0.0;
         const double o = a.sA * acc[r] + a.sV * vi + (a.x0 ? a.x0[i] : 0.0) + a.shift;
         a.out[i] = o;
@@ -275,6 +285,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_gemv_tt(TTArgs a) {
   if (VECLOAD) {
     const int64_t nv = a.cols / VEC;
     const char* base = a.At + j0 * a.row_bytes;
+#pragma unroll NYS_GEMV_UNROLL
     for (int64_t iv = threadIdx.x; iv < nv; iv += NYS_BLOCK) {
       const int64_t i = iv * VEC;
       u32x4 u[RB];
@@ -368,7 +379,8 @@ void dispatch_t(dim3 g, T1Args& k, bool fused, bool vecload, hipStream_t st) {
 
 template <class T, int RB, bool SQ>
 void launch_n_rb(T2Args& k, bool vecload, hipStream_t st) {
-  dim3 g((unsigned)((k.m + RB - 1) / RB));
+  constexpr int64_t SP = RB > 1 ? NYS_N_SPACE : 1;
+  dim3 g((unsigned)((k.m + RB * SP - 1) / (RB * SP) * SP));
   if (vecload) hipLaunchKernelGGL((k_gemv_n<T, RB, true, SQ>), g, dim3(NYS_BLOCK), 0, st, k);
   else hipLaunchKernelGGL((k_gemv_n<T, RB, false, SQ>), g, dim3(NYS_BLOCK), 0, st, k);
 }
@@ -463,7 +475,8 @@ void t_chunks(const nys_matrix* A, int64_t* ncol_out, int64_t* nch_out, int64_t*
 
 int n_blocks_pass2(int64_t m) {
   const int rb = m >= 8 * 1536 ? NYS_N_RB : m >= 4 * 1024 ? 4 : m >= 2 * 1024 ? 2 : 1;
-  return (int)((m + rb - 1) / rb);
+  const int64_t sp = rb > 1 ? NYS_N_SPACE : 1;
+  return (int)((m + rb * sp - 1) / (rb * sp) * sp);
 }
 
 }  // namespace

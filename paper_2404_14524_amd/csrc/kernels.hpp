@@ -84,9 +84,11 @@ int normal_apply(nys_handle h, const nys_matrix* A, const double* d, double delt
                  const double* v, double* out, double* dot_out);
 
 // Read-stream reference (16-byte non-temporal loads over `bytes`, a multiple of
-// 16); launch stream_read_blocks(bytes) blocks; part receives nblocks * 4 words.
-int stream_read_blocks(int64_t bytes);
-int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int nblocks);
+// 16) in one of stream_read_shapes() shapes; launch stream_read_blocks(bytes,
+// shape) blocks; part receives nblocks * 4 words.
+int stream_read_shapes();
+int stream_read_blocks(int64_t bytes, int shape);
+int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int shape);
 
 // ---------------------------------------------------------------- vectors
 int fill(nys_handle h, double* x, int64_t n, double value);

@@ -62,27 +62,28 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_nonfinite(const char* A, int64_t 
   if (threadIdx.x == 0) part[blockIdx.x] = c[0];
 }
 
-// Read-stream reference: the buffer read once, in the shape of the GEMV
-// passes that stream A: each block takes eight consecutive rows of 64 KB
-// (512 KB) and every thread keeps one 16-byte non-temporal load per row in
-// flight, a wave covering 1 KB of a row per load; the words are XOR-folded so
-// the reads cannot be elided.  A tail shorter than a block is read by the
-// last block piece by piece.
-constexpr int64_t SR_ROW = 64 * 1024;          // bytes per row
-constexpr int SR_RB = 8;                        // rows per block
+// Read-stream reference: the buffer read once with the 16-byte non-temporal
+// loads of the GEMV passes, in their shape: each block streams RB rows of
+// ROWB bytes side by side, every thread keeping one load per row in flight (a
+// wave covers 1 KB of a row per load); the words are XOR-folded so that the
+// reads cannot be elided.  A tail shorter than a block is read by the last
+// block piece by piece.  The spacing of a block's rows matters on HBM3E
+// (rows 80 KB apart stream faster than 64 or 100 KB apart), so the reference
+// is the fastest of a few shapes (SR_SHAPES).
+template <int64_t ROWB, int RB>
 __global__ __launch_bounds__(NYS_BLOCK) void k_stream_read(const char* p, int64_t n16, unsigned* part) {
-  constexpr int64_t ROW16 = SR_ROW / 16;
-  const int64_t r0 = (int64_t)blockIdx.x * SR_RB;
+  constexpr int64_t ROW16 = ROWB / 16;
+  const int64_t r0 = (int64_t)blockIdx.x * RB;
   const int64_t nrows = n16 / ROW16;
   unsigned acc = 0u;
-  if (r0 + SR_RB <= nrows) {
-    const char* base = p + r0 * SR_ROW;
+  if (r0 + RB <= nrows) {
+    const char* base = p + r0 * ROWB;
     for (int64_t c = threadIdx.x; c < ROW16; c += NYS_BLOCK) {
-      u32x4 u[SR_RB];
+      u32x4 u[RB];
 #pragma unroll
-      for (int r = 0; r < SR_RB; ++r) u[r] = ld_stream16(base + r * SR_ROW + 16 * c);
+      for (int r = 0; r < RB; ++r) u[r] = ld_stream16(base + r * ROWB + 16 * c);
 #pragma unroll
-      for (int r = 0; r < SR_RB; ++r) acc ^= u[r].x ^ u[r].y ^ u[r].z ^ u[r].w;
+      for (int r = 0; r < RB; ++r) acc ^= u[r].x ^ u[r].y ^ u[r].z ^ u[r].w;
     }
   } else {
     for (int64_t i = r0 * ROW16 + threadIdx.x; i < n16; i += NYS_BLOCK) {
@@ -94,6 +95,13 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_stream_read(const char* p, int64_
   for (int off = 32; off > 0; off >>= 1) acc ^= __shfl_xor(acc, off, NYS_WAVE);
   if ((threadIdx.x & (NYS_WAVE - 1)) == 0) part[blockIdx.x * (NYS_BLOCK / NYS_WAVE) + threadIdx.x / NYS_WAVE] = acc;
 }
+
+struct SrShape {
+  int64_t row_bytes;
+  int rb;
+};
+constexpr SrShape SR_SHAPES[] = {{80 * 1024, 8}, {40 * 1024, 8}, {80 * 1024, 4}, {40 * 1024, 4}};
+constexpr int SR_NSHAPES = sizeof(SR_SHAPES) / sizeof(SR_SHAPES[0]);
 
 // ---------------------------------------------------------------- PCG / P^{-1}
 // Every reduction below is two launches: per-block partials, then a one-block
@@ -326,15 +334,24 @@ size_t update_part_doubles(int64_t m, int ell, bool precond) {
 
 size_t expand_part_doubles(int64_t m) { return expand_blocks(m); }
 
-int stream_read_blocks(int64_t bytes) {
-  // full blocks of SR_RB rows, plus one block for the tail
-  const int64_t rows = bytes / SR_ROW;
-  return (int)(rows / SR_RB + 1);
+int stream_read_shapes() { return SR_NSHAPES; }
+
+int stream_read_blocks(int64_t bytes, int shape) {
+  // full blocks of rb rows, plus one block for the tail
+  const SrShape sh = SR_SHAPES[shape];
+  return (int)(bytes / sh.row_bytes / sh.rb + 1);
 }
 
-int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int nblocks) {
-  hipLaunchKernelGGL(k_stream_read, dim3((unsigned)nblocks), dim3(NYS_BLOCK), 0, h->stream,
-                     (const char*)data, bytes / 16, part);
+int stream_read(nys_handle h, const void* data, int64_t bytes, unsigned* part, int shape) {
+  const int nb = stream_read_blocks(bytes, shape);
+  const char* p = (const char*)data;
+  const int64_t n16 = bytes / 16;
+  switch (shape) {
+    case 0: hipLaunchKernelGGL((k_stream_read<80 * 1024, 8>), dim3((unsigned)nb), dim3(NYS_BLOCK), 0, h->stream, p, n16, part); break;
+    case 1: hipLaunchKernelGGL((k_stream_read<40 * 1024, 8>), dim3((unsigned)nb), dim3(NYS_BLOCK), 0, h->stream, p, n16, part); break;
+    case 2: hipLaunchKernelGGL((k_stream_read<80 * 1024, 4>), dim3((unsigned)nb), dim3(NYS_BLOCK), 0, h->stream, p, n16, part); break;
+    default: hipLaunchKernelGGL((k_stream_read<40 * 1024, 4>), dim3((unsigned)nb), dim3(NYS_BLOCK), 0, h->stream, p, n16, part); break;
+  }
   NYS_LAUNCH_CHECK(h);
   return NYS_OK;
 }

@@ -183,10 +183,10 @@ def test_shapes_beyond_the_limits_are_rejected_before_any_work(nys):
 
 def test_read_stream_reference_sizes(nys):
     """The read-stream reference takes any 16-byte multiple: less than one
-    64 KB row, whole blocks of eight rows, and blocks plus a ragged tail; it
-    refuses misaligned data and sizes."""
-    buf = torch.ones(((8 * 65536 * 3 + 65536 + 48) // 4,), dtype=torch.float32, device=DEV)
-    for nbytes in (16, 65536 - 16, 8 * 65536, 8 * 65536 * 3 + 65536 + 48, buf.numel() * 4):
+    row of its smallest shape (40 KB), whole blocks of eight 80 KB rows, and
+    blocks plus a ragged tail; it refuses misaligned data and sizes."""
+    buf = torch.ones(((8 * 81920 * 3 + 40960 + 48) // 4,), dtype=torch.float32, device=DEV)
+    for nbytes in (16, 40960 - 16, 8 * 81920, 4 * 40960 * 5 + 48, buf.numel() * 4):
         print(f"stream_read {nbytes} B", flush=True)
         ms = nys.nys_stream_read(buf[: nbytes // 4])
         assert ms > 0.0

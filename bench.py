@@ -45,6 +45,7 @@ import argparse
 import hashlib
 import json
 import os
+import subprocess
 import sys
 import time
 
@@ -294,11 +295,18 @@ class OracleChild:
     def collect(self, gpu_iters: int, wait_s: float):
         """The child's results, waiting at most wait_s for it; the child is
         ended (its own process only) if it is still running then."""
-        try:
-            self.proc.wait(timeout=max(wait_s, 0.0))
-        except Exception:
-            self.proc.kill()
-            self.proc.wait()
+        deadline = time.perf_counter() + max(wait_s, 0.0)
+        while True:
+            left = deadline - time.perf_counter()
+            try:
+                self.proc.wait(timeout=max(0.0, min(60.0, left)))
+                break
+            except subprocess.TimeoutExpired:
+                if time.perf_counter() >= deadline:
+                    self.proc.kill()
+                    self.proc.wait()
+                    break
+                log("waiting for the oracle child")
         self.log.close()
         path = os.path.join(self.dir, "result.json")
         res = json.load(open(path)) if os.path.exists(path) else {}
@@ -723,6 +731,9 @@ def main():
     t0 = time.perf_counter()
     for s in range(args.steps):
         x, y, z, info = nys.ipm_solve(A, inst.b, inst.c, inst.q, **mixed)
+        # a progress line per solve (ipm_solve has read its device scalars, so
+        # the solve has finished; the print costs microseconds of the ~14 s)
+        log(f"step {s}: iters={info.iters} pcg={info.pcg_iters_total}")
     torch.cuda.synchronize()
     t_total = time.perf_counter() - t0
     prof = nys.nys_profile_read()

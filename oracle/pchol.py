@@ -9,7 +9,7 @@ replaced by its diagonal, diag(S)_i = (N_delta)_ii - ||L21[i, :]||^2.
 
 Readings of the paper used here:
 * Pivots: the ell largest diagonal entries of N_delta, chosen once from the
-  diagonal (the leading block "contains the ell largest diagonal elements");
+  diagonal (the paper's leading block holds the largest diagonal entries);
   ties go to the smaller index.  Only the set matters: any order of the
   pivots inside the leading block gives the same P_Chol.
 * The paper's experiments form the diagonal with entrywise access to A,

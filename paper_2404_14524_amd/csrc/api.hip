@@ -411,13 +411,15 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
   if (omega) NYS_CHECK(copy(h, Om, omega, m * ell));
   else NYS_CHECK(philox_gaussian(h, m, ell, seed, counter, Om));
   const bool one_pass = !omega && m >= 4 * (int64_t)ell;
+  // One Cholesky-QR pass on X (m x ell): R = chol(X^T X + shift) in G (and
+  // Rout), R^{-1} in Cinv; with Xout, Xout = X R^{-1}.
   auto cholqr_pass = [&](double* X, double* Xout, double shift_rel, double* Rout) -> int {
     NYS_CHECK(gemm_f64(h, true, false, ell, ell, m, X, NYS_F64, ell, X, ell, G, ell, nullptr));
     NYS_CHECK(chol_upper(h, G, ell, 0.0, shift_rel, fail));
     NYS_CHECK(read_scalars(h, SC_FAIL, 1));
     if (h->hscal[SC_FAIL] != 0.0) return set_error(h, NYS_ENOTPD, "Cholesky-QR: Gram matrix not positive definite");
     NYS_CHECK(tri_inv_upper(h, G, Cinv, ell, jw));
-    NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, X, NYS_F64, ell, Cinv, ell, Xout, ell, nullptr, true));
+    if (Xout) NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, X, NYS_F64, ell, Cinv, ell, Xout, ell, nullptr, true));
     if (Rout) NYS_CHECK(copy(h, Rout, G, l2));
     return NYS_OK;
   };
@@ -460,7 +462,10 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
   // R1 = chol(B^T B + s ||B||_F^2 I), then two plain passes.
   const double u = 1.1102230246251565e-16;
   const double srel = 11.0 * ((double)m * ell + (double)ell * (ell + 1)) * u;
-  double* Qf = B;                                   // Q and R of B
+  // The last pass forms no Q: with Q = P R_last^{-1} (P the previous pass's
+  // output, R_last^{-1} in Cinv), U_hat = Q U_R = P (R_last^{-1} U_R), one
+  // ell x ell x ell product in place of an m x ell x ell one.
+  double* P = B;
   double* Rf = R2;
   bool two_pass = false;
   NYS_CHECK(gemm_f64(h, true, false, ell, ell, m, Q1, NYS_F64, ell, Q1, ell, G, ell, nullptr));
@@ -482,21 +487,23 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
     NYS_CHECK(tri_inv_upper(h, G, Cinv, ell, jw));
     NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, Q1, NYS_F64, ell, Cinv, ell, B, ell, nullptr, true));
     NYS_CHECK(copy(h, R1, G, l2));
-    NYS_CHECK(cholqr_pass(B, Q1, 0.0, R2));
-    NYS_CHECK(small_mm(h, R2, R1, T, ell));         // R = R2 R1 in T, Q in Q1
-    Qf = Q1;
+    NYS_CHECK(cholqr_pass(B, nullptr, 0.0, R2));
+    NYS_CHECK(small_mm(h, R2, R1, T, ell));         // R = R2 R1 in T, Q = B R2^{-1}
+    P = B;
     Rf = T;
   } else {
     NYS_CHECK(cholqr_pass(Q1, B, srel, R1));
     NYS_CHECK(cholqr_pass(B, Q1, 0.0, R2));
     NYS_CHECK(small_mm(h, R2, R1, T, ell));         // T = R2 R1
-    NYS_CHECK(cholqr_pass(Q1, B, 0.0, R1));         // Q in B, R3 in R1
+    NYS_CHECK(cholqr_pass(Q1, nullptr, 0.0, R1));   // R3 in R1, Q = Q1 R3^{-1}
     NYS_CHECK(small_mm(h, R1, T, R2, ell));         // R = R3 R2 R1 in R2
+    P = Q1;
   }
   // SVD of the triangular factor: left singular vectors U_R, Sigma^2
   NYS_CHECK(jacobi_svd(h, Rf, ell, sig2, jw));
-  // U_hat = Q U_R ; Lambda_hat = max(0, Sigma^2 - nu)
-  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, Qf, NYS_F64, ell, Rf, ell, outp->U, ell, nullptr));
+  // U_hat = Q U_R = P (R_last^{-1} U_R) ; Lambda_hat = max(0, Sigma^2 - nu)
+  NYS_CHECK(gemm_f64(h, false, false, ell, ell, ell, Cinv, NYS_F64, ell, Rf, ell, R1, ell, nullptr));
+  NYS_CHECK(gemm_f64(h, false, false, m, ell, ell, P, NYS_F64, ell, R1, ell, outp->U, ell, nullptr));
   NYS_CHECK(map_reduce<0, 0>(h, ell, LamF{sig2, outp->lam, nu}, nullptr));
   outp->nu = nu;
   return NYS_OK;

@@ -478,7 +478,7 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_scale_block(double* X, int64_t ld
 
 // ---------------------------------------------------------------- Cholesky across workgroups
 // G = C^T C, C upper, for larger ell: right-looking by panels of CP rows.  Per
-// panel: the CP x CP diagonal block is factored by one block in LDS, the row
+// panel: the CP x CP diagonal block is factored by one wave in registers, the row
 // panel C[k0:k0+nb, k0+nb:] = C_kk^{-T} G[k0:k0+nb, k0+nb:] is solved one
 // column per thread, and the trailing upper triangle is updated in 64 x 64
 // tiles by as many blocks as there are tiles.  Arithmetic per entry is the
@@ -508,47 +508,60 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_chol_shift(double* G, int ell, do
   if (threadIdx.x == 0) *fail = 0.0;
 }
 
-// factor the nb x nb diagonal block at k0 (nb <= CP) in LDS; *fail = 1 on a
-// pivot that is not positive and finite
-__global__ __launch_bounds__(NYS_BLOCK) void k_chol_diag(double* G, int ell, int k0, int nb, double* fail) {
-  __shared__ double P[CP * CP];
-  const int tid = threadIdx.x;
-  for (int idx = tid; idx < nb * nb; idx += NYS_BLOCK) {
-    const int r = idx / nb, c = idx % nb;
-    P[r * CP + c] = G[(int64_t)(k0 + r) * ell + k0 + c];
-  }
-  __syncthreads();
+// Broadcast of lane l's double (l wave-uniform) through two scalar reads.
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)b, l);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(b >> 32), l);
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+}
+
+// factor the nb x nb diagonal block at k0 (nb <= CP) by one wave, without
+// barriers: lane c < nb keeps column c of the block (rows 0..c) in registers,
+// and each pivot row reaches the other lanes by lane broadcasts.  *fail = 1 on
+// a pivot that is not positive and finite.
+__global__ __launch_bounds__(NYS_WAVE) void k_chol_diag(double* G, int ell, int k0, int nb, double* fail) {
+  const int c = threadIdx.x;
+  const bool col = c < nb;
+  double x[CP];
+#pragma unroll
+  for (int r = 0; r < CP; ++r) x[r] = (col && r <= c) ? G[(int64_t)(k0 + r) * ell + k0 + c] : 0.0;
   bool bad = false;
-  for (int kk = 0; kk < nb; ++kk) {
-    const double g = P[kk * CP + kk];
-    if (!(g > 0.0) || !isfinite(g)) {    // uniform: every thread read the same g
-      bad = true;
-      break;
+#pragma unroll
+  for (int k = 0; k < CP; ++k) {
+    if (k < nb && !bad) {                      // uniform
+      const double g = lane_bcast(x[k], k);
+      if (!(g > 0.0) || !isfinite(g)) {
+        bad = true;
+      } else {
+        const double piv = sqrt(g);
+        if (c == k) x[k] = piv;
+        else if (c > k) x[k] = x[k] / piv;
+        // rows r > k: C[r][c] -= C[k][r] C[k][c] for c >= r
+#pragma unroll
+        for (int r = k + 1; r < CP; ++r) {
+          if (r < nb) {
+            const double ckr = lane_bcast(x[k], r);
+            if (c >= r) x[r] = fma(-ckr, x[k], x[r]);
+          }
+        }
+      }
     }
-    const double piv = sqrt(g);
-    __syncthreads();
-    for (int c = kk + 1 + tid; c < nb; c += NYS_BLOCK) P[kk * CP + c] /= piv;
-    if (tid == 0) P[kk * CP + kk] = piv;
-    __syncthreads();
-    const int rows = nb - kk - 1;
-    for (int idx = tid; idx < rows * nb; idx += NYS_BLOCK) {
-      const int r = kk + 1 + idx / nb, c = idx % nb;
-      if (c >= r) P[r * CP + c] -= P[kk * CP + r] * P[kk * CP + c];
-    }
-    __syncthreads();
   }
   if (bad) {
-    if (tid == 0) *fail = 1.0;
+    if (c == 0) *fail = 1.0;
     return;
   }
-  for (int idx = tid; idx < nb * nb; idx += NYS_BLOCK) {
-    const int r = idx / nb, c = idx % nb;
-    G[(int64_t)(k0 + r) * ell + k0 + c] = c >= r ? P[r * CP + c] : 0.0;
+  if (col) {
+#pragma unroll
+    for (int r = 0; r < CP; ++r)
+      if (r < nb) G[(int64_t)(k0 + r) * ell + k0 + c] = r <= c ? x[r] : 0.0;
   }
 }
 
 // row panel: for every column c >= k0 + nb, x = C_kk^{-T} G[k0:k0+nb, c] by
-// forward substitution (C_kk^T is lower triangular), one column per thread
+// forward substitution (C_kk^T is lower triangular), one column per thread;
+// the column's nb entries are all read before the first is written back
 __global__ __launch_bounds__(NYS_BLOCK) void k_chol_row(double* G, int ell, int k0, int nb) {
   __shared__ double Ck[CP * CP];
   for (int idx = threadIdx.x; idx < nb * nb; idx += NYS_BLOCK) {
@@ -560,15 +573,19 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_chol_row(double* G, int ell, int 
   if (c >= ell) return;
   double x[CP];
 #pragma unroll
+  for (int r = 0; r < CP; ++r) x[r] = r < nb ? G[(int64_t)(k0 + r) * ell + c] : 0.0;
+#pragma unroll
   for (int r = 0; r < CP; ++r) {
     if (r < nb) {
-      double s = G[(int64_t)(k0 + r) * ell + c];
+      double s = x[r];
 #pragma unroll
       for (int q = 0; q < r; ++q) s -= Ck[q * CP + r] * x[q];
       x[r] = s / Ck[r * CP + r];
-      G[(int64_t)(k0 + r) * ell + c] = x[r];
     }
   }
+#pragma unroll
+  for (int r = 0; r < CP; ++r)
+    if (r < nb) G[(int64_t)(k0 + r) * ell + c] = x[r];
 }
 
 // trailing update: G[i][j] -= sum_q C[k0+q][i] C[k0+q][j] for t0 <= i <= j < ell,
@@ -767,13 +784,14 @@ __device__ __forceinline__ bool jacobi_pair_held(f64x2 (&u)[C2], double* xq, int
 // column pair meets at least once per sweep, so the convergence test (a sweep
 // without rotations) is unchanged.  Columns move between memory and LDS eight
 // elements per thread at a time; CH > 0 holds a pair in registers while it
-// is rotated (ell <= 64 CH).
+// is rotated (ell <= 64 CH).  A negative round pairs groups 2b and 2b + 1 in
+// block b (the pairs inside the 2*JG-column groups of the wide variant).
 template <int JG, int CH, bool FULL>
 __device__ __forceinline__ void jacobi_block_body(double* Xc, int ell, int ngp, int round, double tol,
                                                   unsigned* rotations, double* cols) {
   constexpr int NT = JG * NYS_WAVE, U = 8;
-  const int ga = rr_player(blockIdx.x, round, ngp);
-  const int gb = rr_player(ngp - 1 - blockIdx.x, round, ngp);
+  const int ga = round < 0 ? 2 * (int)blockIdx.x : rr_player(blockIdx.x, round, ngp);
+  const int gb = round < 0 ? ga + 1 : rr_player(ngp - 1 - blockIdx.x, round, ngp);
   auto gcol = [&](int c) { return c < JG ? ga * JG + c : gb * JG + (c - JG); };
   const int total = 2 * JG * ell;
   const int wid = threadIdx.x / NYS_WAVE, lane = threadIdx.x % NYS_WAVE;
@@ -891,6 +909,65 @@ __global__ __launch_bounds__(JG * NYS_WAVE) void k_jacobi_block_round(double* Xc
   jacobi_block_body<JG, CH, FULL>(Xc, ell, ngp, round, tol, rotations, cols);
 }
 
+// Wide variant (even ell): groups of G columns, twice the block variant's JG
+// at the same LDS size.  A launch is one round of the round-robin over these
+// groups; each block takes one group pair with G waves.  Wave w keeps column w
+// of the first group in registers for the whole launch (C2 pairs of doubles
+// per lane, ell <= 128 C2) and meets every column of the second group, which
+// sits in LDS, once: G rounds of G pairs, against JG rounds of JG pairs for
+// the same columns moved.  The pairs inside each group are left to a launch of
+// the block variant's FULL round with a negative round (one per sweep).
+template <int G, int C2>
+__global__ __launch_bounds__(G * NYS_WAVE) void k_jacobi_wide_round(double* Xc, int ell, int ngw, int round,
+                                                                    double tol, unsigned* rotations) {
+  extern __shared__ double cols[];       // G columns of length ell
+  const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / NYS_WAVE), lane = threadIdx.x % NYS_WAVE;
+  const int ga = rr_player(blockIdx.x, round, ngw);
+  const int gb = rr_player(ngw - 1 - blockIdx.x, round, ngw);
+  const int half = ell / 2, cu = ga * G + wid, cv = gb * G + wid;
+  // column wid of the second group straight into LDS (16 bytes per lane)
+  if (cv < ell) {
+    const int cb = ell * 8;
+    const char* src = (const char*)(Xc + (int64_t)cv * ell);
+    char* dst = (char*)(cols + (int64_t)wid * ell);
+    for (int off = 0; off < cb; off += 1024)
+      if (off + lane * 16 < cb)
+        __builtin_amdgcn_global_load_lds((const void*)(src + off + lane * 16),
+                                         (__attribute__((address_space(3))) void*)(dst + off), 16, 0, 0);
+  }
+  // column wid of the first group into registers
+  const bool live = cu < ell;
+  f64x2 u[C2];
+  const f64x2* up = (const f64x2*)(Xc + (int64_t)(live ? cu : 0) * ell);
+#pragma unroll
+  for (int t = 0; t < C2; ++t) {
+    const int i = lane + t * NYS_WAVE;
+    u[t] = live && i < half ? up[i] : f64x2{0.0, 0.0};
+  }
+  __builtin_amdgcn_s_waitcnt(0);
+  __syncthreads();
+  unsigned nrot = 0;
+  for (int r = 0; r < G; ++r) {
+    const int q = (wid + r) % G;
+    if (live && gb * G + q < ell && jacobi_pair_held<C2>(u, cols + (int64_t)q * ell, ell, tol, lane)) ++nrot;
+    __syncthreads();
+  }
+  if (live) {
+    f64x2* uw = (f64x2*)(Xc + (int64_t)cu * ell);
+#pragma unroll
+    for (int t = 0; t < C2; ++t) {
+      const int i = lane + t * NYS_WAVE;
+      if (i < half) uw[i] = u[t];
+    }
+  }
+  if (cv < ell) {
+    const f64x2* srcl = (const f64x2*)(cols + (int64_t)wid * ell);
+    f64x2* dstg = (f64x2*)(Xc + (int64_t)cv * ell);
+    for (int i = lane; i < half; i += NYS_WAVE) dstg[i] = srcl[i];
+  }
+  if (lane == 0 && nrot) atomicAdd(rotations, nrot);
+}
+
 template <int JG, int CH>
 void launch_jacobi_round(hipStream_t st, int ngp, size_t lds, double* Xc, int ell, int round, double tol, unsigned* rot) {
   if (round == 0)
@@ -903,6 +980,20 @@ hipError_t jacobi_lds_attr(size_t lds) {
   hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_block_round<JG, CH, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
   if (e != hipSuccess) return e;
   return hipFuncSetAttribute((const void*)k_jacobi_block_round<JG, CH, false>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+}
+// One sweep of the wide variant: the pairs inside each group of 2*JG columns,
+// then the ngw - 1 rounds across groups.
+template <int JG, int C2>
+void launch_jacobi_wide_sweep(hipStream_t st, int ngw, size_t lds, double* Xc, int ell, double tol, unsigned* rot) {
+  hipLaunchKernelGGL((k_jacobi_block_round<JG, 32, true>), dim3(ngw), dim3(JG * NYS_WAVE), lds, st, Xc, ell, 2 * ngw, -1, tol, rot);
+  for (int round = 0; round < ngw - 1; ++round)
+    hipLaunchKernelGGL((k_jacobi_wide_round<2 * JG, C2>), dim3(ngw / 2), dim3(2 * JG * NYS_WAVE), lds, st, Xc, ell, ngw, round, tol, rot);
+}
+template <int JG, int C2>
+hipError_t jacobi_wide_attr(size_t lds) {
+  hipError_t e = hipFuncSetAttribute((const void*)k_jacobi_block_round<JG, 32, true>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
+  if (e != hipSuccess) return e;
+  return hipFuncSetAttribute((const void*)k_jacobi_wide_round<2 * JG, C2>, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds);
 }
 
 __global__ __launch_bounds__(DB) void k_transpose_sq(const double* X, double* Y, int ell) {
@@ -1138,7 +1229,7 @@ int chol_upper(nys_handle h, double* G, int ell, double shift_abs, double shift_
     hipLaunchKernelGGL(k_chol_shift, dim3(1), dim3(NYS_BLOCK), 0, h->stream, G, ell, shift_abs, shift_rel, fail);
     for (int k0 = 0; k0 < ell; k0 += CP) {
       const int nb = std::min(CP, ell - k0);
-      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(NYS_BLOCK), 0, h->stream, G, ell, k0, nb, fail);
+      hipLaunchKernelGGL(k_chol_diag, dim3(1), dim3(NYS_WAVE), 0, h->stream, G, ell, k0, nb, fail);
       const int rest = ell - k0 - nb;
       if (rest > 0) {
         hipLaunchKernelGGL(k_chol_row, dim3((unsigned)((rest + NYS_BLOCK - 1) / NYS_BLOCK)), dim3(NYS_BLOCK), 0,
@@ -1264,12 +1355,26 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
     }
     if (e != hipSuccess) return set_error(h, NYS_EHIP, "Jacobi SVD: LDS attribute: %s", hipGetErrorString(e));
   }
+  // wide variant (groups of 2 * jg columns, one held in registers per wave)
+  // for even ell with jg in {8, 6, 4} and ell <= 2048; its register group of
+  // C2 = 10, 14, 16 pairs per lane covers ell up to 1280, 1792, 2048
+  const bool wide = regs && (ell & 1) == 0 && jg >= 4 && jg <= 8 && ell <= 2048;
+  const int ngwide = wide ? (ell + 2 * jg - 1) / (2 * jg) : 0;
+  const int ngw = ngwide + (ngwide & 1);
+  if (wide) {
+    hipError_t e = jg == 8 ? jacobi_wide_attr<8, 10>(lds) : jg == 6 ? jacobi_wide_attr<6, 14>(lds) : jacobi_wide_attr<4, 16>(lds);
+    if (e != hipSuccess) return set_error(h, NYS_EHIP, "Jacobi SVD: LDS attribute: %s", hipGetErrorString(e));
+  }
   int sweep = 0;
   const int max_sweeps = 40;
   if (np >= 2) {
     for (; sweep < max_sweeps; ++sweep) {
       NYS_CHECK(zero_u32(h, rot, 1));
-      if (jg) {
+      if (wide) {
+        if (jg == 8) launch_jacobi_wide_sweep<8, 10>(h->stream, ngw, lds, Xc, ell, tol, rot);
+        else if (jg == 6) launch_jacobi_wide_sweep<6, 14>(h->stream, ngw, lds, Xc, ell, tol, rot);
+        else launch_jacobi_wide_sweep<4, 16>(h->stream, ngw, lds, Xc, ell, tol, rot);
+      } else if (jg) {
         for (int round = 0; round < ngp - 1; ++round) dispatch(round);
       } else {
         for (int round = 0; round < np - 1; ++round) {

@@ -754,7 +754,10 @@ int sketch_gemm(nys_handle h, SkArgs a, bool tiled, bool want_w, float** part, i
   const SkShape sh = sk_shape(a.N);
   const int64_t tiles = (a.M + sh.bm() - 1) / sh.bm();
   if (tiles > 0x7FFFFFFFLL) return set_error(h, NYS_EINVAL, "BF16 sketch: %lld row tiles", (long long)tiles);
-  int nsplit = sk_splits(tiles * sh.groups, a.K);
+  // The W product writes BF16 W directly, without split-K, once its grid has
+  // a block for every compute unit: partial sums of n x ell in FP32 per split
+  // and their summation cost more than a last, partly filled round of blocks.
+  int nsplit = want_w && tiles * sh.groups >= 256 ? 1 : sk_splits(tiles * sh.groups, a.K);
   const bool direct = want_w && nsplit == 1;
   int64_t klen = (a.K + nsplit - 1) / nsplit;
   klen = (klen + SK_TK - 1) / SK_TK * SK_TK;

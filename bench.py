@@ -29,10 +29,12 @@ Modes:
   python bench.py --adaptive [--workload NAME]  # sketch size from the d_eff
                                     # estimate and preconditioner reuse against
                                     # the fixed size: one JSON line per variant
-  python bench.py --operator MxN [--ell L]      # the normal-equation operator and
-                                    # the BF16 sketch product alone on an m x n
-                                    # FP32 matrix (e.g. one column shard of a
-                                    # larger A): one JSON line of per-pass rates
+  python bench.py --operator MxN [--ell L] [--nystrom K]
+                                    # the normal-equation operator and the BF16
+                                    # sketch product alone on an m x n FP32
+                                    # matrix (e.g. one column shard of a larger
+                                    # A): one JSON line of per-pass rates; with
+                                    # K, also K whole Nystrom constructions
   python bench.py --kernel-loop R   # only R normal-equation applies (pass 1 on a
                                     # transposed copy, as in the solver), a plain
                                     # copy and read-stream kernels of known size
@@ -454,11 +456,13 @@ def compare(nys, inst, args):
         print(json.dumps(rec), flush=True)
 
 
-def operator_shape(nys, shape: str, ell: int, reps: int, seed: int):
+def operator_shape(nys, shape: str, ell: int, reps: int, seed: int, nystrom: int = 0):
     """The normal-equation operator (pass 1 on a transposed copy) and the BF16
     matrix-core sketch product (on sketch tiles), as in the solver, alone on a seeded Gaussian
     FP32 m x n matrix: launches and rates per kernel class from the library's
-    HIP events, against the read-stream reference over the same matrix."""
+    HIP events, against the read-stream reference over the same matrix.  With
+    nystrom > 0, also that many whole Nystrom constructions (Algorithm 1 with
+    the BF16 sketch on the same tiles, a fresh Omega each), timed end to end."""
     import torch
     m, n = (int(t) for t in shape.lower().split("x"))
     dev = "cuda"
@@ -501,6 +505,21 @@ def operator_shape(nys, shape: str, ell: int, reps: int, seed: int):
         nl, ms = prof[k]
         rec[k] = {"ell": ell, "launches": nl, "avg_ms": round(ms / nl, 3),
                   "TFLOPs": round(flops / (ms / nl * 1e-3) / 1e12, 1)}
+    if nystrom > 0:
+        times = []
+        for r in range(nystrom + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            P = nys.nys_sketch(A_lo, d, ell, seed=seed + r, sketch_dtype="bf16", tiles=tiles)
+            torch.cuda.synchronize()
+            t = time.perf_counter() - t0
+            del P
+            log(f"nystrom construction {r}: {t * 1e3:.1f} ms" + (" (warm-up)" if r == 0 else ""))
+            if r > 0:
+                times.append(t)
+        rec["nystrom_construction"] = {"ell": ell, "sketch": "bf16", "runs": nystrom,
+                                       "avg_ms": round(1e3 * sum(times) / len(times), 1),
+                                       "min_ms": round(1e3 * min(times), 1)}
     print(json.dumps(rec), flush=True)
 
 
@@ -617,6 +636,7 @@ def main():
     ap.add_argument("--kernel-loop", type=int, default=0)
     ap.add_argument("--operator", default="", metavar="MxN")
     ap.add_argument("--ell", type=int, default=400)
+    ap.add_argument("--nystrom", type=int, default=0)
     ap.add_argument("--reps", type=int, default=200)
     ap.add_argument("--compare", action="store_true")
     ap.add_argument("--adaptive", action="store_true")
@@ -672,7 +692,7 @@ def main():
     from instances import make_instance
 
     if args.operator:
-        operator_shape(nys, args.operator, args.ell, args.reps, args.seed)
+        operator_shape(nys, args.operator, args.ell, args.reps, args.seed, args.nystrom)
         return
 
     dev = "cuda"

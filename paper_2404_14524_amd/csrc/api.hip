@@ -126,6 +126,14 @@ struct LamF {
   double nu;
   __device__ void operator()(int64_t j, double*, double*) const { lam[j] = fmax(0.0, sig2[j] - nu); }
 };
+// out[j] = G[j][j] (the diagonal of an ell x ell row-major matrix, gathered
+// for one contiguous copy to the host)
+struct DiagF {
+  const double* G;
+  double* out;
+  int64_t ell;
+  __device__ void operator()(int64_t j, double*, double*) const { out[j] = G[j * (ell + 1)]; }
+};
 // Y_nu = Y + nu Omega
 struct ShiftF {
   double* out;
@@ -472,9 +480,11 @@ int sketch_run(nys_handle h, const nys_matrix* A, const double* d, int ell, uint
   NYS_CHECK(chol_upper(h, G, ell, 0.0, 0.0, fail));
   NYS_CHECK(read_scalars(h, SC_FAIL, 1));
   if (h->hscal[SC_FAIL] == 0.0) {
+    // the diagonal goes through the Jacobi work area and one contiguous copy
+    // (a strided 2D copy to the host read zeros under a kernel tracer)
     std::vector<double> dg((size_t)ell);
-    NYS_HIP(h, hipMemcpy2DAsync(dg.data(), sizeof(double), G, (size_t)(ell + 1) * sizeof(double), sizeof(double),
-                                (size_t)ell, hipMemcpyDeviceToHost, h->stream));
+    NYS_CHECK(map_reduce<0, 0>(h, ell, DiagF{G, jw, ell}, nullptr));
+    NYS_HIP(h, hipMemcpyAsync(dg.data(), jw, (size_t)ell * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     NYS_HIP(h, hipStreamSynchronize(h->stream));
     double dmin = INFINITY, dmax = 0.0;
     for (double v : dg) {

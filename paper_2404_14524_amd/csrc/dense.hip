@@ -542,7 +542,8 @@ __global__ __launch_bounds__(NYS_WAVE) void k_chol_diag(double* G, int ell, int 
         for (int r = k + 1; r < CP; ++r) {
           if (r < nb) {
             const double ckr = lane_bcast(x[k], r);
-            if (c >= r) x[r] = fma(-ckr, x[k], x[r]);
+            const double xr = fma(-ckr, x[k], x[r]);
+            x[r] = c >= r ? xr : x[r];              // a select, not a branch
           }
         }
       }
@@ -944,8 +945,9 @@ __global__ __launch_bounds__(G * NYS_WAVE) void k_jacobi_wide_round(double* Xc, 
     const int i = lane + t * NYS_WAVE;
     u[t] = live && i < half ? up[i] : f64x2{0.0, 0.0};
   }
+  // round 0 pairs each wave with the LDS column it loaded itself, so its own
+  // wait suffices; the barrier after each round orders the rest
   __builtin_amdgcn_s_waitcnt(0);
-  __syncthreads();
   unsigned nrot = 0;
   for (int r = 0; r < G; ++r) {
     const int q = (wid + r) % G;

@@ -141,6 +141,7 @@ struct SkArgs {
   int64_t Mp;                       // partial row pitch, a multiple of 4
   int64_t ntile;                    // row tiles; with ngroup > 1 the grid's x runs over
   int ngroup;                       // (row tile, column group) in XCD order
+  int64_t tile0;                    // first row tile of the grid (ngroup == 1)
 };
 
 #ifndef SK_DA_MAX
@@ -188,7 +189,7 @@ __global__ __launch_bounds__(SK_THREADS, 1) void k_sketch_mfma(SkArgs a) {
   // of row tile (x / (8 ng)) * 8 + x % 8: blocks are dispatched to the eight
   // XCDs in turn, so the groups of one row tile run back to back on one XCD
   // and its Aop stream comes from HBM once, the other groups reading it in L2
-  int64_t tile = blockIdx.x, group = blockIdx.y;
+  int64_t tile = a.tile0 + blockIdx.x, group = blockIdx.y;
   if (a.ngroup > 1) {
     const int64_t x = blockIdx.x, q = x >> 3;
     group = q % a.ngroup;
@@ -503,17 +504,17 @@ __global__ __launch_bounds__(NYS_BLOCK) void k_omega_t(const double* Om, int64_t
 }
 
 // W from the split-K partials: bf16(d[j] * sum_z part[z][c][j]) for c < N and
-// j < jlim, row-major (out[c * ldout + j], jlim = M) or in tiles of rpo rows
-// (jlim = the tiles' K, zero for j >= M)
+// j0 <= j < jlim, row-major (out[c * ldout + j], jlim = M) or in tiles of rpo
+// rows (jlim = the tiles' K, zero for j >= M)
 template <bool TILES>
 __global__ __launch_bounds__(NYS_BLOCK) void k_sketch_finish_w(const float* part, int nsplit, int64_t M,
-                                                               int64_t N, int64_t Mp, int64_t jlim,
+                                                               int64_t N, int64_t Mp, int64_t j0, int64_t jlim,
                                                                const double* d, uint16_t* out, int64_t ldout,
                                                                int64_t rpo) {
-  const int64_t total = N * jlim;
+  const int64_t rows = jlim - j0, total = N * rows;
   for (int64_t idx = (int64_t)blockIdx.x * NYS_BLOCK + threadIdx.x; idx < total;
        idx += (int64_t)gridDim.x * NYS_BLOCK) {
-    const int64_t c = idx / jlim, j = idx % jlim;
+    const int64_t c = idx / rows, j = j0 + idx % rows;
     uint16_t w = 0;
     if (j < M) {
       double s = 0.0;
@@ -749,15 +750,71 @@ void launch_sk_ctw(int ctw, const SkArgs& a, dim3 g, bool tiled, bool vec, int o
 // want_w and one split, C is written as BF16 W (SK_OUT_WT or
 // SK_OUT_WT_TILES per a.out...); otherwise split-K partials go to the
 // workspace and *part / *nsplit describe them (*part = NULL when W was
-// written directly).
-int sketch_gemm(nys_handle h, SkArgs a, bool tiled, bool want_w, float** part, int* nsplit_out) {
+// written directly), for rows from *row0 on (the rows before it were
+// written as W directly).
+int sketch_gemm(nys_handle h, SkArgs a, bool tiled, bool want_w, float** part, int* nsplit_out,
+                int64_t* row0 = nullptr) {
   const SkShape sh = sk_shape(a.N);
   const int64_t tiles = (a.M + sh.bm() - 1) / sh.bm();
   if (tiles > 0x7FFFFFFFLL) return set_error(h, NYS_EINVAL, "BF16 sketch: %lld row tiles", (long long)tiles);
+  if (row0) *row0 = 0;
   // The W product writes BF16 W directly, without split-K, once its grid has
   // a block for every compute unit: partial sums of n x ell in FP32 per split
   // and their summation cost more than a last, partly filled round of blocks.
-  int nsplit = want_w && tiles * sh.groups >= 256 ? 1 : sk_splits(tiles * sh.groups, a.K);
+  // When that last round (one block per compute unit, tiles % 256 of them)
+  // is under half full, it runs as a launch of its own, split over K so that
+  // it fills the units: the split s minimises its rounds times the stages
+  // per block, plus the partial sums' traffic counted in stages (one stage
+  // moves about (BM + BN) * 64 bytes into a unit, 256 units at a time).
+  // Measured: W at 50000 x 200000, ell = 400 (27 tiles in the last round)
+  // 8.8 ms against 9.8; at 20000 x 100000, ell = 200 (135 tiles) no change.
+  const int64_t ncu = 256;
+  if (want_w && sh.groups == 1 && tiles > ncu && tiles % ncu != 0 && tiles % ncu <= ncu / 2 && row0) {
+    const int64_t full = tiles - tiles % ncu, tail = tiles % ncu;
+    const int64_t kt = (a.K + SK_TK - 1) / SK_TK;
+    const double stage_bytes = (double)(sh.bm() + sh.bnp()) * SK_ROWB * ncu;
+    int best = 1;
+    double best_cost = 0.0;
+    for (int sp = 1; sp <= 16 && sp <= kt; ++sp) {
+      const int64_t rounds = (tail * sp + ncu - 1) / ncu, per = (kt + sp - 1) / sp;
+      const double traffic = sp > 1 ? 2.0 * sp * (double)(tail * sh.bm()) * (double)a.N * 4.0 / stage_bytes : 0.0;
+      const double cost = (double)(rounds * per) + traffic;
+      if (sp == 1 || cost < best_cost) {
+        best = sp;
+        best_cost = cost;
+      }
+    }
+    if (best > 1) {
+      SkArgs b = a;
+      b.ntile = full;
+      b.ngroup = 1;
+      b.tile0 = 0;
+      b.klen = kt * SK_TK;
+      b.Mp = (a.M + 3) / 4 * 4;
+      const bool vec = tiled || (((uintptr_t)a.A % 16 == 0) && (a.lda % 8 == 0));
+      const int out_w = tiled ? SK_OUT_WT_TILES : SK_OUT_WT;
+      dim3 g1((unsigned)full, 1u, 1u);
+      if (sh.wc == 1) launch_sk_ctw<1>(sh.ctw, b, g1, tiled, vec, out_w, h->stream);
+      else launch_sk_ctw<2>(sh.ctw, b, g1, tiled, vec, out_w, h->stream);
+      NYS_LAUNCH_CHECK(h);
+      int64_t klen = (a.K + best - 1) / best;
+      klen = (klen + SK_TK - 1) / SK_TK * SK_TK;
+      const int nsplit = (int)std::max<int64_t>(1, (a.K + klen - 1) / klen);
+      b.klen = klen;
+      b.tile0 = full;
+      b.ntile = tiles;
+      NYS_CHECK(ws_get(h, WS_SK_SPLIT, (size_t)nsplit * a.N * b.Mp * sizeof(float), (void**)&b.part));
+      dim3 g2((unsigned)tail, 1u, (unsigned)nsplit);
+      if (sh.wc == 1) launch_sk_ctw<1>(sh.ctw, b, g2, tiled, vec, SK_OUT_PART, h->stream);
+      else launch_sk_ctw<2>(sh.ctw, b, g2, tiled, vec, SK_OUT_PART, h->stream);
+      NYS_LAUNCH_CHECK(h);
+      *part = b.part;
+      *nsplit_out = nsplit;
+      *row0 = full * sh.bm();
+      return NYS_OK;
+    }
+  }
+  int nsplit = want_w && tiles * sh.groups >= ncu ? 1 : sk_splits(tiles * sh.groups, a.K);
   const bool direct = want_w && nsplit == 1;
   int64_t klen = (a.K + nsplit - 1) / nsplit;
   klen = (klen + SK_TK - 1) / SK_TK * SK_TK;
@@ -853,11 +910,12 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
       a.rpo = rpb;
       a.kout = kbn * SK_TK;
       a.d = d;
-      NYS_CHECK(sketch_gemm(h, a, true, true, &part, &nsplit));
+      int64_t row0 = 0;
+      NYS_CHECK(sketch_gemm(h, a, true, true, &part, &nsplit, &row0));
       if (part) {
-        hipLaunchKernelGGL((k_sketch_finish_w<true>), dim3(grid1d((int64_t)ell * kbn * SK_TK)), dim3(NYS_BLOCK), 0,
-                           h->stream, part, nsplit, n, (int64_t)ell, (n + 3) / 4 * 4, kbn * SK_TK, d, (uint16_t*)Wt,
-                           (int64_t)0, rpb);
+        hipLaunchKernelGGL((k_sketch_finish_w<true>), dim3(grid1d((int64_t)ell * (kbn * SK_TK - row0))),
+                           dim3(NYS_BLOCK), 0, h->stream, part, nsplit, n, (int64_t)ell, (n + 3) / 4 * 4, row0,
+                           kbn * SK_TK, d, (uint16_t*)Wt, (int64_t)0, rpb);
         NYS_LAUNCH_CHECK(h);
       }
       prof_end(h, ps);
@@ -906,10 +964,11 @@ int sketch_bf16(nys_handle h, const nys_matrix* A, const double* d, const double
       a.out = Wt;
       a.ldout = ldw;
       a.d = d;
-      NYS_CHECK(sketch_gemm(h, a, false, true, &part, &nsplit));
+      int64_t row0 = 0;
+      NYS_CHECK(sketch_gemm(h, a, false, true, &part, &nsplit, &row0));
       if (part) {
-        hipLaunchKernelGGL((k_sketch_finish_w<false>), dim3(grid1d(n * ell)), dim3(NYS_BLOCK), 0, h->stream, part,
-                           nsplit, n, (int64_t)ell, (n + 3) / 4 * 4, n, d, Wt, ldw, (int64_t)0);
+        hipLaunchKernelGGL((k_sketch_finish_w<false>), dim3(grid1d((n - row0) * ell)), dim3(NYS_BLOCK), 0, h->stream,
+                           part, nsplit, n, (int64_t)ell, (n + 3) / 4 * 4, row0, n, d, Wt, ldw, (int64_t)0);
         NYS_LAUNCH_CHECK(h);
       }
     } else {

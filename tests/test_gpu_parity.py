@@ -170,11 +170,15 @@ def test_sketch_fp64_parity(nys, m, n, ell):
 
 
 @pytest.mark.parametrize("m,n,ell", [(1, 9, 1), (130, 257, 7), (1000, 3000, 100), (2000, 8000, 50),
-                                     (777, 5001, 200), (300, 1000, 257), (515, 2049, 400), (600, 1500, 1000)])
+                                     (777, 5001, 200), (300, 1000, 257), (515, 2049, 400), (600, 1500, 1000),
+                                     (300, 70000, 16), (200, 40000, 300)])
 def test_sketch_product_parity(nys, m, n, ell):
     """Y = A diag(d) A^T Omega in FP64 and on BF16 matrix cores, with the
     operands as A alone, with a transposed copy, and as sketch tiles (made
-    from the BF16 copy and from the FP32 matrix: the same BF16 values)."""
+    from the BF16 copy and from the FP32 matrix: the same BF16 values).  The
+    last two shapes give the W product more row tiles than one round of
+    blocks with the last round under half full (274 of 256 rows, 313 of 128
+    rows): that round runs split over K."""
     print(f"sketch_product {m}x{n} ell={ell}", flush=True)
     rng = np.random.default_rng(m + n + ell)
     A = rng.standard_normal((m, n)) / np.sqrt(n)

@@ -143,12 +143,13 @@ def _nhat(U, lam):
 
 @pytest.mark.parametrize("m,n,ell", [(120, 300, 10), (700, 2000, 64), (1500, 4000, 100), (1200, 3000, 300),
                                      (1300, 3000, 1100), (1800, 3600, 1600), (2000, 4000, 1800),
-                                     (2200, 4400, 2100)])
+                                     (2200, 4400, 2100), (1100, 2500, 999), (1500, 3000, 1280)])
 def test_sketch_fp64_parity(nys, m, n, ell):
     """Algorithm 1 in FP64 against the oracle; the larger sizes take the
     multi-workgroup Cholesky (ell >= 128), the blocked triangular inverse, and
     the Jacobi SVD's wide groups of 16, 12 and 8 columns (ell = 1100, 1600,
-    1800; 2100 takes the block variant)."""
+    1800; 1280 fills the 160 KB of LDS exactly); 2100 and the odd 999 take
+    the block variant."""
     print(f"sketch {m}x{n} ell={ell}", flush=True)
     inst = make_instance("lowrank_5000x20000", seed=11, m=m, n=n, rank=max(ell // 2, 4))
     A = inst.A.double().numpy()

@@ -1328,9 +1328,12 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
   const int ngp = ng + (ng & 1);
   const size_t lds = (size_t)2 * jg * ell * sizeof(double);
   // pairs held in registers up to ell = 64 * CH (CH = 16 for the 16-wave
-  // groups, whose waves have 128 registers, else 32); beyond, rotated in LDS
+  // groups, whose waves have 128 registers, else 32); beyond, rotated in LDS.
+  // The 16-wave groups (ell <= 640) take CH = 4, 8 or 16 by ell, so that no
+  // wave runs its dot products and rotations over padding.
   const int chmax = jg == 16 ? 16 : 32;
   const bool regs = ell <= chmax * NYS_WAVE;
+  const int ch16 = ell <= 4 * NYS_WAVE ? 4 : ell <= 8 * NYS_WAVE ? 8 : 16;
   auto dispatch = [&](int round) {
 #define NYS_JAC(JGV, CHV)                                                                  \
   case JGV:                                                                                \
@@ -1338,7 +1341,11 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
     else launch_jacobi_round<JGV, 0>(h->stream, ngp, lds, Xc, ell, round, tol, rot);        \
     break;
     switch (jg) {
-      NYS_JAC(16, 16)
+      case 16:
+        if (ch16 == 4) launch_jacobi_round<16, 4>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else if (ch16 == 8) launch_jacobi_round<16, 8>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else launch_jacobi_round<16, 16>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        break;
       NYS_JAC(8, 32)
       NYS_JAC(6, 32)
       NYS_JAC(4, 32)
@@ -1349,7 +1356,7 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
   if (jg && lds > 65536) {
     hipError_t e = hipSuccess;
     switch (jg) {
-      case 16: e = regs ? jacobi_lds_attr<16, 16>(lds) : jacobi_lds_attr<16, 0>(lds); break;
+      case 16: e = ch16 == 8 ? jacobi_lds_attr<16, 8>(lds) : jacobi_lds_attr<16, 16>(lds); break;
       case 8: e = regs ? jacobi_lds_attr<8, 32>(lds) : jacobi_lds_attr<8, 0>(lds); break;
       case 6: e = regs ? jacobi_lds_attr<6, 32>(lds) : jacobi_lds_attr<6, 0>(lds); break;
       case 4: e = regs ? jacobi_lds_attr<4, 32>(lds) : jacobi_lds_attr<4, 0>(lds); break;
@@ -1359,12 +1366,18 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
   }
   // wide variant (groups of 2 * jg columns, one held in registers per wave)
   // for even ell with jg in {8, 6, 4} and ell <= 2048; its register group of
-  // C2 = 10, 14, 16 pairs per lane covers ell up to 1280, 1792, 2048
+  // C2 pairs per lane covers ell up to 128 C2: C2 = 8 or 10 with jg = 8
+  // (ell <= 1024, 1280), 12 or 14 with jg = 6 (1536, 1792), 16 with jg = 4
   const bool wide = regs && (ell & 1) == 0 && jg >= 4 && jg <= 8 && ell <= 2048;
   const int ngwide = wide ? (ell + 2 * jg - 1) / (2 * jg) : 0;
   const int ngw = ngwide + (ngwide & 1);
+  const int c2w = jg == 8 ? (ell <= 1024 ? 8 : 10) : jg == 6 ? (ell <= 1536 ? 12 : 14) : 16;
   if (wide) {
-    hipError_t e = jg == 8 ? jacobi_wide_attr<8, 10>(lds) : jg == 6 ? jacobi_wide_attr<6, 14>(lds) : jacobi_wide_attr<4, 16>(lds);
+    hipError_t e = c2w == 8    ? jacobi_wide_attr<8, 8>(lds)
+                   : c2w == 10 ? jacobi_wide_attr<8, 10>(lds)
+                   : c2w == 12 ? jacobi_wide_attr<6, 12>(lds)
+                   : c2w == 14 ? jacobi_wide_attr<6, 14>(lds)
+                               : jacobi_wide_attr<4, 16>(lds);
     if (e != hipSuccess) return set_error(h, NYS_EHIP, "Jacobi SVD: LDS attribute: %s", hipGetErrorString(e));
   }
   int sweep = 0;
@@ -1373,8 +1386,10 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
     for (; sweep < max_sweeps; ++sweep) {
       NYS_CHECK(zero_u32(h, rot, 1));
       if (wide) {
-        if (jg == 8) launch_jacobi_wide_sweep<8, 10>(h->stream, ngw, lds, Xc, ell, tol, rot);
-        else if (jg == 6) launch_jacobi_wide_sweep<6, 14>(h->stream, ngw, lds, Xc, ell, tol, rot);
+        if (c2w == 8) launch_jacobi_wide_sweep<8, 8>(h->stream, ngw, lds, Xc, ell, tol, rot);
+        else if (c2w == 10) launch_jacobi_wide_sweep<8, 10>(h->stream, ngw, lds, Xc, ell, tol, rot);
+        else if (c2w == 12) launch_jacobi_wide_sweep<6, 12>(h->stream, ngw, lds, Xc, ell, tol, rot);
+        else if (c2w == 14) launch_jacobi_wide_sweep<6, 14>(h->stream, ngw, lds, Xc, ell, tol, rot);
         else launch_jacobi_wide_sweep<4, 16>(h->stream, ngw, lds, Xc, ell, tol, rot);
       } else if (jg) {
         for (int round = 0; round < ngp - 1; ++round) dispatch(round);

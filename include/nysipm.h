@@ -438,7 +438,7 @@ typedef struct {
   double predictor_rtol;
   /* inner tolerance of the Newton solves: ||xi - M dy|| <= max(f mu,
      f tol (1 + ||b||)) (capped at pcg.rtol ||xi||, 1e-2 by default, and
-     floored at 1e-12 ||xi||), with f = inner_factor in (0, 1); else 0.5    */
+     floored at 1e-12 ||xi||), with f = inner_factor in (0, 1); else 0.9    */
   double inner_factor;
 } nys_ipm_opts;
 

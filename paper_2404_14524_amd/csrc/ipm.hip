@@ -11,7 +11,7 @@
 //   rho = delta = max(5e-10, min(rho, mu)).
 // * stopping test: max(||r_p||/(1+||b||), ||r_d||/(1+||c||), mu) <= tol.
 // * inner tolerance: ||xi - M dy|| <= max(1e-12 ||xi||, min(1e-2 ||xi||, tau)) with
-//   tau = f max(mu, tol (1 + ||b||)), f = 0.5 by default, judged on the true residual (the
+//   tau = f max(mu, tol (1 + ||b||)), f = 0.9 by default, judged on the true residual (the
 //   theory asks for a residual of order mu; the floor keeps solves from being
 //   asked for accuracy that the primal-feasibility target cannot use).
 // * a fresh test matrix per iteration (Philox key = seed, counter = k), shared
@@ -395,7 +395,7 @@ struct Opts {
   int trace_len = 0;
   bool separate_corrector = false;
   double predictor_rtol = 1e-3;
-  double inner_factor = 0.5;
+  double inner_factor = 0.9;
 };
 
 // Transposed copies only where the transpose kernel's grid (65535 tiles of 64
@@ -786,7 +786,7 @@ static int ipm_core(nys_handle h, const nys_qp* qp, const nys_ipm_opts* opts_in,
     NYS_CHECK(map_reduce<0, 0>(h, n, PredN{Rd, Rxz, rd, x, zeta, z, rho, vt, Rws, Ru, qp->u, w, s}, nullptr));
     NYS_CHECK(map_reduce<0, 0>(h, m, PredM{Rp, rp, y, lam, delta}, nullptr));
     // inner tolerance: max(1e-12 ||xi||, min(cap ||xi||, tau)), cap = pcg.rtol or 1e-2,
-    // tau = f max(mu, tol (1 + ||b||)), f = inner_factor (0.5): the normal-equation
+    // tau = f max(mu, tol (1 + ||b||)), f = inner_factor (0.9): the normal-equation
     // residual enters only the primal block of the Newton system (Proposition 3.1),
     // so no solve is asked for a residual below a fraction f of the
     // primal-feasibility target.

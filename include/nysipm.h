@@ -427,7 +427,7 @@ typedef struct {
      R_xz = -XZ + mu~ - dx_p dz_p, R_ws likewise), started from the
      predictor's dy and run to the inner tolerance.  With exact solves this
      equals the sum of the two solves (linearity).  The predictor itself is
-     solved only to a relative residual of predictor_rtol (<= 0: 1e-3) or the
+     solved only to a relative residual of predictor_rtol (<= 0: 2e-3) or the
      usual inner tolerance, whichever is looser; its error then enters the
      predictor step lengths, mu_aff, mu~ and dx_p dz_p of the corrector's
      right-hand side, so the default iterates differ from Algorithm 6's (they

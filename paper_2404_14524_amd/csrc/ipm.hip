@@ -394,7 +394,7 @@ struct Opts {
   double* trace = nullptr;
   int trace_len = 0;
   bool separate_corrector = false;
-  double predictor_rtol = 1e-3;
+  double predictor_rtol = 2e-3;
   double inner_factor = 0.9;
 };
 

@@ -1316,10 +1316,15 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
   // ell carries a rounding error up to about ell * eps, so a smaller threshold
   // keeps rotating on noise and only stops when a sweep happens to find none
   const double tol = (double)ell * 2.220446049250313e-16;
-  // group size of the block variant: the largest of 16, 8, 6, 4, 2 whose 2*JG
-  // columns fit in the 160 KB of LDS (0: per-pair launches)
+  // Group sizes, from sweep timings on gfx950 (ell = 64 to 1600): eight
+  // waves per block beat sixteen (fewer waves per SIMD shorten each round
+  // more than the extra launches cost) and match twelve at ell = 1600.
+  // Block variant: JG = 8 (16 columns in LDS) when they fit in the 160 KB of
+  // LDS (ell <= 1280), else the largest of 6, 4, 2 that fits (0: per-pair
+  // launches).  Pairs are held in registers up to ell = 64 * CH, with CH = 4,
+  // 8, 16 or 32 by ell so that no wave rotates padding; beyond, in LDS.
   int jg = 0;
-  for (int c : {16, 8, 6, 4, 2})
+  for (int c : {8, 6, 4, 2})
     if ((size_t)2 * c * ell * sizeof(double) <= (size_t)160 * 1024) {
       jg = c;
       break;
@@ -1327,57 +1332,54 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
   const int ng = jg ? (ell + jg - 1) / jg : 0;
   const int ngp = ng + (ng & 1);
   const size_t lds = (size_t)2 * jg * ell * sizeof(double);
-  // pairs held in registers up to ell = 64 * CH (CH = 16 for the 16-wave
-  // groups, whose waves have 128 registers, else 32); beyond, rotated in LDS.
-  // The 16-wave groups (ell <= 640) take CH = 4, 8 or 16 by ell, so that no
-  // wave runs its dot products and rotations over padding.
-  const int chmax = jg == 16 ? 16 : 32;
-  const bool regs = ell <= chmax * NYS_WAVE;
-  const int ch16 = ell <= 4 * NYS_WAVE ? 4 : ell <= 8 * NYS_WAVE ? 8 : 16;
+  const bool regs = ell <= 32 * NYS_WAVE;
+  const int ch = ell <= 4 * NYS_WAVE ? 4 : ell <= 8 * NYS_WAVE ? 8 : ell <= 16 * NYS_WAVE ? 16 : 32;
   auto dispatch = [&](int round) {
-#define NYS_JAC(JGV, CHV)                                                                  \
-  case JGV:                                                                                \
-    if (regs) launch_jacobi_round<JGV, CHV>(h->stream, ngp, lds, Xc, ell, round, tol, rot); \
-    else launch_jacobi_round<JGV, 0>(h->stream, ngp, lds, Xc, ell, round, tol, rot);        \
-    break;
     switch (jg) {
-      case 16:
-        if (ch16 == 4) launch_jacobi_round<16, 4>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
-        else if (ch16 == 8) launch_jacobi_round<16, 8>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
-        else launch_jacobi_round<16, 16>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+      case 8:
+        if (ch == 4) launch_jacobi_round<8, 4>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else if (ch == 8) launch_jacobi_round<8, 8>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else if (ch == 16) launch_jacobi_round<8, 16>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else launch_jacobi_round<8, 32>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
         break;
-      NYS_JAC(8, 32)
-      NYS_JAC(6, 32)
-      NYS_JAC(4, 32)
-      default: NYS_JAC(2, 32)
+      case 6:
+        if (regs) launch_jacobi_round<6, 32>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else launch_jacobi_round<6, 0>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        break;
+      case 4:
+        if (regs) launch_jacobi_round<4, 32>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else launch_jacobi_round<4, 0>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        break;
+      default:
+        if (regs) launch_jacobi_round<2, 32>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        else launch_jacobi_round<2, 0>(h->stream, ngp, lds, Xc, ell, round, tol, rot);
+        break;
     }
-#undef NYS_JAC
   };
-  if (jg && lds > 65536) {
+  // wide variant for even 256 < ell <= 2048: groups of G = 8 columns, each
+  // wave of a block holding one in registers (C2 pairs per lane, ell <= 128
+  // C2, C2 = 4, 8, 10, 12, 14 or 16 by ell), the other group in LDS
+  const bool wide = (ell & 1) == 0 && ell > 4 * NYS_WAVE && ell <= 2048;
+  const int ngwide = wide ? (ell + 7) / 8 : 0;
+  const int ngw = ngwide + (ngwide & 1);
+  const size_t ldsw = (size_t)8 * ell * sizeof(double);
+  const int c2w = ell <= 512 ? 4 : ell <= 1024 ? 8 : ell <= 1280 ? 10 : ell <= 1536 ? 12 : ell <= 1792 ? 14 : 16;
+  if (wide) {
+    hipError_t e = c2w == 4    ? jacobi_wide_attr<4, 4>(ldsw)
+                   : c2w == 8  ? jacobi_wide_attr<4, 8>(ldsw)
+                   : c2w == 10 ? jacobi_wide_attr<4, 10>(ldsw)
+                   : c2w == 12 ? jacobi_wide_attr<4, 12>(ldsw)
+                   : c2w == 14 ? jacobi_wide_attr<4, 14>(ldsw)
+                               : jacobi_wide_attr<4, 16>(ldsw);
+    if (e != hipSuccess) return set_error(h, NYS_EHIP, "Jacobi SVD: LDS attribute: %s", hipGetErrorString(e));
+  } else if (jg && lds > 65536) {
     hipError_t e = hipSuccess;
     switch (jg) {
-      case 16: e = ch16 == 8 ? jacobi_lds_attr<16, 8>(lds) : jacobi_lds_attr<16, 16>(lds); break;
-      case 8: e = regs ? jacobi_lds_attr<8, 32>(lds) : jacobi_lds_attr<8, 0>(lds); break;
+      case 8: e = ch == 16 ? jacobi_lds_attr<8, 16>(lds) : jacobi_lds_attr<8, 32>(lds); break;
       case 6: e = regs ? jacobi_lds_attr<6, 32>(lds) : jacobi_lds_attr<6, 0>(lds); break;
       case 4: e = regs ? jacobi_lds_attr<4, 32>(lds) : jacobi_lds_attr<4, 0>(lds); break;
       default: e = regs ? jacobi_lds_attr<2, 32>(lds) : jacobi_lds_attr<2, 0>(lds); break;
     }
-    if (e != hipSuccess) return set_error(h, NYS_EHIP, "Jacobi SVD: LDS attribute: %s", hipGetErrorString(e));
-  }
-  // wide variant (groups of 2 * jg columns, one held in registers per wave)
-  // for even ell with jg in {8, 6, 4} and ell <= 2048; its register group of
-  // C2 pairs per lane covers ell up to 128 C2: C2 = 8 or 10 with jg = 8
-  // (ell <= 1024, 1280), 12 or 14 with jg = 6 (1536, 1792), 16 with jg = 4
-  const bool wide = regs && (ell & 1) == 0 && jg >= 4 && jg <= 8 && ell <= 2048;
-  const int ngwide = wide ? (ell + 2 * jg - 1) / (2 * jg) : 0;
-  const int ngw = ngwide + (ngwide & 1);
-  const int c2w = jg == 8 ? (ell <= 1024 ? 8 : 10) : jg == 6 ? (ell <= 1536 ? 12 : 14) : 16;
-  if (wide) {
-    hipError_t e = c2w == 8    ? jacobi_wide_attr<8, 8>(lds)
-                   : c2w == 10 ? jacobi_wide_attr<8, 10>(lds)
-                   : c2w == 12 ? jacobi_wide_attr<6, 12>(lds)
-                   : c2w == 14 ? jacobi_wide_attr<6, 14>(lds)
-                               : jacobi_wide_attr<4, 16>(lds);
     if (e != hipSuccess) return set_error(h, NYS_EHIP, "Jacobi SVD: LDS attribute: %s", hipGetErrorString(e));
   }
   int sweep = 0;
@@ -1386,11 +1388,12 @@ int jacobi_svd(nys_handle h, double* X, int ell, double* sig2, double* work) {
     for (; sweep < max_sweeps; ++sweep) {
       NYS_CHECK(zero_u32(h, rot, 1));
       if (wide) {
-        if (c2w == 8) launch_jacobi_wide_sweep<8, 8>(h->stream, ngw, lds, Xc, ell, tol, rot);
-        else if (c2w == 10) launch_jacobi_wide_sweep<8, 10>(h->stream, ngw, lds, Xc, ell, tol, rot);
-        else if (c2w == 12) launch_jacobi_wide_sweep<6, 12>(h->stream, ngw, lds, Xc, ell, tol, rot);
-        else if (c2w == 14) launch_jacobi_wide_sweep<6, 14>(h->stream, ngw, lds, Xc, ell, tol, rot);
-        else launch_jacobi_wide_sweep<4, 16>(h->stream, ngw, lds, Xc, ell, tol, rot);
+        if (c2w == 4) launch_jacobi_wide_sweep<4, 4>(h->stream, ngw, ldsw, Xc, ell, tol, rot);
+        else if (c2w == 8) launch_jacobi_wide_sweep<4, 8>(h->stream, ngw, ldsw, Xc, ell, tol, rot);
+        else if (c2w == 10) launch_jacobi_wide_sweep<4, 10>(h->stream, ngw, ldsw, Xc, ell, tol, rot);
+        else if (c2w == 12) launch_jacobi_wide_sweep<4, 12>(h->stream, ngw, ldsw, Xc, ell, tol, rot);
+        else if (c2w == 14) launch_jacobi_wide_sweep<4, 14>(h->stream, ngw, ldsw, Xc, ell, tol, rot);
+        else launch_jacobi_wide_sweep<4, 16>(h->stream, ngw, ldsw, Xc, ell, tol, rot);
       } else if (jg) {
         for (int round = 0; round < ngp - 1; ++round) dispatch(round);
       } else {

@@ -144,14 +144,16 @@ def _nhat(U, lam):
 @pytest.mark.parametrize("m,n,ell", [(120, 300, 10), (700, 2000, 64), (1500, 4000, 100), (1200, 3000, 300),
                                      (1300, 3000, 1100), (1800, 3600, 1600), (2000, 4000, 1800),
                                      (2200, 4400, 2100), (1100, 2500, 999), (1500, 3000, 1280),
-                                     (900, 2000, 600), (1000, 2500, 800), (1600, 3200, 1400)])
+                                     (900, 2000, 600), (1000, 2500, 800), (1600, 3200, 1400),
+                                     (700, 1500, 301), (1300, 2600, 1151)])
 def test_sketch_fp64_parity(nys, m, n, ell):
     """Algorithm 1 in FP64 against the oracle; the larger sizes take the
     multi-workgroup Cholesky (ell >= 128), the blocked triangular inverse, and
-    the Jacobi SVD's wide groups of 16, 12 and 8 columns (ell = 800 and 1100,
-    1400 and 1600, 1800: each register-group size; 1280 fills the 160 KB of
-    LDS exactly); 2100 and the odd 999 take the block variant, and 10 to 600
-    its 16-wave groups with each register-chunk size."""
+    the Jacobi SVD's wide groups of 8 columns for even 256 < ell <= 2048 with
+    each register-group size (300; 600 and 800; 1100 and 1280; 1400; 1600;
+    1800); the block variant's 8-wave groups with each register-chunk size
+    (10 to 100; the odd 301, 999 and 1151), and its smaller groups with the
+    pairs in LDS at 2100."""
     print(f"sketch {m}x{n} ell={ell}", flush=True)
     inst = make_instance("lowrank_5000x20000", seed=11, m=m, n=n, rank=max(ell // 2, 4))
     A = inst.A.double().numpy()

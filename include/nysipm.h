@@ -210,7 +210,8 @@ int nys_sketch_product(nys_handle h, const nys_matrix* A, const double* d, const
    counter); Omega is orthonormalised by a thin QR; Y = N Omega computed as
    W = d .* (A^T Omega), Y = A W, in FP64 (sketch_dtype NYS_F64, A must then be
    FP64 or FP32) or on BF16 matrix cores with FP32 accumulation (NYS_BF16;
-   A must then be BF16 storage); nu = c_nu * eps(||Y||_F) in the sketch
+   A must then be BF16 storage or carry sketch tiles of A and A^T, see
+   nys_sketch_tiles); nu = c_nu * eps(||Y||_F) in the sketch
    precision; Y_nu = Y + nu Omega; C = chol(Omega^T Y_nu) (upper, C^T C = G);
    B = Y_nu C^{-1}; thin SVD of B by Cholesky-QR and a one-sided Jacobi SVD of
    the triangular factor; U_hat = left singular vectors, Lambda_hat =
